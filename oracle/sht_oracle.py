@@ -1,0 +1,381 @@
+"""Plain FP64 CPU oracle for the spherical-harmonic transform pair on the
+Clenshaw-Curtis latitude grids (Hotta & Ujiie, "A nestable, multigrid-friendly
+grid on a sphere for global spectral models based on Clenshaw-Curtis
+quadrature").
+
+TEST INFRASTRUCTURE ONLY.  Nothing on the product path may import, call or
+execute this module: only the test-suite, the smoke check and the benchmark's
+CPU-baseline leg use it.  It shares no code with the GPU library; the two meet
+only through the seeded input generators.
+
+Everything here is written straight from the definitions, slowly and in
+float64: a DFT matrix instead of an FFT, the Legendre quadrature summed over
+all J latitudes (no equatorial folding), associated Legendre functions from the
+plain three-term recurrence.  Each function names the passage it follows.
+
+Conventions (the readings of the paper used throughout):
+  * grid kinds: "fejer2" is the paper's pole-free grid, theta_j = j*pi/(J+1),
+    j = 1..J (Sec. 3.1, eq. cc-points); "cc_poles" is the classical
+    Clenshaw-Curtis grid with the poles, theta_j = j*pi/(J-1), j = 0..J-1.
+    Row 0 is the one nearest the north pole in both cases.
+  * P~_n^m is normalised so that its square integrates to 1 over mu in
+    [-1, 1] (Sec. 2, eq. pnm-ortho), with no Condon-Shortley phase.
+  * spectra are stored for m >= 0 only, as float pairs (re, im), m-major
+    triangular: index(m, n) = m*(2N+3-m)/2 + (n-m).  Im a_n^0 is 0 on output
+    and ignored on input (real fields).
+  * the discrete zonal pair carries 1/I on the analysis side (Sec. 2, the
+    discretised zonal integral); synthesis is the Hermitian sum over m.
+"""
+
+import math
+
+import numpy as np
+
+GRID_KINDS = ("cc_poles", "fejer2")
+
+
+# --------------------------------------------------------------------------
+# indexing helpers
+# --------------------------------------------------------------------------
+
+def ncoef(N):
+    """Number of triangular coefficients with 0 <= m <= n <= N (Sec. 2)."""
+    return (N + 1) * (N + 2) // 2
+
+
+def spec_index(N, m, n):
+    """Position of (m, n) in the m-major triangular spectral array."""
+    return m * (2 * N + 3 - m) // 2 + (n - m)
+
+
+# --------------------------------------------------------------------------
+# nodes and weights
+# --------------------------------------------------------------------------
+
+def _sinpi_frac(a, b):
+    """sin(pi*a/b) after reducing a/b by their gcd, odd in a bit for bit."""
+    if a == 0:
+        return 0.0
+    g = math.gcd(abs(a), b)
+    a //= g
+    b //= g
+    s = math.sin(math.pi * abs(a) / b)
+    return s if a > 0 else -s
+
+
+def _node_fraction(J, kind, j):
+    """theta_j = pi*p/q as the integer pair (p, q)."""
+    if kind == "cc_poles":
+        if J < 2:
+            raise ValueError("cc_poles needs J >= 2")
+        return j, J - 1
+    if kind == "fejer2":
+        if J < 1:
+            raise ValueError("fejer2 needs J >= 1")
+        return j + 1, J + 1          # Sec. 3.1, eq. cc-points
+    raise ValueError("unknown grid kind %r" % (kind,))
+
+
+def nodes(J, kind):
+    """Colatitudes theta_j, mu_j = cos(theta_j) = sin(phi_j) and sin(theta_j).
+
+    Sec. 3.1 (eq. cc-points) for "fejer2"; the classical grid with the poles
+    for "cc_poles".  mu is evaluated as sin(pi*(q-2p)/(2q)) with the fraction
+    reduced by its gcd, so that the equator gets mu = 0 exactly, the mirror
+    node gets exactly -mu and nested grids share their common nodes bit for
+    bit.
+    """
+    theta = np.empty(J)
+    mu = np.empty(J)
+    sint = np.empty(J)
+    for j in range(J):
+        p, q = _node_fraction(J, kind, j)
+        theta[j] = math.pi * p / q
+        mu[j] = _sinpi_frac(q - 2 * p, 2 * q)
+        sint[j] = _sinpi_frac(min(p, q - p), q)
+    return theta, mu, sint
+
+
+def weights(J, kind):
+    """Quadrature weights w_j for integrals over mu in [-1, 1].
+
+    "fejer2": the paper's closed form, Sec. 3.1 eq. cc-wgt (derived in
+    App. A): w_j = 4 sin(theta_j)/(J+1) * sum over odd p <= J of
+    sin(p theta_j)/p.
+
+    "cc_poles": the classical Clenshaw-Curtis rule on n+1 = J points,
+    w_k = (c_k/n) [1 - sum_{l=1}^{floor(n/2)} b_l cos(2 l theta_k)/(4l^2-1)]
+    with c_0 = c_n = 1, c_k = 2 otherwise and b_l = 1 for l = n/2, 2 otherwise
+    (the rule the paper cites from Trefethen 2008 and Waldvogel 2006).
+    """
+    w = np.empty(J)
+    if kind == "fejer2":
+        for j in range(J):
+            p0, q = _node_fraction(J, kind, j)
+            s = 0.0
+            for p in range(1, J + 1, 2):
+                s += _sinpi_frac((p * p0) % (2 * q), q) / p
+            w[j] = 4.0 * _sinpi_frac(p0, q) / (J + 1) * s
+        return w
+    if kind == "cc_poles":
+        n = J - 1
+        for k in range(J):
+            c = 1.0 if (k == 0 or k == n) else 2.0
+            s = 0.0
+            for l in range(1, n // 2 + 1):
+                b = 1.0 if 2 * l == n else 2.0
+                # cos(2 l theta_k) with 2 l theta_k = 2 pi (l k mod n) / n
+                r = (l * k) % n
+                s += b * math.cos(2.0 * math.pi * r / n) / (4.0 * l * l - 1.0)
+            w[k] = c / n * (1.0 - s)
+        return w
+    raise ValueError("unknown grid kind %r" % (kind,))
+
+
+# --------------------------------------------------------------------------
+# normalised associated Legendre functions
+# --------------------------------------------------------------------------
+
+def alf_m(N, m, mu, sint):
+    """P~_n^m(mu_j) for n = m..N as an array [N-m+1, len(mu)].
+
+    The standard three-term recurrence the paper uses (Sec. 4.1, after
+    Enomoto 2015), in float64 and normalised as in eq. pnm-ortho:
+      P~_0^0 = 1/sqrt(2)
+      P~_m^m = sqrt((2m+1)/(2m)) sin(theta) P~_{m-1}^{m-1}
+      P~_{m+1}^m = sqrt(2m+3) mu P~_m^m
+      P~_n^m = a_n^m (mu P~_{n-1}^m - P~_{n-2}^m / a_{n-1}^m),
+      a_n^m = sqrt((4n^2-1)/(n^2-m^2)).
+    """
+    mu = np.asarray(mu, dtype=np.float64)
+    sint = np.asarray(sint, dtype=np.float64)
+    out = np.zeros((N - m + 1, mu.size))
+    pmm = np.full(mu.size, 1.0 / math.sqrt(2.0))
+    for k in range(1, m + 1):
+        pmm = math.sqrt((2.0 * k + 1.0) / (2.0 * k)) * sint * pmm
+    out[0] = pmm
+    if N == m:
+        return out
+    out[1] = math.sqrt(2.0 * m + 3.0) * mu * pmm
+
+    def a(n):
+        return math.sqrt((4.0 * n * n - 1.0) / (n * n - m * m))
+
+    for n in range(m + 2, N + 1):
+        out[n - m] = a(n) * (mu * out[n - m - 1] - out[n - m - 2] / a(n - 1))
+    return out
+
+
+# --------------------------------------------------------------------------
+# zonal (longitude) step
+# --------------------------------------------------------------------------
+
+def _phase(N, I):
+    """alpha[m, i] = 2 pi ((m i) mod I) / I, for m = 0..N, i = 0..I-1."""
+    m = np.arange(N + 1)[:, None]
+    i = np.arange(I)[None, :]
+    return 2.0 * np.pi * ((m * i) % I) / I
+
+
+def zonal_analysis(x, N):
+    """X^m(phi_j) = (1/I) sum_i x(lambda_i, phi_j) exp(-i m lambda_i), m <= N.
+
+    Sec. 2, the discretised zonal integral, evaluated with an explicit DFT
+    matrix.  x: [..., J, I] real -> [..., J, N+1] complex.
+    """
+    I = x.shape[-1]
+    al = _phase(N, I)
+    e = np.cos(al) - 1j * np.sin(al)
+    return (x @ e.T) / I
+
+
+def zonal_synthesis(X, I):
+    """x(lambda_i) = Re X^0 + 2 sum_{m>=1} Re(X^m exp(i m lambda_i)).
+
+    Sec. 2: the inverse DFT over m = -N..N with X^{-m} = conj(X^m) for a real
+    field; Im X^0 is dropped.  X: [..., J, N+1] complex -> [..., J, I].
+    """
+    N = X.shape[-1] - 1
+    al = _phase(N, I)
+    c = np.cos(al)
+    s = np.sin(al)
+    c[1:] *= 2.0
+    s[1:] *= 2.0
+    return X.real @ c - X.imag @ s
+
+
+# --------------------------------------------------------------------------
+# the transform pair
+# --------------------------------------------------------------------------
+
+def _check_grid(grid):
+    grid = np.asarray(grid, dtype=np.float64)
+    if grid.ndim == 2:
+        grid = grid[None]
+    return grid
+
+
+def _check_spec(spec, N):
+    spec = np.asarray(spec, dtype=np.float64)
+    if spec.ndim == 2:
+        spec = spec[None]
+    if spec.shape[-2:] != (ncoef(N), 2):
+        raise ValueError("spec must be [F, ncoef, 2]")
+    return spec
+
+
+def forward(grid, N, kind):
+    """Analysis (direct SHT), Sec. 2 eq. dSHT/dLT with the Clenshaw-Curtis
+    quadrature of Sec. 3.1 eq. cc-quad:
+
+        a_n^m = sum_{j=0}^{J-1} w_j P~_n^m(mu_j) X^m(phi_j).
+
+    grid [F, J, I] -> spec [F, ncoef, 2]; Im a_n^0 set to 0.
+    """
+    grid = _check_grid(grid)
+    F, J, I = grid.shape
+    _, mu, sint = nodes(J, kind)
+    w = weights(J, kind)
+    X = zonal_analysis(grid, N)                  # [F, J, N+1]
+    spec = np.zeros((F, ncoef(N), 2))
+    for m in range(N + 1):
+        P = alf_m(N, m, mu, sint)                # [n_m, J]
+        a = (X[:, :, m] * w[None, :]) @ P.T      # [F, n_m]
+        k0 = spec_index(N, m, m)
+        spec[:, k0:k0 + N - m + 1, 0] = a.real
+        spec[:, k0:k0 + N - m + 1, 1] = a.imag if m > 0 else 0.0
+    return spec
+
+
+def inverse(spec, N, J, I, kind):
+    """Synthesis (inverse SHT), Sec. 2 eq. iSHT in its two steps: the
+    Legendre sum eq. iLT, X^m(phi_j) = sum_n a_n^m P~_n^m(mu_j), then the
+    zonal synthesis.  spec [F, ncoef, 2] -> grid [F, J, I].
+    """
+    spec = _check_spec(spec, N)
+    F = spec.shape[0]
+    _, mu, sint = nodes(J, kind)
+    X = np.zeros((F, J, N + 1), dtype=np.complex128)
+    for m in range(N + 1):
+        P = alf_m(N, m, mu, sint)
+        k0 = spec_index(N, m, m)
+        a = spec[:, k0:k0 + N - m + 1, 0] + 1j * spec[:, k0:k0 + N - m + 1, 1]
+        if m == 0:
+            a = a.real + 0j
+        X[:, :, m] = a @ P
+    return zonal_synthesis(X, I)
+
+
+def forward_adjoint(spec_bar, N, J, I, kind):
+    """Transpose of `forward` under the Euclidean inner product of the stored
+    real arrays (not a formula of the paper; needed for reverse-mode
+    differentiation).  Written out from the definition of `forward`:
+
+        d a_re(n,m) / d x_ji =  (w_j/I) P~_n^m(mu_j) cos(m lambda_i)
+        d a_im(n,m) / d x_ji = -(w_j/I) P~_n^m(mu_j) sin(m lambda_i)  (m > 0)
+
+    so x_bar_ji = (w_j/I) sum_m sum_n P~_n^m(mu_j)
+                  (abar_re cos(m lambda_i) - abar_im sin(m lambda_i)),
+    with the m = 0 imaginary part contributing nothing.
+    """
+    spec_bar = _check_spec(spec_bar, N)
+    F = spec_bar.shape[0]
+    _, mu, sint = nodes(J, kind)
+    w = weights(J, kind)
+    al = _phase(N, I)
+    out = np.zeros((F, J, I))
+    for m in range(N + 1):
+        P = alf_m(N, m, mu, sint)
+        k0 = spec_index(N, m, m)
+        br = spec_bar[:, k0:k0 + N - m + 1, 0] @ P          # [F, J]
+        bi = spec_bar[:, k0:k0 + N - m + 1, 1] @ P
+        if m == 0:
+            bi = np.zeros_like(bi)
+        out += br[:, :, None] * np.cos(al[m])[None, None, :]
+        out -= bi[:, :, None] * np.sin(al[m])[None, None, :]
+    return out * (w / I)[None, :, None]
+
+
+def inverse_adjoint(grid_bar, N, kind):
+    """Transpose of `inverse` under the Euclidean inner product of the stored
+    real arrays.  From x_ji = sum_n a_re(n,0) P~_n^0
+    + 2 sum_{m>=1} sum_n P~_n^m (a_re cos - a_im sin):
+
+        abar_re(n,m) =  c_m sum_j P~_n^m(mu_j) sum_i gbar_ji cos(m lambda_i)
+        abar_im(n,m) = -c_m sum_j P~_n^m(mu_j) sum_i gbar_ji sin(m lambda_i)
+
+    with c_0 = 1, c_m = 2 for m > 0, and abar_im(n, 0) = 0.
+    """
+    grid_bar = _check_grid(grid_bar)
+    F, J, I = grid_bar.shape
+    _, mu, sint = nodes(J, kind)
+    al = _phase(N, I)
+    cs = grid_bar @ np.cos(al).T                 # [F, J, N+1]
+    sn = grid_bar @ np.sin(al).T
+    out = np.zeros((F, ncoef(N), 2))
+    for m in range(N + 1):
+        P = alf_m(N, m, mu, sint)
+        c = 1.0 if m == 0 else 2.0
+        k0 = spec_index(N, m, m)
+        out[:, k0:k0 + N - m + 1, 0] = c * (cs[:, :, m] @ P.T)
+        if m > 0:
+            out[:, k0:k0 + N - m + 1, 1] = -c * (sn[:, :, m] @ P.T)
+    return out
+
+
+# --------------------------------------------------------------------------
+# pointwise evaluation for sampled checks at large sizes
+# --------------------------------------------------------------------------
+
+def forward_sample(grid_field, N, kind, m, n_list):
+    """a_n^m of one field for one m and a few n, straight from the definition
+    (same formula as `forward`, restricted).  grid_field [J, I] -> [len, 2]."""
+    x = np.asarray(grid_field, dtype=np.float64)
+    J, I = x.shape
+    _, mu, sint = nodes(J, kind)
+    w = weights(J, kind)
+    al = 2.0 * np.pi * ((m * np.arange(I)) % I) / I
+    Xm = (x @ np.cos(al) - 1j * (x @ np.sin(al))) / I       # [J]
+    P = alf_m(N, m, mu, sint)
+    out = np.zeros((len(n_list), 2))
+    for k, n in enumerate(n_list):
+        v = np.sum(w * P[n - m] * Xm)
+        out[k] = (v.real, v.imag if m > 0 else 0.0)
+    return out
+
+
+def inverse_sample_row(spec_field, N, J, I, kind, j):
+    """Row j of the synthesis of one field (same formula as `inverse`,
+    restricted to one latitude).  spec_field [ncoef, 2] -> [I]."""
+    spec = np.asarray(spec_field, dtype=np.float64)
+    _, mu, sint = nodes(J, kind)
+    X = np.zeros(N + 1, dtype=np.complex128)
+    for m in range(N + 1):
+        P = alf_m(N, m, mu[j:j + 1], sint[j:j + 1])[:, 0]
+        k0 = spec_index(N, m, m)
+        a = spec[k0:k0 + N - m + 1, 0] + 1j * spec[k0:k0 + N - m + 1, 1]
+        if m == 0:
+            a = a.real + 0j
+        X[m] = a @ P
+    return zonal_synthesis(X[None, :], I)[0]
+
+
+# --------------------------------------------------------------------------
+# numerical orthonormality (Sec. 4.1, eq. norm-err and eq. orth-err)
+# --------------------------------------------------------------------------
+
+def orthonormality_errors(N, J, kind):
+    """Normality error |sum_j P~_n^m(mu_j)^2 w_j - 1| and orthogonality error
+    max_{n' != n} |sum_j P~_n^m P~_n'^m w_j|, as arrays [N+1 (m), N+1 (n)]
+    with NaN where n < m (Sec. 4.1, eq. norm-err, eq. orth-err)."""
+    _, mu, sint = nodes(J, kind)
+    w = weights(J, kind)
+    en = np.full((N + 1, N + 1), np.nan)
+    eo = np.full((N + 1, N + 1), np.nan)
+    for m in range(N + 1):
+        P = alf_m(N, m, mu, sint)
+        G = (P * w[None, :]) @ P.T
+        en[m, m:] = np.abs(np.diag(G) - 1.0)
+        off = np.abs(G - np.diag(np.diag(G)))
+        eo[m, m:] = off.max(axis=1) if G.shape[0] > 1 else 0.0
+    return en, eo
