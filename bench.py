@@ -1,0 +1,179 @@
+"""Throughput of the Clenshaw-Curtis spherical-harmonic transform pair on one
+MI355X.
+
+One step = one analysis (grid -> spec) plus one synthesis (spec -> grid) of
+the whole batch: N=959 (T959), J=1919 CC latitudes with the poles, I=2880
+longitudes, 64 fields, FP32 data with FP32-MFMA Legendre contraction.  The
+FP64 form of the same batch is timed alongside for the speedup, the per
+kernel times come from HIP events on the stream the kernels run on, and the
+FP64 oracle is timed on a one-field sample on the host.
+
+Prints one JSON line.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--N", type=int, default=959)
+    ap.add_argument("--J", type=int, default=1919)
+    ap.add_argument("--I", type=int, default=2880)
+    ap.add_argument("--F", type=int, default=64)
+    ap.add_argument("--grid", default="cc_poles")
+    ap.add_argument("--form", default="fp32")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-form comparison")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    return ap.parse_args()
+
+
+def time_pairs(plan, g, steps, warmup, torch):
+    s = plan.forward(g)
+    g2 = plan.inverse(s)
+    for _ in range(warmup):
+        plan.forward(g, out=s)
+        plan.inverse(s, out=g2)
+    torch.cuda.synchronize()
+    plan.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.forward(g, out=s)
+        plan.inverse(s, out=g2)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stages = plan.profile_read()
+    plan.profile(False)
+    return (t1 - t0), stages, s, g2
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the transform batch is sharded over fields with no "
+              "exchange, so more GPUs run independent copies; run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_1711_11296_amd import Plan, inputs
+
+    torch.cuda.set_device(0)
+    N, J, I, F = args.N, args.J, args.I, args.F
+    dt = torch.float64 if args.form == "fp64" else torch.float32
+
+    # ---- workload: grids synthesised from k^-3 band-limited spectra ----
+    spec0 = inputs.random_spectra(N, F, seed=0, profile="k3")
+    plan = Plan(N, J, I, F, grid=args.grid, form=args.form)
+    a = torch.from_numpy(spec0).to("cuda:0", dt)
+    g = plan.inverse(a)
+    torch.cuda.synchronize()
+
+    secs, stages, s_out, g_out = time_pairs(plan, g, args.steps, args.warmup, torch)
+    value = F * args.steps / secs
+    ms_step = secs / args.steps * 1e3
+    flops_dir = plan.legendre_flops
+
+    # dominant kernel: the slower Legendre direction
+    la_ms, la_n = stages["legendre_analysis"]
+    ls_ms, ls_n = stages["legendre_synthesis"]
+    la_avg, ls_avg = la_ms / max(la_n, 1), ls_ms / max(ls_n, 1)
+    dom = "legendre_analysis" if la_avg >= ls_avg else "legendre_synthesis"
+    dom_ms = max(la_avg, ls_avg)
+    achieved = flops_dir / (dom_ms * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[args.form]
+    leg_tflops = 2 * flops_dir / ((la_avg + ls_avg) * 1e-3) / 1e12
+    stage_avg = {k: (v[0] / max(v[1], 1)) for k, v in stages.items()}
+
+    # ---- accuracy of this run against the oracle on field 0 ----
+    import oracle as O
+    cpu = None
+    err = {}
+    if not args.no_cpu:
+        g0 = g[0].double().cpu().numpy()
+        a0 = a[0:1].double().cpu().numpy()
+        nthreads = None
+        try:
+            from threadpoolctl import threadpool_info
+            nthreads = sum(int(i.get("num_threads", 0)) for i in threadpool_info())
+        except Exception:
+            pass
+        t0 = time.perf_counter()
+        s_ref = O.forward(g0[None], N, args.grid)
+        g_ref = O.inverse(a0, N, J, I, args.grid)
+        t_cpu = time.perf_counter() - t0
+        s_gpu = s_out[0].double().cpu().numpy()
+        g_in = plan.inverse(a)        # synthesis of the input spectra
+        torch.cuda.synchronize()
+        g_gpu = g_in[0].double().cpu().numpy()
+        err["forward_rel_l2"] = float(np.linalg.norm(s_gpu - s_ref[0]) / np.linalg.norm(s_ref[0]))
+        err["inverse_rel_l2"] = float(np.linalg.norm(g_gpu - g_ref[0]) / np.linalg.norm(g_ref[0]))
+        cpu = {"value": 1.0 / t_cpu, "unit": "fields*SHT-pairs/s", "cores": int(nthreads or os.cpu_count()),
+               "kind": "oracle",
+               "sample": "1 of %d fields (field 0), one analysis + one synthesis at N=%d J=%d I=%d, FP64 "
+                         "numpy oracle (DFT matrix, unfolded Legendre sums), %.1f s" % (F, N, J, I, t_cpu)}
+
+    # ---- FP64 form on the same batch (speedup of the chosen form) ----
+    fp64 = None
+    if not args.no_fp64 and args.form != "fp64":
+        del s_out, g_out
+        p64 = Plan(N, J, I, F, grid=args.grid, form="fp64")
+        g64 = g.double()
+        st = max(2, args.steps // 4)
+        secs64, stages64, _, _ = time_pairs(p64, g64, st, 1, torch)
+        v64 = F * st / secs64
+        la64 = stages64["legendre_analysis"][0] / max(stages64["legendre_analysis"][1], 1)
+        ls64 = stages64["legendre_synthesis"][0] / max(stages64["legendre_synthesis"][1], 1)
+        fp64 = {"value": v64, "ms_per_step": secs64 / st * 1e3,
+                "legendre_tflops": 2 * flops_dir / ((la64 + ls64) * 1e-3) / 1e12,
+                "legendre_mfma_frac": 2 * flops_dir / ((la64 + ls64) * 1e-3) / 1e12 / PEAK_TFLOPS["fp64"],
+                "speedup_of_%s" % args.form: value / v64}
+        p64.close()
+
+    out = {
+        "metric": "fields*SHT-pairs/s",
+        "value": value,
+        "unit": "fields*SHT-pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.form == "fp32" else ("f64" if args.form == "fp64" else "bf16x6/f32"),
+        "data": "synthetic: grids synthesised from k^-3 random spectra (seed 0)",
+        "config": {"workload": "T959 batch: N=%d J=%d I=%d, %d fields, %s grid, %s form, forward+inverse"
+                               % (N, J, I, F, args.grid, args.form),
+                   "N": N, "J": J, "I": I, "fields": F, "grid": args.grid, "form": args.form},
+        "legendre_tflops": leg_tflops,
+        "legendre_mfma_frac": leg_tflops / peak,
+        "end_to_end_mfma_frac": 2 * flops_dir / (ms_step * 1e-3) / 1e12 / peak,
+        "stage_ms": stage_avg,
+        "rel_err_vs_oracle_field0": err,
+        "fp64_form": fp64,
+        "roofline": {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "algorithmic_flops_per_launch": flops_dir},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    plan.close()
+
+
+if __name__ == "__main__":
+    main()

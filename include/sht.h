@@ -1,0 +1,203 @@
+/*
+ * sht.h - C ABI of the Clenshaw-Curtis spherical-harmonic transform library
+ * for AMD Instinct MI355X (gfx950).
+ *
+ * The transform pair is the one of Hotta & Ujiie, "A nestable,
+ * multigrid-friendly grid on a sphere for global spectral models based on
+ * Clenshaw-Curtis quadrature":
+ *   synthesis (Sec. 2, eq. iSHT / eq. iLT): a Legendre sum per zonal
+ *     wavenumber m, X^m(phi_j) = sum_n a_n^m P~_n^m(sin phi_j), followed by the
+ *     zonal inverse DFT  x(lambda_i, phi_j) = sum_{m=-N..N} X^m e^{i m lambda_i};
+ *   analysis (Sec. 2, eq. dSHT / eq. dLT / eq. dFT, discretised with the
+ *     Clenshaw-Curtis rule of Sec. 3.1, eq. cc-quad / eq. cc-wgt): the zonal
+ *     DFT X^m(phi_j) = (1/I) sum_i x e^{-i m lambda_i}, then the quadrature
+ *     a_n^m = sum_j w_j P~_n^m(sin phi_j) X^m(phi_j), exact when J >= 2N+1
+ *     (eq. cc-condition) and I > 2N (eq. fourier-condition).
+ * The Legendre sums use the equatorial parity fold of App. B (eqs. B3, B4).
+ *
+ * Conventions
+ *   Grids (sht_grid_t): SHT_GRID_FEJER2 is the paper's pole-free grid,
+ *   theta_j = j*pi/(J+1), j = 1..J (Sec. 3.1, eq. cc-points);
+ *   SHT_GRID_CC_POLES is the classical Clenshaw-Curtis grid with the poles,
+ *   theta_j = j*pi/(J-1), j = 0..J-1.  Row 0 is nearest the north pole.
+ *   lambda_i = 2*pi*i/I.  P~_n^m has unit L2 norm over mu in [-1, 1]
+ *   (eq. pnm-ortho) and no Condon-Shortley phase.
+ *
+ * Memory layout (all buffers are device memory, contiguous, row-major):
+ *   grid: [nfields][J][I] real;
+ *   spec: [nfields][ncoef][2] (re, im), ncoef = (N+1)(N+2)/2, m-major:
+ *         index(m, n) = m*(2N+3-m)/2 + (n-m), 0 <= m <= n <= N.
+ *         Im of m = 0 is written as 0 and ignored on input.
+ *   Element type: double for SHT_FORM_FP64, float for SHT_FORM_FP32 and
+ *   SHT_FORM_BF16X6 (that form splits operands into bfloat16 pieces inside
+ *   the Legendre kernels; its inputs and outputs are float).
+ *   Multi-level plans: the buffers of the levels are concatenated in level
+ *   order (use SHT_Q_GRID_OFFSET / SHT_Q_SPEC_OFFSET to find a level).
+ *
+ * Ownership and concurrency
+ *   The caller owns every grid and spec buffer.  The plan owns its tables,
+ *   twiddles and workspace.  sht_forward / sht_inverse / the adjoints
+ *   allocate nothing, do not synchronise with the host and only enqueue work
+ *   on `stream` (a hipStream_t; NULL is the default stream).  A plan holds
+ *   one workspace, so two calls on the same plan must not overlap in time
+ *   (use one stream per plan, or one plan per stream).  Inputs and outputs
+ *   must not alias.  Input buffers are not modified.
+ *
+ * Errors
+ *   Every entry point returns SHT_OK (0) or a negative code; the message of
+ *   the last failure on the calling thread is available from
+ *   sht_last_error().  Arguments are validated before any work is enqueued.
+ *   No C++ exception crosses this interface.
+ */
+#ifndef SHT_H_
+#define SHT_H_
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sht_plan_s* sht_plan_t;
+
+typedef enum {
+  SHT_GRID_CC_POLES = 0,
+  SHT_GRID_FEJER2 = 1
+} sht_grid_t;
+
+typedef enum {
+  SHT_FORM_FP64 = 0,   /* FP64 data, FP64 MFMA (v_mfma_f64_16x16x4) */
+  SHT_FORM_FP32 = 1,   /* FP32 data, FP32 MFMA (v_mfma_f32_16x16x4) */
+  SHT_FORM_BF16X6 = 2  /* FP32 data; Legendre operands split into three
+                          bfloat16 pieces, six piece products per term,
+                          FP32 accumulation */
+} sht_form_t;
+
+typedef struct {
+  int grid;       /* sht_grid_t */
+  int form;       /* sht_form_t */
+  int autotune;   /* nonzero: time candidate tile shapes at plan time */
+  int use_graph;  /* nonzero: replay each transform from a captured hipGraph */
+} sht_options;
+
+enum {
+  SHT_OK = 0,
+  SHT_EINVAL = -1,   /* bad argument */
+  SHT_ENOMEM = -2,   /* device or host allocation failed */
+  SHT_EHIP = -3,     /* a HIP runtime call failed */
+  SHT_ESTATE = -4    /* destroyed or corrupt plan handle */
+};
+
+/* Query keys for sht_plan_query. */
+enum {
+  SHT_Q_NLEVELS = 0,        /* int */
+  SHT_Q_NCOEF = 1,          /* int, level 0 */
+  SHT_Q_EXACT = 2,          /* int: 1 if J >= 2N+1 on every level */
+  SHT_Q_WORKSPACE_BYTES = 3,/* size_t */
+  SHT_Q_TABLE_BYTES = 4,    /* size_t */
+  SHT_Q_GRID_ELEMS = 5,     /* size_t: elements of the (concatenated) grid */
+  SHT_Q_SPEC_ELEMS = 6,     /* size_t: elements of the (concatenated) spec */
+  SHT_Q_FORM = 7,           /* int */
+  SHT_Q_GRID_KIND = 8,      /* int */
+  SHT_Q_LEGENDRE_FLOPS = 9, /* double: parity-folded Legendre flops of one
+                               direction, 2*ceil(J/2)*(N+1)(N+2)*F summed
+                               over levels */
+  SHT_Q_GRID_OFFSET = 100,  /* size_t: element offset of level (key-100) */
+  SHT_Q_SPEC_OFFSET = 200   /* size_t: element offset of level (key-200) */
+};
+
+/*
+ * sht_plan: plan for one level with the defaults (SHT_GRID_CC_POLES,
+ * SHT_FORM_FP64) on the current HIP device.  Returns NULL on failure.
+ *   N >= 0 truncation wavenumber; J latitudes (>= 2 on CC_POLES, >= 1 on
+ *   FEJER2); I >= 2N+1 longitudes (radix 2, 3, 5 only, I <= 4096);
+ *   nfields >= 1 independent fields.  J < 2N+1 is accepted (the quadrature
+ *   then aliases, Sec. 3.1; SHT_Q_EXACT reports 0).
+ * Plan time builds the nodes and weights (Sec. 3.1, eq. cc-points,
+ * eq. cc-wgt; App. A), the table of P~_n^m (three-term recurrence of
+ * Sec. 4.1, evaluated with a separately carried binary exponent so that no
+ * value underflows) and uploads them; it synchronises the device.
+ */
+sht_plan_t sht_plan(int N, int J, int I, int nfields);
+
+/* As sht_plan with options (NULL = defaults); the plan goes to *out. */
+int sht_plan_ex(int N, int J, int I, int nfields, const sht_options* opts,
+                sht_plan_t* out);
+
+/*
+ * A hierarchy of nlevels (1..8) independent transforms executed together:
+ * one launch per stage covers all levels (e.g. the nested truncations of
+ * Sec. 3.2).  Arrays have nlevels entries; buffers are concatenated.
+ */
+int sht_plan_multi(int nlevels, const int* N, const int* J, const int* I,
+                   const int* nfields, const sht_options* opts,
+                   sht_plan_t* out);
+
+/* Analysis, grid -> spec (Sec. 2 eq. dSHT; Sec. 3.1 eq. cc-quad). */
+int sht_forward(sht_plan_t plan, const void* grid, void* spec, void* stream);
+
+/* Synthesis, spec -> grid (Sec. 2 eq. iSHT, eq. iLT). */
+int sht_inverse(sht_plan_t plan, const void* spec, void* grid, void* stream);
+
+/*
+ * Transpose of sht_forward under the Euclidean inner product of the stored
+ * real arrays: grid_bar = forward^T spec_bar.  Equals (w_j / I) times a
+ * synthesis of spec_bar with every m > 0 coefficient halved and Im of m = 0
+ * dropped.  (Not a formula of the paper; it is what reverse-mode
+ * differentiation of the analysis needs.)
+ */
+int sht_forward_adjoint(sht_plan_t plan, const void* spec_bar, void* grid_bar,
+                        void* stream);
+
+/*
+ * Transpose of sht_inverse: spec_bar = inverse^T grid_bar, i.e. c_m * I times
+ * an analysis without the weights w_j, c_0 = 1, c_m = 2 (m > 0), and Im of
+ * m = 0 set to 0.
+ */
+int sht_inverse_adjoint(sht_plan_t plan, const void* grid_bar, void* spec_bar,
+                        void* stream);
+
+/* Read a plan property (see SHT_Q_*); `out` points to the documented type. */
+int sht_plan_query(sht_plan_t plan, int key, void* out);
+
+/*
+ * Copy plan tables of level 0 to host memory (any pointer may be NULL):
+ * mu[J] = sin(latitude) of each row, w[J] quadrature weights, and
+ * alf[(N+1)(N+2)/2 * ceil(J/2)] = P~_n^m(mu_j) for the northern rows
+ * j < ceil(J/2), in spec order (m-major), each entry a row of ceil(J/2)
+ * values, as built in FP64 before any conversion to the form's precision.
+ */
+int sht_plan_tables(sht_plan_t plan, double* mu, double* w, double* alf);
+
+/*
+ * Per-stage timing for measurement.  While enabled, every transform call
+ * brackets each of its kernel launches with hipEvents recorded on the
+ * caller's stream (stages: 0 zonal analysis, 1 Legendre analysis,
+ * 2 Legendre synthesis, 3 zonal synthesis).  sht_plan_profile_read waits for
+ * the last recorded event, returns the summed milliseconds ms[4] and launch
+ * counts counts[4] since the last read (or enable), and starts over.
+ * Profiling creates events on first use, so keep it off under graph capture.
+ */
+int sht_plan_profile(sht_plan_t plan, int enable);
+int sht_plan_profile_read(sht_plan_t plan, double* ms, int* counts);
+
+/* Release every resource of the plan (after the device has finished with
+ * any work that uses it).  A destroyed handle is rejected with SHT_ESTATE. */
+int sht_plan_destroy(sht_plan_t plan);
+
+/* Message for the last failure on the calling thread ("" if none). */
+const char* sht_last_error(void);
+
+/*
+ * Host-only planning (no GPU needed): nodes and weights of a grid, and the
+ * FP64 table of P~_n^m for the northern rows, as sht_plan_tables.  Returns
+ * SHT_EINVAL on bad arguments.
+ */
+int sht_host_tables(int N, int J, int grid, double* mu, double* w,
+                    double* alf);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SHT_H_ */

@@ -1,0 +1,8 @@
+"""Clenshaw-Curtis spherical-harmonic transforms on AMD Instinct MI355X.
+
+The transform pair (analysis, synthesis) and both adjoints run in the HIP
+library libsht.so; see include/sht.h for the C ABI.
+"""
+
+from .plan import Plan, host_tables  # noqa: F401
+from ._lib import SHTError  # noqa: F401

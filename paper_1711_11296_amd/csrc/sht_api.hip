@@ -1,0 +1,628 @@
+// C ABI of the transform library: plan construction (tables, twiddles,
+// workspace, tile schedules) and the four transform entry points.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <set>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "sht_internal.h"
+
+using namespace sht;
+
+namespace {
+
+constexpr uint32_t kMagic = 0x53485443u;  // "SHTC"
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  if (std::getenv("SHT_LOG")) std::fprintf(stderr, "[sht] %s\n", msg.c_str());
+  return code;
+}
+
+std::mutex g_live_mu;
+std::set<const void*> g_live;
+
+bool is_live(const void* p) {
+  std::lock_guard<std::mutex> lk(g_live_mu);
+  return g_live.count(p) != 0;
+}
+
+long long roundup(long long a, long long b) { return (a + b - 1) / b * b; }
+
+}  // namespace
+
+struct sht_plan_s {
+  uint32_t magic = 0;
+  int form = SHT_FORM_FP64;
+  int grid = SHT_GRID_CC_POLES;
+  int autotune = 0;
+  int use_graph = 0;
+  int device = 0;
+  int nlev = 0;
+  int ncb = 1;
+  int maxN = 0;
+  int nitems = 0;
+  int ntiles_fwd = 0, ntiles_inv = 0;
+  LevelDesc lev[SHT_MAX_LEVELS];
+  size_t elem = 8;             // bytes per grid/spec scalar
+  size_t grid_elems = 0, spec_elems = 0;
+  size_t ws_elems = 0, table_elems = 0, table_bytes = 0, ws_bytes = 0;
+  double flops = 0.0;
+  bool exact = true;
+  void* d_table = nullptr;
+  void* d_ws = nullptr;
+  void* d_tw = nullptr;
+  double* d_w = nullptr;
+  long long* d_taboff = nullptr;
+  Tile* d_tiles_fwd = nullptr;
+  Tile* d_tiles_inv = nullptr;
+  std::vector<void*> allocs;
+  size_t alloc_bytes = 0;
+  // optional per-stage timing with events on the caller's stream
+  int profile = 0;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<int> ev_stage;  // stage of each recorded (start, stop) pair
+};
+
+namespace {
+
+size_t g_alloc_total = 0;
+
+// Device allocation with an optional test limit (SHT_TEST_MAX_BYTES).
+int dev_alloc(sht_plan_s* P, void** out, size_t bytes) {
+  static const char* lim_s = std::getenv("SHT_TEST_MAX_BYTES");
+  size_t lim = lim_s ? (size_t)std::strtoull(lim_s, nullptr, 10) : 0;
+  if (lim && g_alloc_total + bytes > lim)
+    return fail(SHT_ENOMEM, "device allocation of " + std::to_string(bytes) +
+                                " bytes exceeds SHT_TEST_MAX_BYTES");
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes ? bytes : 16);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(SHT_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+  }
+  g_alloc_total += bytes;
+  P->alloc_bytes += bytes;
+  P->allocs.push_back(p);
+  *out = p;
+  return SHT_OK;
+}
+
+void free_plan(sht_plan_s* P) {
+  for (hipEvent_t e : P->ev_pool) (void)hipEventDestroy(e);
+  P->ev_pool.clear();
+  for (void* p : P->allocs) (void)hipFree(p);
+  P->allocs.clear();
+  g_alloc_total -= P->alloc_bytes;
+  P->alloc_bytes = 0;
+}
+
+int hip_check(hipError_t e, const char* what) {
+  if (e == hipSuccess) return SHT_OK;
+  (void)hipGetLastError();
+  return fail(SHT_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int check_level_args(int N, int J, int I, int F, int grid) {
+  if (N < 0) return fail(SHT_EINVAL, "N must be >= 0");
+  if (F < 1) return fail(SHT_EINVAL, "nfields must be >= 1");
+  if (!grid_args_ok(J, grid))
+    return fail(SHT_EINVAL, grid == SHT_GRID_CC_POLES ? "J must be >= 2 on the CC grid with poles"
+                                                     : (grid == SHT_GRID_FEJER2 ? "J must be >= 1"
+                                                                                : "unknown grid kind"));
+  if (I < 2 * N + 1) return fail(SHT_EINVAL, "I must be >= 2N+1 (no retained wavenumber may alias)");
+  if (I > SHT_MAX_I) return fail(SHT_EINVAL, "I exceeds the supported maximum 4096");
+  int rad[SHT_MAX_RADICES], nrad;
+  if (!factor_radices(I, rad, &nrad)) return fail(SHT_EINVAL, "I must factor into 2, 3 and 5");
+  return SHT_OK;
+}
+
+// Column blocking shared by all levels: the one that pads the least
+// (weighted by the Legendre work), preferring wider tiles on ties.
+int choose_ncb(int form, int nlev, const int* N, const int* J, const int* F) {
+  const int cand64[] = {8, 4, 2, 1};
+  const int cand32[] = {10, 8, 4, 2, 1};
+  const int* cand = form == SHT_FORM_FP64 ? cand64 : cand32;
+  const int nc = form == SHT_FORM_FP64 ? 4 : 5;
+  int best = 1;
+  double bestc = 1e300;
+  for (int k = 0; k < nc; ++k) {
+    double c = 0;
+    for (int l = 0; l < nlev; ++l) {
+      double work = (double)(N[l] + 1) * (N[l] + 2) * ((J[l] + 1) / 2);
+      c += work * (double)roundup(2LL * F[l], 16LL * cand[k]);
+    }
+    if (c < bestc * (1 - 1e-12)) {
+      bestc = c;
+      best = cand[k];
+    }
+  }
+  return best;
+}
+
+// Split a tile list (in locality order) into 8 contiguous chunks of equal
+// cost and deal them so that chunk x runs on XCD x (block id % 8 == x).
+std::vector<Tile> xcd_schedule(const std::vector<Tile>& tiles, const std::vector<double>& cost) {
+  const int X = 8;
+  double total = 0;
+  for (double c : cost) total += c;
+  std::vector<std::vector<Tile>> chunk(X);
+  double acc = 0;
+  int x = 0;
+  for (size_t i = 0; i < tiles.size(); ++i) {
+    chunk[x].push_back(tiles[i]);
+    acc += cost[i];
+    while (x < X - 1 && acc >= total * (x + 1) / X) ++x;
+  }
+  size_t len = 0;
+  for (auto& c : chunk) len = std::max(len, c.size());
+  std::vector<Tile> out(len * X, Tile{-1, 0, 0, 0});
+  for (int xx = 0; xx < X; ++xx)
+    for (size_t i = 0; i < chunk[xx].size(); ++i) out[i * X + xx] = chunk[xx][i];
+  return out;
+}
+
+template <typename T>
+void fill_table_level(const LevelDesc& L, const double* mu, const double* sint,
+                      T* dst, const long long* taboff_level) {
+  // dst is the whole table; rows of each m go to taboff_level[m]
+  const int N = L.N, Jh = L.Jh, Kp = L.Kp;
+  int nth = (int)std::thread::hardware_concurrency();
+  nth = std::max(1, std::min(nth, 64));
+  std::vector<std::thread> pool;
+  for (int t = 0; t < nth; ++t) {
+    pool.emplace_back([=]() {
+      std::vector<double> col;
+      for (int k = t; k <= N; k += nth) {
+        const int m = (k % 2 == 0) ? k / 2 : N - k / 2;
+        const int nm = N - m + 1;
+        col.assign((size_t)nm * Jh, 0.0);
+        alf_column(N, m, Jh, mu, sint, col.data(), Jh);
+        T* blk = dst + taboff_level[m];
+        const int R = (int)roundup(nm, SHT_ROWS_PAD);
+        for (int r = 0; r < R; ++r)
+          for (int j = 0; j < Kp; ++j)
+            blk[(size_t)r * Kp + j] = (r < nm && j < Jh) ? (T)col[(size_t)r * Jh + j] : (T)0;
+      }
+    });
+  }
+  for (auto& th : pool) th.join();
+}
+
+int build_plan(int nlev, const int* Nv, const int* Jv, const int* Iv, const int* Fv,
+               const sht_options* opts, sht_plan_t* out) {
+  if (!out) return fail(SHT_EINVAL, "out must not be NULL");
+  *out = nullptr;
+  if (nlev < 1 || nlev > SHT_MAX_LEVELS) return fail(SHT_EINVAL, "nlevels must be 1..8");
+  if (!Nv || !Jv || !Iv || !Fv) return fail(SHT_EINVAL, "level arrays must not be NULL");
+  sht_options o{SHT_GRID_CC_POLES, SHT_FORM_FP64, 0, 0};
+  if (opts) o = *opts;
+  if (o.form < SHT_FORM_FP64 || o.form > SHT_FORM_BF16X6) return fail(SHT_EINVAL, "unknown form");
+  if (o.form == SHT_FORM_BF16X6) return fail(SHT_EINVAL, "the split-bfloat16 form is not built in this library version");
+  for (int l = 0; l < nlev; ++l) {
+    int rc = check_level_args(Nv[l], Jv[l], Iv[l], Fv[l], o.grid);
+    if (rc) return rc;
+  }
+
+  sht_plan_s* P = new (std::nothrow) sht_plan_s();
+  if (!P) return fail(SHT_ENOMEM, "host allocation failed");
+  P->form = o.form;
+  P->grid = o.grid;
+  P->autotune = o.autotune;
+  P->use_graph = o.use_graph;
+  P->nlev = nlev;
+  P->elem = o.form == SHT_FORM_FP64 ? 8 : 4;
+  int rc = hip_check(hipGetDevice(&P->device), "hipGetDevice");
+  if (rc) {
+    delete P;
+    return rc;
+  }
+  P->ncb = choose_ncb(o.form, nlev, Nv, Jv, Fv);
+  const int BN = 16 * P->ncb;
+  const int FB = zonal_fields_per_block(o.form);
+
+  // ---- level descriptors and sizes ----
+  long long goff = 0, soff = 0, woff = 0, moff = 0, item = 0;
+  std::vector<long long> taboff;
+  long long tab = 0;
+  for (int l = 0; l < nlev; ++l) {
+    LevelDesc& L = P->lev[l];
+    std::memset(&L, 0, sizeof(L));
+    L.N = Nv[l];
+    L.J = Jv[l];
+    L.I = Iv[l];
+    L.F = Fv[l];
+    L.Jh = (L.J + 1) / 2;
+    L.Kp = (int)roundup(L.Jh, SHT_K_PAD);
+    L.Cp = (int)roundup(2LL * L.F, std::max(BN, 2 * FB));
+    factor_radices(L.I, L.rad, &L.nrad);
+    L.nfb = (L.F + FB - 1) / FB;
+    L.fft_item0 = (int)item;
+    item += (long long)L.Jh * L.nfb;
+    L.m_base = (int)moff;
+    moff += L.N + 1;
+    L.grid_off = goff;
+    goff += (long long)L.F * L.J * L.I;
+    L.spec_off = soff;
+    soff += (long long)L.F * (L.N + 1) * (L.N + 2);
+    L.ws_off = woff;
+    woff += roundup((long long)(L.N + 1) * 2 * L.Kp * L.Cp, 64);
+    for (int m = 0; m <= L.N; ++m) {
+      taboff.push_back(tab);
+      tab += roundup(L.N - m + 1, SHT_ROWS_PAD) * L.Kp;
+    }
+    P->maxN = std::max(P->maxN, L.N);
+    P->flops += 2.0 * L.Jh * (double)(L.N + 1) * (L.N + 2) * L.F;
+    if (L.J < 2 * L.N + 1) P->exact = false;
+  }
+  if (item > 0x7fffffff) {
+    delete P;
+    return fail(SHT_EINVAL, "too many zonal work items");
+  }
+  P->nitems = (int)item;
+  P->grid_elems = (size_t)goff;
+  P->spec_elems = (size_t)soff;
+  P->ws_elems = (size_t)woff;
+  P->table_elems = (size_t)tab;
+  P->table_bytes = P->table_elems * P->elem;
+  P->ws_bytes = P->ws_elems * P->elem;
+
+  // ---- host tables ----
+  std::vector<unsigned char> htab(P->table_bytes);
+  std::vector<double> hw;
+  std::vector<std::vector<unsigned char>> htw(nlev);
+  size_t tw_total = 0;
+  std::vector<size_t> tw_off(nlev), w_off(nlev);
+  size_t w_total = 0;
+  for (int l = 0; l < nlev; ++l) {
+    LevelDesc& L = P->lev[l];
+    std::vector<double> mu(L.J), sint(L.J), w(L.J);
+    grid_nodes(L.J, o.grid, mu.data(), sint.data());
+    grid_weights(L.J, o.grid, w.data());
+    w_off[l] = w_total;
+    w_total += L.Jh;
+    hw.insert(hw.end(), w.begin(), w.begin() + L.Jh);
+    const long long* to = taboff.data() + L.m_base;
+    if (o.form == SHT_FORM_FP64)
+      fill_table_level<double>(L, mu.data(), sint.data(), reinterpret_cast<double*>(htab.data()), to);
+    else
+      fill_table_level<float>(L, mu.data(), sint.data(), reinterpret_cast<float*>(htab.data()), to);
+    // twiddles exp(-2 pi i k / I)
+    const size_t cs = 2 * P->elem;
+    htw[l].resize((size_t)L.I * cs);
+    for (int k = 0; k < L.I; ++k) {
+      const long double ang = 2.0L * 3.141592653589793238462643383279502884L * (long double)k / (long double)L.I;
+      const long double c = cosl(ang), s = -sinl(ang);
+      if (o.form == SHT_FORM_FP64) {
+        double v[2] = {(double)c, (double)s};
+        std::memcpy(&htw[l][k * cs], v, cs);
+      } else {
+        float v[2] = {(float)c, (float)s};
+        std::memcpy(&htw[l][k * cs], v, cs);
+      }
+    }
+    tw_off[l] = tw_total;
+    tw_total += roundup((long long)htw[l].size(), 256);
+  }
+
+  // ---- tile schedules ----
+  std::vector<Tile> tf, ti;
+  std::vector<double> cf, ci;
+  for (int l = 0; l < nlev; ++l) {
+    const LevelDesc& L = P->lev[l];
+    const int ncol = L.Cp / BN;
+    for (int m = 0; m <= L.N; ++m) {
+      const int nm = L.N - m + 1;
+      for (int cb = 0; cb < ncol; ++cb) {
+        for (int rb = 0; rb < (nm + 63) / 64; ++rb) {
+          tf.push_back(Tile{l, m, rb, cb});
+          cf.push_back((double)L.Kp);
+        }
+        for (int jb = 0; jb < L.Kp / 32; ++jb) {
+          ti.push_back(Tile{l, m, jb, cb});
+          ci.push_back((double)roundup(nm, 32));
+        }
+      }
+    }
+  }
+  std::vector<Tile> sf = xcd_schedule(tf, cf), si = xcd_schedule(ti, ci);
+  P->ntiles_fwd = (int)sf.size();
+  P->ntiles_inv = (int)si.size();
+
+  // ---- device buffers ----
+  void *dtw = nullptr, *dw = nullptr, *dto = nullptr, *dtf = nullptr, *dti = nullptr;
+  if ((rc = dev_alloc(P, &P->d_table, P->table_bytes)) ||
+      (rc = dev_alloc(P, &P->d_ws, P->ws_bytes)) ||
+      (rc = dev_alloc(P, &dtw, tw_total)) ||
+      (rc = dev_alloc(P, &dw, w_total * sizeof(double))) ||
+      (rc = dev_alloc(P, &dto, taboff.size() * sizeof(long long))) ||
+      (rc = dev_alloc(P, &dtf, sf.size() * sizeof(Tile))) ||
+      (rc = dev_alloc(P, &dti, si.size() * sizeof(Tile)))) {
+    free_plan(P);
+    delete P;
+    return rc;
+  }
+  P->d_tw = dtw;
+  P->d_w = static_cast<double*>(dw);
+  P->d_taboff = static_cast<long long*>(dto);
+  P->d_tiles_fwd = static_cast<Tile*>(dtf);
+  P->d_tiles_inv = static_cast<Tile*>(dti);
+  for (int l = 0; l < nlev; ++l) {
+    P->lev[l].tw = static_cast<unsigned char*>(dtw) + tw_off[l];
+    P->lev[l].wrow = P->d_w + w_off[l];
+  }
+  rc = hip_check(hipMemcpy(P->d_table, htab.data(), P->table_bytes, hipMemcpyHostToDevice), "upload table");
+  if (!rc) rc = hip_check(hipMemset(P->d_ws, 0, P->ws_bytes), "clear workspace");
+  for (int l = 0; l < nlev && !rc; ++l)
+    rc = hip_check(hipMemcpy(static_cast<unsigned char*>(dtw) + tw_off[l], htw[l].data(), htw[l].size(),
+                             hipMemcpyHostToDevice),
+                   "upload twiddles");
+  if (!rc) rc = hip_check(hipMemcpy(dw, hw.data(), w_total * sizeof(double), hipMemcpyHostToDevice), "upload weights");
+  if (!rc)
+    rc = hip_check(hipMemcpy(dto, taboff.data(), taboff.size() * sizeof(long long), hipMemcpyHostToDevice),
+                   "upload table offsets");
+  if (!rc) rc = hip_check(hipMemcpy(dtf, sf.data(), sf.size() * sizeof(Tile), hipMemcpyHostToDevice), "upload tiles");
+  if (!rc) rc = hip_check(hipMemcpy(dti, si.data(), si.size() * sizeof(Tile), hipMemcpyHostToDevice), "upload tiles");
+  if (!rc) rc = hip_check(hipDeviceSynchronize(), "plan synchronize");
+  if (rc) {
+    free_plan(P);
+    delete P;
+    return rc;
+  }
+  P->magic = kMagic;
+  {
+    std::lock_guard<std::mutex> lk(g_live_mu);
+    g_live.insert(P);
+  }
+  *out = P;
+  return SHT_OK;
+}
+
+int check_plan(sht_plan_t p) {
+  if (!p) return fail(SHT_EINVAL, "plan is NULL");
+  if (!is_live(p) || p->magic != kMagic) return fail(SHT_ESTATE, "plan handle is not live (destroyed?)");
+  return SHT_OK;
+}
+
+int check_ptr(const void* p, const char* name) {
+  if (!p) return fail(SHT_EINVAL, std::string(name) + " must not be NULL");
+  if (reinterpret_cast<uintptr_t>(p) % 16) return fail(SHT_EINVAL, std::string(name) + " must be 16-byte aligned");
+  return SHT_OK;
+}
+
+FftArgs fft_args(const sht_plan_s* P, const void* src, void* dst, int use_w, int use_inv_I, double mscale) {
+  FftArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.nlev = P->nlev;
+  a.nitems = P->nitems;
+  for (int l = 0; l < P->nlev; ++l) a.lev[l] = P->lev[l];
+  a.src = src;
+  a.dst = dst;
+  a.use_w = use_w;
+  a.use_inv_I = use_inv_I;
+  a.mscale = mscale;
+  return a;
+}
+
+GemmArgs gemm_args(const sht_plan_s* P, bool analysis, const void* spec_in, void* spec_out) {
+  GemmArgs g;
+  std::memset(&g, 0, sizeof(g));
+  g.nlev = P->nlev;
+  for (int l = 0; l < P->nlev; ++l) g.lev[l] = P->lev[l];
+  g.ntiles = analysis ? P->ntiles_fwd : P->ntiles_inv;
+  g.tiles = analysis ? P->d_tiles_fwd : P->d_tiles_inv;
+  g.tab_off = P->d_taboff;
+  g.table = P->d_table;
+  g.spec_in = spec_in;
+  g.spec_out = spec_out;
+  g.ws = P->d_ws;
+  return g;
+}
+
+// Stage ids for profiling.
+enum { ST_ZONAL_A = 0, ST_LEG_A = 1, ST_LEG_S = 2, ST_ZONAL_S = 3, ST_COUNT = 4 };
+
+hipEvent_t next_event(sht_plan_s* P) {
+  if (P->ev_used == P->ev_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    P->ev_pool.push_back(e);
+  }
+  return P->ev_pool[P->ev_used++];
+}
+
+void prof_mark(sht_plan_s* P, void* stream, int stage, bool start) {
+  if (!P->profile) return;
+  hipEvent_t e = next_event(P);
+  if (!e) return;
+  (void)hipEventRecord(e, static_cast<hipStream_t>(stream));
+  if (start) P->ev_stage.push_back(stage);
+}
+
+// grid -> spec through the zonal analysis (row scale and m scale given)
+int run_analysis(sht_plan_s* P, const void* grid, void* spec, void* stream, int use_w, int use_inv_I,
+                 double mscale) {
+  FftArgs a = fft_args(P, grid, P->d_ws, use_w, use_inv_I, mscale);
+  prof_mark(P, stream, ST_ZONAL_A, true);
+  int e = launch_zonal(P->form, true, a, P->maxN, stream);
+  prof_mark(P, stream, ST_ZONAL_A, false);
+  if (e) return hip_check((hipError_t)e, "zonal analysis launch");
+  GemmArgs g = gemm_args(P, true, nullptr, spec);
+  prof_mark(P, stream, ST_LEG_A, true);
+  e = launch_legendre(P->form, true, g, P->ncb, stream);
+  prof_mark(P, stream, ST_LEG_A, false);
+  if (e) return hip_check((hipError_t)e, "Legendre analysis launch");
+  return SHT_OK;
+}
+
+int run_synthesis(sht_plan_s* P, const void* spec, void* grid, void* stream, int use_w, int use_inv_I,
+                  double mscale) {
+  GemmArgs g = gemm_args(P, false, spec, nullptr);
+  prof_mark(P, stream, ST_LEG_S, true);
+  int e = launch_legendre(P->form, false, g, P->ncb, stream);
+  prof_mark(P, stream, ST_LEG_S, false);
+  if (e) return hip_check((hipError_t)e, "Legendre synthesis launch");
+  FftArgs a = fft_args(P, P->d_ws, grid, use_w, use_inv_I, mscale);
+  prof_mark(P, stream, ST_ZONAL_S, true);
+  e = launch_zonal(P->form, false, a, P->maxN, stream);
+  prof_mark(P, stream, ST_ZONAL_S, false);
+  if (e) return hip_check((hipError_t)e, "zonal synthesis launch");
+  return SHT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* sht_last_error(void) { return g_err.c_str(); }
+
+sht_plan_t sht_plan(int N, int J, int I, int nfields) {
+  sht_plan_t p = nullptr;
+  if (build_plan(1, &N, &J, &I, &nfields, nullptr, &p) != SHT_OK) return nullptr;
+  return p;
+}
+
+int sht_plan_ex(int N, int J, int I, int nfields, const sht_options* opts, sht_plan_t* out) {
+  return build_plan(1, &N, &J, &I, &nfields, opts, out);
+}
+
+int sht_plan_multi(int nlevels, const int* N, const int* J, const int* I, const int* nfields,
+                   const sht_options* opts, sht_plan_t* out) {
+  return build_plan(nlevels, N, J, I, nfields, opts, out);
+}
+
+int sht_forward(sht_plan_t plan, const void* grid, void* spec, void* stream) {
+  int rc;
+  if ((rc = check_plan(plan)) || (rc = check_ptr(grid, "grid")) || (rc = check_ptr(spec, "spec"))) return rc;
+  return run_analysis(plan, grid, spec, stream, 1, 1, 1.0);
+}
+
+int sht_inverse(sht_plan_t plan, const void* spec, void* grid, void* stream) {
+  int rc;
+  if ((rc = check_plan(plan)) || (rc = check_ptr(spec, "spec")) || (rc = check_ptr(grid, "grid"))) return rc;
+  return run_synthesis(plan, spec, grid, stream, 0, 0, 1.0);
+}
+
+int sht_forward_adjoint(sht_plan_t plan, const void* spec_bar, void* grid_bar, void* stream) {
+  int rc;
+  if ((rc = check_plan(plan)) || (rc = check_ptr(spec_bar, "spec_bar")) || (rc = check_ptr(grid_bar, "grid_bar")))
+    return rc;
+  return run_synthesis(plan, spec_bar, grid_bar, stream, 1, 1, 0.5);
+}
+
+int sht_inverse_adjoint(sht_plan_t plan, const void* grid_bar, void* spec_bar, void* stream) {
+  int rc;
+  if ((rc = check_plan(plan)) || (rc = check_ptr(grid_bar, "grid_bar")) || (rc = check_ptr(spec_bar, "spec_bar")))
+    return rc;
+  return run_analysis(plan, grid_bar, spec_bar, stream, 0, 0, 2.0);
+}
+
+int sht_plan_query(sht_plan_t plan, int key, void* out) {
+  int rc;
+  if ((rc = check_plan(plan))) return rc;
+  if (!out) return fail(SHT_EINVAL, "out must not be NULL");
+  const sht_plan_s* P = plan;
+  switch (key) {
+    case SHT_Q_NLEVELS: *(int*)out = P->nlev; return SHT_OK;
+    case SHT_Q_NCOEF: *(int*)out = (P->lev[0].N + 1) * (P->lev[0].N + 2) / 2; return SHT_OK;
+    case SHT_Q_EXACT: *(int*)out = P->exact ? 1 : 0; return SHT_OK;
+    case SHT_Q_WORKSPACE_BYTES: *(size_t*)out = P->ws_bytes; return SHT_OK;
+    case SHT_Q_TABLE_BYTES: *(size_t*)out = P->table_bytes; return SHT_OK;
+    case SHT_Q_GRID_ELEMS: *(size_t*)out = P->grid_elems; return SHT_OK;
+    case SHT_Q_SPEC_ELEMS: *(size_t*)out = P->spec_elems; return SHT_OK;
+    case SHT_Q_FORM: *(int*)out = P->form; return SHT_OK;
+    case SHT_Q_GRID_KIND: *(int*)out = P->grid; return SHT_OK;
+    case SHT_Q_LEGENDRE_FLOPS: *(double*)out = P->flops; return SHT_OK;
+    default: break;
+  }
+  if (key >= SHT_Q_GRID_OFFSET && key < SHT_Q_GRID_OFFSET + P->nlev) {
+    *(size_t*)out = (size_t)P->lev[key - SHT_Q_GRID_OFFSET].grid_off;
+    return SHT_OK;
+  }
+  if (key >= SHT_Q_SPEC_OFFSET && key < SHT_Q_SPEC_OFFSET + P->nlev) {
+    *(size_t*)out = (size_t)P->lev[key - SHT_Q_SPEC_OFFSET].spec_off;
+    return SHT_OK;
+  }
+  return fail(SHT_EINVAL, "unknown query key");
+}
+
+int sht_host_tables(int N, int J, int grid, double* mu, double* w, double* alf) {
+  if (N < 0) return fail(SHT_EINVAL, "N must be >= 0");
+  if (!grid_args_ok(J, grid)) return fail(SHT_EINVAL, "bad J or grid kind");
+  std::vector<double> m_(J), s_(J), w_(J);
+  grid_nodes(J, grid, m_.data(), s_.data());
+  grid_weights(J, grid, w_.data());
+  if (mu) std::memcpy(mu, m_.data(), J * sizeof(double));
+  if (w) std::memcpy(w, w_.data(), J * sizeof(double));
+  if (alf) {
+    int nth = (int)std::thread::hardware_concurrency();
+    alf_table(N, (J + 1) / 2, m_.data(), s_.data(), alf, std::max(1, std::min(nth, 64)));
+  }
+  return SHT_OK;
+}
+
+int sht_plan_tables(sht_plan_t plan, double* mu, double* w, double* alf) {
+  int rc;
+  if ((rc = check_plan(plan))) return rc;
+  return sht_host_tables(plan->lev[0].N, plan->lev[0].J, plan->grid, mu, w, alf);
+}
+
+int sht_plan_profile(sht_plan_t plan, int enable) {
+  int rc;
+  if ((rc = check_plan(plan))) return rc;
+  plan->profile = enable ? 1 : 0;
+  plan->ev_used = 0;
+  plan->ev_stage.clear();
+  return SHT_OK;
+}
+
+int sht_plan_profile_read(sht_plan_t plan, double* ms, int* counts) {
+  int rc;
+  if ((rc = check_plan(plan))) return rc;
+  if (!ms || !counts) return fail(SHT_EINVAL, "ms and counts must not be NULL");
+  for (int k = 0; k < ST_COUNT; ++k) {
+    ms[k] = 0.0;
+    counts[k] = 0;
+  }
+  if (plan->ev_used) {
+    rc = hip_check(hipEventSynchronize(plan->ev_pool[plan->ev_used - 1]), "profile synchronize");
+    if (rc) return rc;
+  }
+  for (size_t k = 0; k < plan->ev_stage.size() && 2 * k + 1 < plan->ev_used; ++k) {
+    float t = 0.f;
+    rc = hip_check(hipEventElapsedTime(&t, plan->ev_pool[2 * k], plan->ev_pool[2 * k + 1]), "profile read");
+    if (rc) return rc;
+    ms[plan->ev_stage[k]] += t;
+    counts[plan->ev_stage[k]] += 1;
+  }
+  plan->ev_used = 0;
+  plan->ev_stage.clear();
+  return SHT_OK;
+}
+
+int sht_plan_destroy(sht_plan_t plan) {
+  int rc;
+  if ((rc = check_plan(plan))) return rc;
+  {
+    std::lock_guard<std::mutex> lk(g_live_mu);
+    g_live.erase(plan);
+  }
+  plan->magic = 0;
+  free_plan(plan);
+  delete plan;
+  return SHT_OK;
+}
+
+}  // extern "C"

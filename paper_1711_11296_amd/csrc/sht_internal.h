@@ -1,0 +1,92 @@
+// Internal declarations shared by the host planner, the kernels and the C ABI.
+#ifndef SHT_INTERNAL_H_
+#define SHT_INTERNAL_H_
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/sht.h"
+
+#define SHT_MAX_LEVELS 8
+#define SHT_MAX_RADICES 16
+#define SHT_MAX_I 4096
+
+// Table rows of one m are padded to a multiple of this (forward tile height).
+#define SHT_ROWS_PAD 64
+// Latitude (contraction) dimension of the table and workspace is padded to a
+// multiple of this.
+#define SHT_K_PAD 32
+
+namespace sht {
+
+// ---- host planning (sht_host.cpp) ----
+bool grid_args_ok(int J, int kind);
+void grid_nodes(int J, int kind, double* mu, double* sint);
+void grid_weights(int J, int kind, double* w);
+void alf_column(int N, int m, int nr, const double* mu, const double* sint,
+                double* out, long ld);
+void alf_table(int N, int nr, const double* mu, const double* sint,
+               double* out, int nthreads);
+bool factor_radices(int I, int* rad, int* nrad);
+
+// ---- device-side descriptors ----
+
+// One transform level as the kernels see it.
+struct LevelDesc {
+  int N, J, I, F;
+  int Jh;      // ceil(J/2): folded rows (northern rows incl. equator)
+  int Kp;      // Jh padded to SHT_K_PAD
+  int Cp;      // workspace row length (columns = 2F padded)
+  int nrad;
+  int rad[SHT_MAX_RADICES];
+  int fft_item0;   // first FFT work item of this level
+  int nfb;         // field blocks of the FFT kernels
+  int m_base;      // index of (level, m=0) in the per-m offset arrays
+  int pad_;
+  long long grid_off;  // element offset of this level in the grid buffer
+  long long spec_off;  // element offset of this level in the spec buffer
+  long long ws_off;    // element offset in the workspace
+  const void* tw;      // I twiddles exp(-2 pi i k / I), complex, data type
+  const double* wrow;  // Jh quadrature weights of the northern rows
+};
+
+struct FftArgs {
+  int nlev;
+  int nitems;
+  LevelDesc lev[SHT_MAX_LEVELS];
+  const void* src;   // grid (analysis) or workspace (synthesis)
+  void* dst;         // workspace (analysis) or grid (synthesis)
+  // scalars: value *= (use_w ? w_j : 1) * (use_inv_I ? 1/I : 1) * (m ? mscale : 1)
+  int use_w;
+  int use_inv_I;
+  double mscale;
+};
+
+// One work tile of a Legendre kernel; level < 0 marks an idle slot.
+struct Tile {
+  int level, m, rb, cb;
+};
+
+struct GemmArgs {
+  int nlev;
+  int ntiles;
+  LevelDesc lev[SHT_MAX_LEVELS];
+  const Tile* tiles;           // one per workgroup
+  const long long* tab_off;    // per (level, m): element offset of the table block
+  const void* table;           // P~ table (data type, or 3 bf16 planes)
+  long long table_plane;       // elements per bf16 plane (split form)
+  const void* spec_in;         // synthesis: spectra
+  void* spec_out;              // analysis: spectra
+  void* ws;                    // workspace
+};
+
+// ---- kernel launchers (sht_fft.hip, sht_legendre.hip) ----
+// The stream argument is a hipStream_t.
+int zonal_fields_per_block(int form);
+int launch_zonal(int form, bool analysis, const FftArgs& a, int maxN, void* stream);
+int launch_legendre(int form, bool analysis, const GemmArgs& g, int ncb, void* stream);
+size_t legendre_lds_bytes(int form, bool analysis, int ncb);
+
+}  // namespace sht
+
+#endif  // SHT_INTERNAL_H_

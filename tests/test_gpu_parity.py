@@ -1,0 +1,170 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle on the
+same seeded inputs.  Bounds: rel-L2 <= 1e-12 for the FP64 form, <= 1e-6 for
+the FP32 form (the oracle receives the FP32 inputs promoted to FP64)."""
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1711_11296_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+TOL = {"fp64": 1e-12, "fp32": 1e-6}
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def _plan(N, J, I, F, kind, form):
+    from paper_1711_11296_amd import Plan
+    return Plan(N, J, I, F, grid=kind, form=form)
+
+
+def _to_dev(x, form):
+    dt = torch.float64 if form == "fp64" else torch.float32
+    return torch.from_numpy(np.ascontiguousarray(x)).to(device=_dev(), dtype=dt)
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.detach().to("cpu", torch.float64).numpy()
+
+
+def _roundtrip_case(N, J, I, F, kind, form, profile="inv1", seed=0):
+    p = _plan(N, J, I, F, kind, form)
+    a = inputs.random_spectra(N, F, seed=seed, profile=profile)
+    a_d = _to_dev(a, form)
+    a_in = _host(a_d)                         # what the GPU received
+    g_d = p.inverse(a_d)
+    g_ref = O.inverse(a_in, N, J, I, kind)
+    assert rel(_host(g_d), g_ref) < TOL[form], "inverse"
+    g_in = _host(g_d)
+    s_d = p.forward(g_d)
+    s_ref = O.forward(g_in, N, kind)
+    assert rel(_host(s_d), s_ref) < TOL[form], "forward"
+    if J >= 2 * N + 1:
+        assert rel(_host(s_d), a_in) < 10 * TOL[form], "round trip"
+    p.close()
+
+
+@pytest.mark.parametrize("kind", O.GRID_KINDS)
+def test_c1_fp64_round_trip(kind):
+    """N=21, J=43, I=64, one field, spectra with std (n+1)^-1, seed 0."""
+    _roundtrip_case(21, 43, 64, 1, kind, "fp64")
+
+
+@pytest.mark.parametrize("form", ["fp64", "fp32"])
+@pytest.mark.parametrize("kind", O.GRID_KINDS)
+@pytest.mark.parametrize("N", [0, 1, 2, 5, 8])
+def test_tiny_sweep(form, kind, N):
+    """Every J from 2N-3 to 2N+3 (odd and even, aliasing or exact)."""
+    for J in range(max(2, 2 * N - 3), 2 * N + 4):
+        I = max(2 * N + 1, 1)
+        I = {1: 1, 3: 3, 5: 5, 11: 12, 17: 18}.get(I, I)
+        _roundtrip_case(N, J, I, 3, kind, form, seed=N * 100 + J)
+
+
+@pytest.mark.parametrize("form", ["fp64", "fp32"])
+@pytest.mark.parametrize("kind,N,J,I,F", [
+    ("cc_poles", 100, 203, 216, 5),     # several row and K tiles, ragged tails, 2^3 3^3
+    ("fejer2", 130, 250, 300, 9),       # even J (no equator row), F not a multiple of 8
+    ("cc_poles", 64, 129, 200, 17),     # 5^2 radix, three field blocks
+    ("fejer2", 33, 80, 81, 2),          # J > 2N+1, pure radix 3
+])
+def test_multi_tile_parity(form, kind, N, J, I, F):
+    _roundtrip_case(N, J, I, F, kind, form, profile="k3", seed=N)
+
+
+@pytest.mark.parametrize("form", ["fp64", "fp32"])
+@pytest.mark.parametrize("kind", O.GRID_KINDS)
+def test_random_grid_forward(form, kind):
+    """Analysis of a grid that is not band-limited is still the oracle's map."""
+    N, J, I, F = 40, 81, 96, 4
+    p = _plan(N, J, I, F, kind, form)
+    g = _to_dev(inputs.random_grid(F, J, I, seed=3), form)
+    s = p.forward(g)
+    assert rel(_host(s), O.forward(_host(g), N, kind)) < TOL[form]
+    p.close()
+
+
+@pytest.mark.parametrize("form", ["fp64", "fp32"])
+@pytest.mark.parametrize("kind", O.GRID_KINDS)
+def test_adjoints_against_oracle(form, kind):
+    N, J, I, F = 30, 61, 64, 3
+    p = _plan(N, J, I, F, kind, form)
+    sb = _to_dev(inputs.random_spectra(N, F, seed=4, profile="inv1"), form)
+    gb = _to_dev(inputs.random_grid(F, J, I, seed=5), form)
+    x = p.forward_adjoint(sb)
+    assert rel(_host(x), O.forward_adjoint(_host(sb), N, J, I, kind)) < TOL[form]
+    y = p.inverse_adjoint(gb)
+    assert rel(_host(y), O.inverse_adjoint(_host(gb), N, kind)) < TOL[form]
+    p.close()
+
+
+@pytest.mark.parametrize("form", ["fp64", "fp32"])
+def test_c2_full_batch(form):
+    """N=159, J=319, I=480, 64 fields (16 levels x 4 variables), k^-3 spectra."""
+    N, J, I, F = 159, 319, 480, 64
+    for kind in O.GRID_KINDS:
+        p = _plan(N, J, I, F, kind, form)
+        a = inputs.random_spectra(N, F, seed=0, profile="k3")
+        a_d = _to_dev(a, form)
+        g_d = p.inverse(a_d)
+        g_ref = O.inverse(_host(a_d), N, J, I, kind)
+        assert rel(_host(g_d), g_ref) < TOL[form]
+        g_in = _to_dev(g_ref, form)
+        s_d = p.forward(g_in)
+        assert rel(_host(s_d), O.forward(_host(g_in), N, kind)) < TOL[form]
+        p.close()
+
+
+def test_determinism_and_stream_order():
+    N, J, I, F = 100, 201, 216, 8
+    p = _plan(N, J, I, F, "cc_poles", "fp32")
+    g = _to_dev(inputs.random_grid(F, J, I, seed=9), "fp32")
+    s1 = p.forward(g).clone()
+    s2 = p.forward(g).clone()
+    torch.cuda.synchronize()
+    assert torch.equal(s1, s2)
+    x1 = p.inverse(s1).clone()
+    x2 = p.inverse(s1).clone()
+    torch.cuda.synchronize()
+    assert torch.equal(x1, x2)
+    p.close()
+
+
+def test_nan_isolation_between_fields():
+    N, J, I, F = 20, 41, 48, 8
+    p = _plan(N, J, I, F, "fejer2", "fp64")
+    g = inputs.random_grid(F, J, I, seed=10)
+    g[3, 7, 11] = np.nan
+    s = _host(p.forward(_to_dev(g, "fp64")))
+    assert np.isnan(s[3]).any()
+    others = np.delete(s, 3, axis=0)
+    assert np.isfinite(others).all()
+    p.close()
+
+
+def test_error_paths_on_device():
+    from paper_1711_11296_amd import Plan, SHTError
+    p = Plan(10, 21, 24, 2, form="fp64")
+    with pytest.raises(ValueError):
+        p.forward(torch.zeros(5, device=_dev(), dtype=torch.float64))
+    with pytest.raises(ValueError):
+        p.forward(torch.zeros(p.grid_shape, device=_dev(), dtype=torch.float32))
+    p.close()
+    p.close()  # idempotent in Python
+    with pytest.raises(SHTError):
+        Plan(10, 21, 20, 2)      # I < 2N+1
