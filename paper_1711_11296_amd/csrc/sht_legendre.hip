@@ -43,13 +43,19 @@ struct Acc<double> {
 };
 
 // 16x16x4 outer-product step: lane l supplies A[l%16][k] and B[k][l%16]
-// for k = l/16 (any k labelling works as long as A and B agree); lane l
-// receives C[4*(l/16) + i][l%16] in element i.
+// for k = l/16 (any k labelling works as long as A and B agree).  Element i
+// of lane l's result is C[out_row(l/16, i)][l%16]: rows 4*(l/16) + i for
+// the FP32 instruction, (l/16) + 4*i for the FP64 one (measured lane layout).
 __device__ __forceinline__ f32x4 mfma16(float a, float b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 __device__ __forceinline__ f64x4 mfma16(double a, double b, f64x4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+template <typename T>
+__device__ __forceinline__ int out_row(int lg, int i) {
+  return sizeof(T) == 8 ? lg + 4 * i : 4 * lg + i;
 }
 
 __device__ __forceinline__ long long spec_idx(int N, int m, int n) {
@@ -147,7 +153,7 @@ __global__ __launch_bounds__(256) void k_legendre_analysis(const GemmArgs g) {
   for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int rl = 32 * h + 2 * (4 * lg + i) + p;
+      const int rl = 32 * h + 2 * out_row<T>(lg, i) + p;
       Cs[rl * BN + cb * 16 + li] = acc[cb][i];
     }
   __syncthreads();
@@ -249,7 +255,7 @@ __global__ __launch_bounds__(256) void k_legendre_synthesis(const GemmArgs g) {
   T* ws = static_cast<T*>(g.ws) + L.ws_off + (2LL * m + p) * Kp * Cp;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const int j = j0 + 16 * h + 4 * lg + i;
+    const int j = j0 + 16 * h + out_row<T>(lg, i);
     if (j < L.Jh) {
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb) ws[(long long)j * Cp + c0 + cb * 16 + li] = acc[cb][i];
