@@ -60,7 +60,10 @@ struct sht_plan_s {
   size_t ws_elems = 0, table_elems = 0, table_bytes = 0, ws_bytes = 0;
   double flops = 0.0;
   bool exact = true;
-  void* d_table = nullptr;
+  void* d_table = nullptr;      // analysis copy of the table
+  void* d_table_syn = nullptr;  // synthesis copy (blocked, parity split)
+  size_t table_syn_elems = 0;
+  long long* d_taboff_syn = nullptr;
   void* d_ws = nullptr;
   void* d_tw = nullptr;
   double* d_w = nullptr;
@@ -174,11 +177,15 @@ std::vector<Tile> xcd_schedule(const std::vector<Tile>& tiles, const std::vector
   return out;
 }
 
+// Fill both copies of one level's table from FP64 columns of P~:
+//  analysis copy: per m, rows r = n - m padded to SHT_ROWS_PAD, Kp columns;
+//  synthesis copy: per m, blocks (64-row j block, 32-row r block), each
+//  laid out [parity][64 j][16 r'] with r = 32 kb + 2 r' + parity.
 template <typename T>
 void fill_table_level(const LevelDesc& L, const double* mu, const double* sint,
-                      T* dst, const long long* taboff_level) {
-  // dst is the whole table; rows of each m go to taboff_level[m]
+                      T* dst, const long long* off_a, T* dsyn, const long long* off_s) {
   const int N = L.N, Jh = L.Jh, Kp = L.Kp;
+  const int JB = (Jh + 63) / 64;
   int nth = (int)std::thread::hardware_concurrency();
   nth = std::max(1, std::min(nth, 64));
   std::vector<std::thread> pool;
@@ -190,11 +197,23 @@ void fill_table_level(const LevelDesc& L, const double* mu, const double* sint,
         const int nm = N - m + 1;
         col.assign((size_t)nm * Jh, 0.0);
         alf_column(N, m, Jh, mu, sint, col.data(), Jh);
-        T* blk = dst + taboff_level[m];
+        T* blk = dst + off_a[m];
         const int R = (int)roundup(nm, SHT_ROWS_PAD);
         for (int r = 0; r < R; ++r)
           for (int j = 0; j < Kp; ++j)
             blk[(size_t)r * Kp + j] = (r < nm && j < Jh) ? (T)col[(size_t)r * Jh + j] : (T)0;
+        const int nkb = (nm + 31) / 32;
+        T* sb = dsyn + off_s[m];
+        for (int jb = 0; jb < JB; ++jb)
+          for (int kb = 0; kb < nkb; ++kb) {
+            T* b = sb + ((size_t)jb * nkb + kb) * 2048;
+            for (int par = 0; par < 2; ++par)
+              for (int jl = 0; jl < 64; ++jl)
+                for (int kl = 0; kl < 16; ++kl) {
+                  const int r = kb * 32 + 2 * kl + par, j = jb * 64 + jl;
+                  b[(par * 64 + jl) * 16 + kl] = (r < nm && j < Jh) ? (T)col[(size_t)r * Jh + j] : (T)0;
+                }
+          }
       }
     });
   }
@@ -235,8 +254,8 @@ int build_plan(int nlev, const int* Nv, const int* Jv, const int* Iv, const int*
 
   // ---- level descriptors and sizes ----
   long long goff = 0, soff = 0, woff = 0, moff = 0, item = 0;
-  std::vector<long long> taboff;
-  long long tab = 0;
+  std::vector<long long> taboff, taboff_syn;
+  long long tab = 0, tabs = 0;
   for (int l = 0; l < nlev; ++l) {
     LevelDesc& L = P->lev[l];
     std::memset(&L, 0, sizeof(L));
@@ -262,6 +281,8 @@ int build_plan(int nlev, const int* Nv, const int* Jv, const int* Iv, const int*
     for (int m = 0; m <= L.N; ++m) {
       taboff.push_back(tab);
       tab += roundup(L.N - m + 1, SHT_ROWS_PAD) * L.Kp;
+      taboff_syn.push_back(tabs);
+      tabs += (long long)((L.Jh + 63) / 64) * ((L.N - m + 1 + 31) / 32) * 2048;
     }
     P->maxN = std::max(P->maxN, L.N);
     P->flops += 2.0 * L.Jh * (double)(L.N + 1) * (L.N + 2) * L.F;
@@ -276,11 +297,12 @@ int build_plan(int nlev, const int* Nv, const int* Jv, const int* Iv, const int*
   P->spec_elems = (size_t)soff;
   P->ws_elems = (size_t)woff;
   P->table_elems = (size_t)tab;
-  P->table_bytes = P->table_elems * P->elem;
+  P->table_syn_elems = (size_t)tabs;
+  P->table_bytes = (P->table_elems + P->table_syn_elems) * P->elem;
   P->ws_bytes = P->ws_elems * P->elem;
 
   // ---- host tables ----
-  std::vector<unsigned char> htab(P->table_bytes);
+  std::vector<unsigned char> htab(P->table_elems * P->elem), htabs(P->table_syn_elems * P->elem);
   std::vector<double> hw;
   std::vector<std::vector<unsigned char>> htw(nlev);
   size_t tw_total = 0;
@@ -295,10 +317,13 @@ int build_plan(int nlev, const int* Nv, const int* Jv, const int* Iv, const int*
     w_total += L.Jh;
     hw.insert(hw.end(), w.begin(), w.begin() + L.Jh);
     const long long* to = taboff.data() + L.m_base;
+    const long long* ts = taboff_syn.data() + L.m_base;
     if (o.form == SHT_FORM_FP64)
-      fill_table_level<double>(L, mu.data(), sint.data(), reinterpret_cast<double*>(htab.data()), to);
+      fill_table_level<double>(L, mu.data(), sint.data(), reinterpret_cast<double*>(htab.data()), to,
+                               reinterpret_cast<double*>(htabs.data()), ts);
     else
-      fill_table_level<float>(L, mu.data(), sint.data(), reinterpret_cast<float*>(htab.data()), to);
+      fill_table_level<float>(L, mu.data(), sint.data(), reinterpret_cast<float*>(htab.data()), to,
+                              reinterpret_cast<float*>(htabs.data()), ts);
     // twiddles exp(-2 pi i k / I)
     const size_t cs = 2 * P->elem;
     htw[l].resize((size_t)L.I * cs);
@@ -330,9 +355,9 @@ int build_plan(int nlev, const int* Nv, const int* Jv, const int* Iv, const int*
           tf.push_back(Tile{l, m, rb, cb});
           cf.push_back((double)L.Kp);
         }
-        for (int jb = 0; jb < L.Kp / 32; ++jb) {
+        for (int jb = 0; jb < (L.Jh + 63) / 64; ++jb) {
           ti.push_back(Tile{l, m, jb, cb});
-          ci.push_back((double)roundup(nm, 32));
+          ci.push_back((double)roundup(nm, 32) + 16.0);
         }
       }
     }
@@ -342,8 +367,10 @@ int build_plan(int nlev, const int* Nv, const int* Jv, const int* Iv, const int*
   P->ntiles_inv = (int)si.size();
 
   // ---- device buffers ----
-  void *dtw = nullptr, *dw = nullptr, *dto = nullptr, *dtf = nullptr, *dti = nullptr;
-  if ((rc = dev_alloc(P, &P->d_table, P->table_bytes)) ||
+  void *dtw = nullptr, *dw = nullptr, *dto = nullptr, *dtf = nullptr, *dti = nullptr, *dtos = nullptr;
+  if ((rc = dev_alloc(P, &P->d_table, P->table_elems * P->elem)) ||
+      (rc = dev_alloc(P, &P->d_table_syn, P->table_syn_elems * P->elem)) ||
+      (rc = dev_alloc(P, &dtos, taboff_syn.size() * sizeof(long long))) ||
       (rc = dev_alloc(P, &P->d_ws, P->ws_bytes)) ||
       (rc = dev_alloc(P, &dtw, tw_total)) ||
       (rc = dev_alloc(P, &dw, w_total * sizeof(double))) ||
@@ -357,13 +384,19 @@ int build_plan(int nlev, const int* Nv, const int* Jv, const int* Iv, const int*
   P->d_tw = dtw;
   P->d_w = static_cast<double*>(dw);
   P->d_taboff = static_cast<long long*>(dto);
+  P->d_taboff_syn = static_cast<long long*>(dtos);
   P->d_tiles_fwd = static_cast<Tile*>(dtf);
   P->d_tiles_inv = static_cast<Tile*>(dti);
   for (int l = 0; l < nlev; ++l) {
     P->lev[l].tw = static_cast<unsigned char*>(dtw) + tw_off[l];
     P->lev[l].wrow = P->d_w + w_off[l];
   }
-  rc = hip_check(hipMemcpy(P->d_table, htab.data(), P->table_bytes, hipMemcpyHostToDevice), "upload table");
+  rc = hip_check(hipMemcpy(P->d_table, htab.data(), htab.size(), hipMemcpyHostToDevice), "upload table");
+  if (!rc)
+    rc = hip_check(hipMemcpy(P->d_table_syn, htabs.data(), htabs.size(), hipMemcpyHostToDevice), "upload table");
+  if (!rc)
+    rc = hip_check(hipMemcpy(dtos, taboff_syn.data(), taboff_syn.size() * sizeof(long long), hipMemcpyHostToDevice),
+                   "upload table offsets");
   if (!rc) rc = hip_check(hipMemset(P->d_ws, 0, P->ws_bytes), "clear workspace");
   for (int l = 0; l < nlev && !rc; ++l)
     rc = hip_check(hipMemcpy(static_cast<unsigned char*>(dtw) + tw_off[l], htw[l].data(), htw[l].size(),
@@ -423,8 +456,8 @@ GemmArgs gemm_args(const sht_plan_s* P, bool analysis, const void* spec_in, void
   for (int l = 0; l < P->nlev; ++l) g.lev[l] = P->lev[l];
   g.ntiles = analysis ? P->ntiles_fwd : P->ntiles_inv;
   g.tiles = analysis ? P->d_tiles_fwd : P->d_tiles_inv;
-  g.tab_off = P->d_taboff;
-  g.table = P->d_table;
+  g.tab_off = analysis ? P->d_taboff : P->d_taboff_syn;
+  g.table = analysis ? P->d_table : P->d_table_syn;
   g.spec_in = spec_in;
   g.spec_out = spec_out;
   g.ws = P->d_ws;

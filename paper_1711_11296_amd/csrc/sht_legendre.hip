@@ -73,11 +73,25 @@ struct V16<double> {
   typedef double type __attribute__((ext_vector_type(2)));
 };
 
+// 16-byte vector store into LDS at an address that is only 8-byte aligned.
+template <typename T>
+__device__ __forceinline__ void lds_store8(T* dst, const typename V16<T>::type& v) {
+  if constexpr (sizeof(T) == 4) {
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    reinterpret_cast<f2*>(dst)[0] = f2{v[0], v[1]};
+    reinterpret_cast<f2*>(dst)[1] = f2{v[2], v[3]};
+  } else {
+    *reinterpret_cast<typename V16<T>::type*>(dst) = v;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // analysis: C[n][c] = P[n][j] * B_par(n)[j][c]
-// tile = 64 consecutive rows n - m (both parities) x BN = 16*NCB columns.
-// wave w: parity p = w & 1, half h = w >> 1; its 16 rows are
-//   r = 32 h + 2 i + p, i = 0..15 (local to the tile).
+// tile = 64 consecutive rows r = n - m (both parities) x BN = 16*NCB columns.
+// wave w: parity p = w & 1 and column half ch = w >> 1; it owns the 32 rows
+// r = 2 i + p (two 16-row MFMA blocks) and HC = ceil(NCB/2) column blocks.
+// The contraction runs over j in blocks of KB with a register prefetch of
+// the next block while the matrix cores work on the current one.
 // ---------------------------------------------------------------------------
 template <typename T, int NCB>
 __global__ __launch_bounds__(256) void k_legendre_analysis(const GemmArgs g) {
@@ -87,8 +101,11 @@ __global__ __launch_bounds__(256) void k_legendre_analysis(const GemmArgs g) {
   constexpr int KB = sizeof(T) == 4 ? 32 : 16;    // contraction block
   constexpr int KQ = KB / 4;                       // k-steps per block
   constexpr int BN = 16 * NCB;
-  constexpr int AS = KB + E;                       // LDS row stride of A
-  constexpr int BS = BN + E;                       // LDS row stride of B
+  constexpr int HC = (NCB + 1) / 2;                // column blocks per wave
+  constexpr int AS = KB + E;                       // odd number of 16-byte units
+  constexpr int BS = BN + 2;                       // conflict-free B reads
+  constexpr int NA = 64 * KB / E / 256;            // A vectors per thread
+  constexpr int NB = 2 * KB * BN / E / 256;        // B vectors per thread
 
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* As = reinterpret_cast<T*>(smem_raw);          // [64][AS]
@@ -104,57 +121,109 @@ __global__ __launch_bounds__(256) void k_legendre_analysis(const GemmArgs g) {
   const int Kp = L.Kp;
   const long long Cp = L.Cp;
   const T* tab = static_cast<const T*>(g.table) + g.tab_off[L.m_base + m] + (long long)r0 * Kp;
-  const T* wsm = static_cast<const T*>(g.ws) + L.ws_off + (2LL * m) * Kp * Cp;
   const long long plane = (long long)Kp * Cp;
+  const T* wsm = static_cast<const T*>(g.ws) + L.ws_off + (2LL * m) * plane + c0;
 
   const int tid = threadIdx.x;
   const int w = tid >> 6, lane = tid & 63;
-  const int p = w & 1, h = w >> 1;
+  const int p = w & 1, ch = w >> 1;
   const int li = lane & 15, lg = lane >> 4;
-  const int arow = 32 * h + 2 * li + p;            // this lane's A row
-  const bool active = (r0 + 32 * h + p) < nm;
+  bool act[2];
+  act[0] = (r0 + p) < nm;
+  act[1] = (r0 + 32 + p) < nm;
 
-  AccT acc[NCB];
+  AccT acc[2][HC];
 #pragma unroll
-  for (int cb = 0; cb < NCB; ++cb) acc[cb] = AccT{0, 0, 0, 0};
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int c = 0; c < HC; ++c) acc[a][c] = AccT{0, 0, 0, 0};
 
-  for (int k0 = 0; k0 < Kp; k0 += KB) {
-    // A block: 64 rows x KB
-    for (int q = tid; q < 64 * KB / E; q += 256) {
+  V ra[NA], rb[NB];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const int q = tid + i * 256;
       const int row = q / (KB / E), cv = q % (KB / E);
-      const V v = *reinterpret_cast<const V*>(tab + (long long)row * Kp + k0 + cv * E);
-      *reinterpret_cast<V*>(As + row * AS + cv * E) = v;
+      ra[i] = *reinterpret_cast<const V*>(tab + (long long)row * Kp + k0 + cv * E);
     }
-    // B blocks: 2 parities x KB rows x BN columns
-    for (int q = tid; q < 2 * KB * BN / E; q += 256) {
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int q = tid + i * 256;
       const int par = q / (KB * BN / E);
       const int rem = q - par * (KB * BN / E);
       const int row = rem / (BN / E), cv = rem % (BN / E);
-      const V v = *reinterpret_cast<const V*>(wsm + par * plane + (long long)(k0 + row) * Cp + c0 + cv * E);
-      *reinterpret_cast<V*>(Bs + (par * KB + row) * BS + cv * E) = v;
+      rb[i] = *reinterpret_cast<const V*>(wsm + par * plane + (long long)(k0 + row) * Cp + cv * E);
     }
-    __syncthreads();
-    if (active) {
-      const T* Ap = As + arow * AS + lg * KQ;       // k = lg*KQ + kk
-      const T* Bp = Bs + (p * KB + lg * KQ) * BS + li;
+  };
+  auto lstore = [&]() {
 #pragma unroll
-      for (int kk = 0; kk < KQ; ++kk) {
-        const T a = Ap[kk];
+    for (int i = 0; i < NA; ++i) {
+      const int q = tid + i * 256;
+      const int row = q / (KB / E), cv = q % (KB / E);
+      *reinterpret_cast<V*>(As + row * AS + cv * E) = ra[i];
+    }
 #pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) acc[cb] = mfma16(a, Bp[kk * BS + cb * 16], acc[cb]);
+    for (int i = 0; i < NB; ++i) {
+      const int q = tid + i * 256;
+      const int par = q / (KB * BN / E);
+      const int rem = q - par * (KB * BN / E);
+      const int row = rem / (BN / E), cv = rem % (BN / E);
+      lds_store8<T>(Bs + (par * KB + row) * BS + cv * E, rb[i]);
+    }
+  };
+
+  const int nkb = Kp / KB;
+  gload(0);
+  lstore();
+  __syncthreads();
+  for (int kb = 0; kb < nkb; ++kb) {
+    if (kb + 1 < nkb) gload((kb + 1) * KB);
+    // operands of this wave: rows 2*(16*rb2 + li) + p, k = lg*KQ + kk
+    T av[2][KQ];
+#pragma unroll
+    for (int rb2 = 0; rb2 < 2; ++rb2) {
+      const T* Ap = As + (2 * (16 * rb2 + li) + p) * AS + lg * KQ;
+#pragma unroll
+      for (int v = 0; v < KQ / E; ++v) {
+        const V x = *reinterpret_cast<const V*>(Ap + v * E);
+#pragma unroll
+        for (int e = 0; e < E; ++e) av[rb2][v * E + e] = x[e];
+      }
+    }
+    const T* Bp = Bs + (p * KB + lg * KQ) * BS + li;
+#pragma unroll
+    for (int kk = 0; kk < KQ; ++kk) {
+#pragma unroll
+      for (int c = 0; c < HC; ++c) {
+        const int cb = ch * HC + c;
+        if (cb < NCB) {
+          const T b = Bp[kk * BS + cb * 16];
+          if (act[0]) acc[0][c] = mfma16(av[0][kk], b, acc[0][c]);
+          if (act[1]) acc[1][c] = mfma16(av[1][kk], b, acc[1][c]);
+        }
       }
     }
     __syncthreads();
+    if (kb + 1 < nkb) {
+      lstore();
+      __syncthreads();
+    }
   }
 
   // stage the 64 x BN tile in LDS, then write spec rows contiguously
   T* Cs = As;  // [64][BN]
 #pragma unroll
-  for (int cb = 0; cb < NCB; ++cb)
+  for (int rb2 = 0; rb2 < 2; ++rb2)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int rl = 32 * h + 2 * out_row<T>(lg, i) + p;
-      Cs[rl * BN + cb * 16 + li] = acc[cb][i];
+    for (int c = 0; c < HC; ++c) {
+      const int cb = ch * HC + c;
+      if (cb < NCB) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int rl = 2 * (16 * rb2 + out_row<T>(lg, i)) + p;
+          Cs[rl * BN + cb * 16 + li] = acc[rb2][c][i];
+        }
+      }
     }
   __syncthreads();
   T* spec = static_cast<T*>(g.spec_out) + L.spec_off;
@@ -173,9 +242,12 @@ __global__ __launch_bounds__(256) void k_legendre_analysis(const GemmArgs g) {
 
 // ---------------------------------------------------------------------------
 // synthesis: S_p[j][c] = sum_{r of parity p} P[r][j] * a[r][c]
-// tile = 32 rows j x BN columns, both parities.
-// wave w: output parity p = w & 1, rows j = 32 jb + 16 h + (0..15), h = w >> 1.
-// contraction over natural rows r = n - m in blocks of 32 (16 per parity).
+// tile = 64 rows j x BN columns, both parities.  The table is read from its
+// synthesis copy, laid out per (m, 64-row j block, 32-row r block) as
+// [parity][64 j][16 r] so that each block is one contiguous 2048-element
+// run that lands in LDS unchanged.
+// wave w: output parity p = w & 1, column half ch = w >> 1; 4 row blocks of
+// 16 j times HC column blocks.
 // ---------------------------------------------------------------------------
 template <typename T, int NCB>
 __global__ __launch_bounds__(256) void k_legendre_synthesis(const GemmArgs g) {
@@ -183,84 +255,146 @@ __global__ __launch_bounds__(256) void k_legendre_synthesis(const GemmArgs g) {
   typedef typename V16<T>::type V;
   constexpr int E = 16 / (int)sizeof(T);
   constexpr int BN = 16 * NCB;
-  constexpr int KR = 32;            // natural rows per block
-  constexpr int KH = KR / 2;        // rows per parity
-  constexpr int AS = KH + E;        // LDS stride of the transposed table
-  constexpr int BS = BN + E;
+  constexpr int HC = (NCB + 1) / 2;
+  constexpr int KH = 16;                          // table rows per parity and block
+  constexpr int AS = KH + E;                      // odd number of 16-byte units
+  constexpr int BS = sizeof(T) == 4 ? BN + 4 : BN + 2;
+  constexpr int NA = 2 * 64 * KH / E / 256;       // table vectors per thread
+  constexpr int NB = (BN / 2) * (KH) / 256 > 0 ? (BN / 2) * KH / 256 : 1;  // row-pair chunks
 
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* At = reinterpret_cast<T*>(smem_raw);     // [2][32 j][AS]
-  T* Bs = At + 2 * 32 * AS;                   // [2][KH][BS]
+  T* At = reinterpret_cast<T*>(smem_raw);     // [2][64 j][AS]
+  T* Bs = At + 2 * 64 * AS;                   // [2][KH][BS]
 
   const Tile t = g.tiles[blockIdx.x];
   if (t.level < 0) return;
   const LevelDesc& L = g.lev[t.level];
   const int N = L.N, m = t.m;
   const int nm = N - m + 1;
-  const int j0 = t.rb * 32;
+  const int nkb = (nm + 31) / 32;
+  const int jb = t.rb;
   const int c0 = t.cb * BN;
-  const int Kp = L.Kp;
   const long long Cp = L.Cp;
-  const T* tab = static_cast<const T*>(g.table) + g.tab_off[L.m_base + m];
+  const T* tab = static_cast<const T*>(g.table) + g.tab_off[L.m_base + m] + (long long)jb * nkb * 2048;
   const T* spec = static_cast<const T*>(g.spec_in) + L.spec_off;
   const long long nc = (long long)(N + 1) * (N + 2) / 2;
   const long long sbase = spec_idx(N, m, m);
 
   const int tid = threadIdx.x;
   const int w = tid >> 6, lane = tid & 63;
-  const int p = w & 1, h = w >> 1;
+  const int p = w & 1, ch = w >> 1;
   const int li = lane & 15, lg = lane >> 4;
 
-  AccT acc[NCB];
+  AccT acc[4][HC];
 #pragma unroll
-  for (int cb = 0; cb < NCB; ++cb) acc[cb] = AccT{0, 0, 0, 0};
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < HC; ++c) acc[a][c] = AccT{0, 0, 0, 0};
 
-  for (int rb0 = 0; rb0 < nm; rb0 += KR) {
-    // table block rows rb0..rb0+31 (padded rows are zero), columns j0..j0+31,
-    // stored transposed and split by parity: At[r&1][j][r>>1]
-    for (int q = tid; q < KR * 32 / E; q += 256) {
-      const int r = q / (32 / E), jv = q % (32 / E);
-      const V v = *reinterpret_cast<const V*>(tab + (long long)(rb0 + r) * Kp + j0 + jv * E);
+  V ra[NA];
+  T rs[NB][4];  // two consecutive rows (re, im) of one field
+  auto gload = [&](int kb) {
+    const T* blk = tab + (long long)kb * 2048;
 #pragma unroll
-      for (int e = 0; e < E; ++e) At[((r & 1) * 32 + jv * E + e) * AS + (r >> 1)] = v[e];
+    for (int i = 0; i < NA; ++i) {
+      const int q = tid + i * 256;
+      ra[i] = *reinterpret_cast<const V*>(blk + q * E);
     }
-    // spectra rows rb0..rb0+31, columns c0..c0+BN: pairs (re, im) of field f
-    for (int q = tid; q < KR * (BN / 2); q += 256) {
-      const int fl = q / KR, r = q % KR;
+    const int rb0 = kb * 32;
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int q = tid + i * 256;
+      const int fl = q / KH, rp = q % KH;
       const int f = (c0 >> 1) + fl;
-      T re = (T)0, im = (T)0;
-      if (rb0 + r < nm && f < L.F) {
-        const T* s = spec + ((long long)f * nc + sbase + rb0 + r) * 2;
-        re = s[0];
-        im = s[1];
-      }
-      T* d = Bs + ((r & 1) * KH + (r >> 1)) * BS + 2 * fl;
-      d[0] = re;
-      d[1] = im;
-    }
-    __syncthreads();
-    {
-      const T* Ap = At + (p * 32 + 16 * h + li) * AS + lg * 4;   // k = lg*4 + kk
-      const T* Bp = Bs + (p * KH + lg * 4) * BS + li;
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        const T a = Ap[kk];
-#pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) acc[cb] = mfma16(a, Bp[kk * BS + cb * 16], acc[cb]);
+      const int r = rb0 + 2 * rp;
+      rs[i][0] = rs[i][1] = rs[i][2] = rs[i][3] = (T)0;
+      if (fl < BN / 2 && f < L.F) {
+        const T* s = spec + ((long long)f * nc + sbase + r) * 2;
+        if (r < nm) {
+          rs[i][0] = s[0];
+          rs[i][1] = s[1];
+        }
+        if (r + 1 < nm) {
+          rs[i][2] = s[2];
+          rs[i][3] = s[3];
+        }
       }
     }
+  };
+  auto lstore = [&]() {
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const int q = tid + i * 256;
+      const int e0 = q * E;                       // element offset in the block
+      const int pj = e0 / KH, kv = e0 % KH;       // (parity*64 + j), k
+      *reinterpret_cast<V*>(At + pj * AS + kv) = ra[i];
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int q = tid + i * 256;
+      const int fl = q / KH, rp = q % KH;
+      if (fl < BN / 2) {
+        T* d0 = Bs + rp * BS + 2 * fl;
+        T* d1 = Bs + (KH + rp) * BS + 2 * fl;
+        d0[0] = rs[i][0];
+        d0[1] = rs[i][1];
+        d1[0] = rs[i][2];
+        d1[1] = rs[i][3];
+      }
+    }
+  };
+
+  gload(0);
+  lstore();
+  __syncthreads();
+  for (int kb = 0; kb < nkb; ++kb) {
+    if (kb + 1 < nkb) gload(kb + 1);
+    T av[4][4];
+#pragma unroll
+    for (int jr = 0; jr < 4; ++jr) {
+      const T* Ap = At + (p * 64 + 16 * jr + li) * AS + lg * 4;
+#pragma unroll
+      for (int v = 0; v < 4 / E + (E > 4 ? 1 : 0); ++v) {
+        const V x = *reinterpret_cast<const V*>(Ap + v * E);
+#pragma unroll
+        for (int e = 0; e < E && v * E + e < 4; ++e) av[jr][v * E + e] = x[e];
+      }
+    }
+    const T* Bp = Bs + (p * KH + lg * 4) * BS + li;
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+#pragma unroll
+      for (int c = 0; c < HC; ++c) {
+        const int cb = ch * HC + c;
+        if (cb < NCB) {
+          const T b = Bp[kk * BS + cb * 16];
+#pragma unroll
+          for (int jr = 0; jr < 4; ++jr) acc[jr][c] = mfma16(av[jr][kk], b, acc[jr][c]);
+        }
+      }
+    }
     __syncthreads();
+    if (kb + 1 < nkb) {
+      lstore();
+      __syncthreads();
+    }
   }
 
-  T* ws = static_cast<T*>(g.ws) + L.ws_off + (2LL * m + p) * Kp * Cp;
+  const long long plane = (long long)L.Kp * Cp;
+  T* ws = static_cast<T*>(g.ws) + L.ws_off + (2LL * m + p) * plane;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int j = j0 + 16 * h + out_row<T>(lg, i);
-    if (j < L.Jh) {
+  for (int jr = 0; jr < 4; ++jr)
 #pragma unroll
-      for (int cb = 0; cb < NCB; ++cb) ws[(long long)j * Cp + c0 + cb * 16 + li] = acc[cb][i];
+    for (int i = 0; i < 4; ++i) {
+      const int j = jb * 64 + 16 * jr + out_row<T>(lg, i);
+      if (j < L.Jh) {
+#pragma unroll
+        for (int c = 0; c < HC; ++c) {
+          const int cb = ch * HC + c;
+          if (cb < NCB) ws[(long long)j * Cp + c0 + cb * 16 + li] = acc[jr][c][i];
+        }
+      }
     }
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -271,7 +405,7 @@ static size_t lds_analysis(int ncb) {
   const int E = 16 / (int)sizeof(T);
   const int KB = sizeof(T) == 4 ? 32 : 16;
   const int BN = 16 * ncb;
-  size_t stage = (size_t)(64 * (KB + E) + 2 * KB * (BN + E)) * sizeof(T);
+  size_t stage = (size_t)(64 * (KB + E) + 2 * KB * (BN + 2)) * sizeof(T);
   size_t cst = (size_t)64 * BN * sizeof(T);
   return stage > cst ? stage : cst;
 }
@@ -280,7 +414,8 @@ template <typename T>
 static size_t lds_synthesis(int ncb) {
   const int E = 16 / (int)sizeof(T);
   const int BN = 16 * ncb;
-  return (size_t)(2 * 32 * (16 + E) + 2 * 16 * (BN + E)) * sizeof(T);
+  const int BS = sizeof(T) == 4 ? BN + 4 : BN + 2;
+  return (size_t)(2 * 64 * (16 + E) + 2 * 16 * BS) * sizeof(T);
 }
 
 template <typename T>
