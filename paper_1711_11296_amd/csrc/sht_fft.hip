@@ -125,24 +125,37 @@ struct Dft<T, 5> {
   }
 };
 
-// One Stockham pass of radix R over the I-point sequence in LDS, in place
-// (all reads of a thread finish at a barrier before any write).
-// Ns is the product of the radices of the earlier passes.
-template <typename T, int NT, int R>
+// q = floor(j / d) for 0 <= j < 2^13 and 2 <= d <= 4096, with
+// magic = floor((2^32 - 1) / d) + 1 (exhaustively checked over that range).
+__device__ __forceinline__ int fastdiv(int j, unsigned magic) {
+  return (int)__umulhi((unsigned)j, magic);
+}
+
+// One Stockham pass of radix R over FC sequences of length I that lie one
+// after the other in LDS, in place: every thread first loads and transforms
+// all its butterflies, then (after a barrier) stores them.  Ns is the product
+// of the radices of the earlier passes.  Butterfly u covers sequence
+// f = u / (I/R) (FC is 1 or 2) and position j = u mod (I/R).
+template <typename T, int NT, int FC, int MAXI, int R>
 __device__ __forceinline__ void stockham_pass(cx<T>* buf, int I, int Ns,
                                               const cx<T>* __restrict__ tw) {
-  constexpr int BPT = (SHT_MAX_I / R + NT - 1) / NT;
+  constexpr int BPT = (FC * MAXI / R + NT - 1) / NT;
   const int nb = I / R;
+  const int tot = FC * nb;
   const int twstep = I / (Ns * R);
+  const unsigned magic = Ns > 1 ? 0xFFFFFFFFu / (unsigned)Ns + 1u : 0u;
   cx<T> v[BPT][R];
 #pragma unroll
   for (int b = 0; b < BPT; ++b) {
-    const int j = threadIdx.x + b * NT;
-    if (j < nb) {
-      const int k = j % Ns;
+    const int u = threadIdx.x + b * NT;
+    if (u < tot) {
+      const int f = (FC == 2 && u >= nb) ? 1 : 0;
+      const int j = u - f * nb;
+      const cx<T>* src = buf + f * I + j;
 #pragma unroll
-      for (int t = 0; t < R; ++t) v[b][t] = buf[j + t * nb];
+      for (int t = 0; t < R; ++t) v[b][t] = src[t * nb];
       if (Ns > 1) {
+        const int k = j - fastdiv(j, magic) * Ns;
 #pragma unroll
         for (int t = 1; t < R; ++t) v[b][t] = cmul(v[b][t], tw[t * k * twstep]);
       }
@@ -152,33 +165,38 @@ __device__ __forceinline__ void stockham_pass(cx<T>* buf, int I, int Ns,
   __syncthreads();
 #pragma unroll
   for (int b = 0; b < BPT; ++b) {
-    const int j = threadIdx.x + b * NT;
-    if (j < nb) {
-      const int k = j % Ns;
-      const int base = (j / Ns) * Ns * R + k;
+    const int u = threadIdx.x + b * NT;
+    if (u < tot) {
+      const int f = (FC == 2 && u >= nb) ? 1 : 0;
+      const int j = u - f * nb;
+      int q = j, k = 0;
+      if (Ns > 1) {
+        q = fastdiv(j, magic);
+        k = j - q * Ns;
+      }
+      cx<T>* dst = buf + f * I + q * Ns * R + k;
 #pragma unroll
-      for (int t = 0; t < R; ++t) buf[base + t * Ns] = v[b][t];
+      for (int t = 0; t < R; ++t) dst[t * Ns] = v[b][t];
     }
   }
   __syncthreads();
 }
 
-// Forward complex FFT (sign -) of the I values in buf, natural order in and
-// out.  Every thread of the block must call it.
-template <typename T, int NT>
-__device__ void fft_lds(cx<T>* buf, const LevelDesc& L) {
-  const cx<T>* tw = (const cx<T>*)L.tw;
+// Forward complex FFTs (sign -) of the FC sequences in buf, natural order in
+// and out.  Every thread of the block must call it.
+template <typename T, int NT, int FC, int MAXI>
+__device__ void fft_lds(cx<T>* buf, const LevelDesc& L, const cx<T>* tw) {
   int Ns = 1;
   for (int p = 0; p < L.nrad; ++p) {
     const int R = L.rad[p];
     if (R == 4)
-      stockham_pass<T, NT, 4>(buf, L.I, Ns, tw);
+      stockham_pass<T, NT, FC, MAXI, 4>(buf, L.I, Ns, tw);
     else if (R == 2)
-      stockham_pass<T, NT, 2>(buf, L.I, Ns, tw);
+      stockham_pass<T, NT, FC, MAXI, 2>(buf, L.I, Ns, tw);
     else if (R == 3)
-      stockham_pass<T, NT, 3>(buf, L.I, Ns, tw);
+      stockham_pass<T, NT, FC, MAXI, 3>(buf, L.I, Ns, tw);
     else
-      stockham_pass<T, NT, 5>(buf, L.I, Ns, tw);
+      stockham_pass<T, NT, FC, MAXI, 5>(buf, L.I, Ns, tw);
     Ns *= R;
   }
 }
@@ -240,11 +258,13 @@ __device__ __forceinline__ void load_run(const T* src, cx<T> (&v)[FB]) {
 
 // ---------------------------------------------------------------------------
 // analysis: grid [F][J][I] -> workspace S/A
+// FB fields per workgroup, FC of them transformed together; the rows of the
+// next FC fields are prefetched into registers while the current ones are
+// transformed.  Twiddles are staged in LDS when TWL is set.
 // ---------------------------------------------------------------------------
-template <typename T, int NT, int FB, int MS>
+template <typename T, int NT, int FB, int FC, int MS, int MAXI, bool TWL>
 __global__ __launch_bounds__(NT) void k_zonal_analysis(const FftArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
   const int item = blockIdx.x;
   if (item >= a.nitems) return;
   const int l = level_of(a, item);
@@ -257,55 +277,75 @@ __global__ __launch_bounds__(NT) void k_zonal_analysis(const FftArgs a) {
   const int js = J - 1 - jp;
   const T* grid = static_cast<const T*>(a.src) + L.grid_off;
   T* ws = static_cast<T*>(a.dst) + L.ws_off;
+  cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+  const cx<T>* tw = static_cast<const cx<T>*>(L.tw);
+  if (TWL) {
+    cx<T>* twl = buf + FC * I;
+    for (int i = threadIdx.x; i < I; i += NT) twl[i] = tw[i];
+    tw = twl;
+  }
 
   T rscale = (T)1;
   if (a.use_w) rscale = (T)L.wrow[jp];
   if (a.use_inv_I) rscale = (T)((double)rscale / (double)I);
   const T msc = (T)a.mscale;
 
-  cx<T> stS[MS][FB], stA[MS][FB];
+  constexpr int LPT = (MAXI + NT - 1) / NT;
+  T pn[FC][LPT], ps[FC][LPT];
+  auto load_rows = [&](int rd) {
 #pragma unroll
-  for (int s = 0; s < MS; ++s)
+    for (int fc = 0; fc < FC; ++fc) {
+      const int f = fb * FB + rd * FC + fc;
+      const bool valid = f < L.F;
+      const T* rn = grid + ((long long)f * J + jp) * I;
+      const T* rs = grid + ((long long)f * J + js) * I;
 #pragma unroll
-    for (int q = 0; q < FB; ++q) stS[s][q] = stA[s][q] = cx<T>{(T)0, (T)0};
-
-  for (int fi = 0; fi < FB; ++fi) {
-    const int f = fb * FB + fi;
-    const bool valid = f < L.F;
-    const T* rn = grid + ((long long)f * J + jp) * I;
-    const T* rs = grid + ((long long)f * J + js) * I;
-    for (int i = threadIdx.x; i < I; i += NT) {
-      T xn = valid ? rn[i] : (T)0;
-      T xs = (valid && !eq) ? rs[i] : (T)0;
-      buf[i] = cx<T>{xn, xs};
+      for (int e = 0; e < LPT; ++e) {
+        const int i = threadIdx.x + e * NT;
+        pn[fc][e] = (valid && i < I) ? rn[i] : (T)0;
+        ps[fc][e] = (valid && !eq && i < I) ? rs[i] : (T)0;
+      }
     }
+  };
+
+  cx<T> stS[MS][FB], stA[MS][FB];
+  load_rows(0);
+#pragma unroll
+  for (int rd = 0; rd < FB / FC; ++rd) {
+#pragma unroll
+    for (int fc = 0; fc < FC; ++fc)
+#pragma unroll
+      for (int e = 0; e < LPT; ++e) {
+        const int i = threadIdx.x + e * NT;
+        if (i < I) buf[fc * I + i] = cx<T>{pn[fc][e], ps[fc][e]};
+      }
     __syncthreads();
-    fft_lds<T, NT>(buf, L);
+    if (rd + 1 < FB / FC) load_rows(rd + 1);
+    fft_lds<T, NT, FC, MAXI>(buf, L, tw);
 #pragma unroll
     for (int s = 0; s < MS; ++s) {
       const int m = threadIdx.x + s * NT;
-      if (m <= N) {
-        const cx<T> P = buf[m];
-        cx<T> Q = buf[m == 0 ? 0 : I - m];
-        Q.y = -Q.y;  // conj Z^{I-m}
-        const T h = (T)0.5;
-        const cx<T> Xn = {h * (P.x + Q.x), h * (P.y + Q.y)};
-        const cx<T> Xs = {h * (P.y - Q.y), -h * (P.x - Q.x)};
-        const T sc = m == 0 ? rscale : rscale * msc;
-        cx<T> S = {sc * (Xn.x + Xs.x), sc * (Xn.y + Xs.y)};
-        cx<T> A = {sc * (Xn.x - Xs.x), sc * (Xn.y - Xs.y)};
-        if (m == 0) {
-          S.y = (T)0;
-          A.y = (T)0;
-        }
-        if (eq) A = cx<T>{(T)0, (T)0};
 #pragma unroll
-        for (int q = 0; q < FB; ++q) {
-          if (q == fi) {
-            stS[s][q] = S;
-            stA[s][q] = A;
+      for (int fc = 0; fc < FC; ++fc) {
+        cx<T> S = {(T)0, (T)0}, A = {(T)0, (T)0};
+        if (m <= N) {
+          const cx<T> P = buf[fc * I + m];
+          cx<T> Q = buf[fc * I + (m == 0 ? 0 : I - m)];
+          Q.y = -Q.y;  // conj Z^{I-m}
+          const T h = (T)0.5;
+          const cx<T> Xn = {h * (P.x + Q.x), h * (P.y + Q.y)};
+          const cx<T> Xs = {h * (P.y - Q.y), -h * (P.x - Q.x)};
+          const T sc = m == 0 ? rscale : rscale * msc;
+          S = cx<T>{sc * (Xn.x + Xs.x), sc * (Xn.y + Xs.y)};
+          A = cx<T>{sc * (Xn.x - Xs.x), sc * (Xn.y - Xs.y)};
+          if (m == 0) {
+            S.y = (T)0;
+            A.y = (T)0;
           }
+          if (eq) A = cx<T>{(T)0, (T)0};
         }
+        stS[s][rd * FC + fc] = S;
+        stA[s][rd * FC + fc] = A;
       }
     }
     __syncthreads();
@@ -327,10 +367,9 @@ __global__ __launch_bounds__(NT) void k_zonal_analysis(const FftArgs a) {
 // ---------------------------------------------------------------------------
 // synthesis: workspace S/A -> grid [F][J][I]
 // ---------------------------------------------------------------------------
-template <typename T, int NT, int FB, int MS>
+template <typename T, int NT, int FB, int FC, int MS, int MAXI, bool TWL>
 __global__ __launch_bounds__(NT) void k_zonal_synthesis(const FftArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
   const int item = blockIdx.x;
   if (item >= a.nitems) return;
   const int l = level_of(a, item);
@@ -343,6 +382,13 @@ __global__ __launch_bounds__(NT) void k_zonal_synthesis(const FftArgs a) {
   const int js = J - 1 - jp;
   const T* ws = static_cast<const T*>(a.src) + L.ws_off;
   T* grid = static_cast<T*>(a.dst) + L.grid_off;
+  cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+  const cx<T>* tw = static_cast<const cx<T>*>(L.tw);
+  if (TWL) {
+    cx<T>* twl = buf + FC * I;
+    for (int i = threadIdx.x; i < I; i += NT) twl[i] = tw[i];
+    tw = twl;
+  }
 
   T rscale = (T)1;
   if (a.use_w) rscale = (T)L.wrow[jp];
@@ -365,45 +411,47 @@ __global__ __launch_bounds__(NT) void k_zonal_synthesis(const FftArgs a) {
     }
   }
 
-  for (int fi = 0; fi < FB; ++fi) {
-    const int f = fb * FB + fi;
-    // zero the bins no thread fills: N < i < I-N
-    for (int i = N + 1 + threadIdx.x; i < I - N; i += NT) buf[i] = cx<T>{(T)0, (T)0};
 #pragma unroll
-    for (int s = 0; s < MS; ++s) {
-      const int m = threadIdx.x + s * NT;
-      if (m <= N) {
-        cx<T> S = stS[s][0], A = stA[s][0];
+  for (int rd = 0; rd < FB / FC; ++rd) {
 #pragma unroll
-        for (int q = 1; q < FB; ++q) {
-          if (q == fi) {
-            S = stS[s][q];
-            A = stA[s][q];
+    for (int fc = 0; fc < FC; ++fc) {
+      cx<T>* bf = buf + fc * I;
+      // zero the bins no thread fills: N < i < I-N
+      for (int i = N + 1 + threadIdx.x; i < I - N; i += NT) bf[i] = cx<T>{(T)0, (T)0};
+#pragma unroll
+      for (int s = 0; s < MS; ++s) {
+        const int m = threadIdx.x + s * NT;
+        if (m <= N) {
+          const cx<T> S = stS[s][rd * FC + fc], A = stA[s][rd * FC + fc];
+          const T sc = m == 0 ? (T)1 : msc;
+          cx<T> Xn = {sc * (S.x + A.x), sc * (S.y + A.y)};
+          cx<T> Xs = {sc * (S.x - A.x), sc * (S.y - A.y)};
+          if (m == 0) {
+            Xn.y = (T)0;
+            Xs.y = (T)0;
           }
+          // the buffer holds conj(Z): the forward FFT of conj(Z) is the
+          // conjugate of the inverse transform of Z, with
+          // Z^m = Xn + i Xs and Z^{I-m} = conj(Xn) + i conj(Xs)
+          bf[m] = cx<T>{Xn.x - Xs.y, -(Xn.y + Xs.x)};
+          if (m > 0) bf[I - m] = cx<T>{Xn.x + Xs.y, Xn.y - Xs.x};
         }
-        const T sc = m == 0 ? (T)1 : msc;
-        cx<T> Xn = {sc * (S.x + A.x), sc * (S.y + A.y)};
-        cx<T> Xs = {sc * (S.x - A.x), sc * (S.y - A.y)};
-        if (m == 0) {
-          Xn.y = (T)0;
-          Xs.y = (T)0;
-        }
-        // buffer holds conj(Z): the forward FFT of conj(Z) is conj of the
-        // inverse transform of Z.
-        // Z^m = Xn + i Xs ; Z^{I-m} = conj(Xn) + i conj(Xs)
-        buf[m] = cx<T>{Xn.x - Xs.y, -(Xn.y + Xs.x)};
-        if (m > 0) buf[I - m] = cx<T>{Xn.x + Xs.y, Xn.y - Xs.x};
       }
     }
     __syncthreads();
-    fft_lds<T, NT>(buf, L);
-    if (f < L.F) {
-      T* rn = grid + ((long long)f * J + jp) * I;
-      T* rs = grid + ((long long)f * J + js) * I;
-      for (int i = threadIdx.x; i < I; i += NT) {
-        const cx<T> y = buf[i];
-        rn[i] = rscale * y.x;
-        if (!eq) rs[i] = -rscale * y.y;
+    fft_lds<T, NT, FC, MAXI>(buf, L, tw);
+#pragma unroll
+    for (int fc = 0; fc < FC; ++fc) {
+      const int f = fb * FB + rd * FC + fc;
+      if (f < L.F) {
+        const cx<T>* bf = buf + fc * I;
+        T* rn = grid + ((long long)f * J + jp) * I;
+        T* rs = grid + ((long long)f * J + js) * I;
+        for (int i = threadIdx.x; i < I; i += NT) {
+          const cx<T> y = bf[i];
+          rn[i] = rscale * y.x;
+          if (!eq) rs[i] = -rscale * y.y;
+        }
       }
     }
     __syncthreads();
@@ -413,44 +461,69 @@ __global__ __launch_bounds__(NT) void k_zonal_synthesis(const FftArgs a) {
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-template <typename T, int FB>
-static hipError_t launch_zonal_t(bool analysis, const FftArgs& a, int maxN,
-                                 hipStream_t st) {
+// LDS per workgroup on gfx950 is 160 KiB; above 64 KiB a kernel has to opt in.
+constexpr size_t kMaxLds = 160 * 1024;
+
+template <auto Kernel>
+static void lds_optin(size_t bytes) {
+  static size_t done = 0;  // one flag per kernel instantiation
+  if (bytes > 65536 && bytes > done) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(Kernel),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    done = bytes;
+  }
+}
+
+template <typename T, int NT, int FB, int FC, int MS, int MAXI>
+static hipError_t launch_cfg(bool analysis, const FftArgs& a, int maxI, hipStream_t st) {
+  const size_t buf = (size_t)FC * maxI * sizeof(cx<T>);
+  const size_t twb = (size_t)maxI * sizeof(cx<T>);
+  const bool twl = buf + twb <= kMaxLds;
+  const size_t lds = buf + (twl ? twb : 0);
+  const dim3 grid(a.nitems), block(NT);
+  if (analysis) {
+    if (twl) {
+      lds_optin<k_zonal_analysis<T, NT, FB, FC, MS, MAXI, true>>(lds);
+      hipLaunchKernelGGL((k_zonal_analysis<T, NT, FB, FC, MS, MAXI, true>), grid, block, lds, st, a);
+    } else {
+      lds_optin<k_zonal_analysis<T, NT, FB, FC, MS, MAXI, false>>(lds);
+      hipLaunchKernelGGL((k_zonal_analysis<T, NT, FB, FC, MS, MAXI, false>), grid, block, lds, st, a);
+    }
+  } else {
+    if (twl) {
+      lds_optin<k_zonal_synthesis<T, NT, FB, FC, MS, MAXI, true>>(lds);
+      hipLaunchKernelGGL((k_zonal_synthesis<T, NT, FB, FC, MS, MAXI, true>), grid, block, lds, st, a);
+    } else {
+      lds_optin<k_zonal_synthesis<T, NT, FB, FC, MS, MAXI, false>>(lds);
+      hipLaunchKernelGGL((k_zonal_synthesis<T, NT, FB, FC, MS, MAXI, false>), grid, block, lds, st, a);
+    }
+  }
+  return hipGetLastError();
+}
+
+template <typename T, int FB, int FC>
+static hipError_t launch_zonal_t(bool analysis, const FftArgs& a, int maxN, hipStream_t st) {
   int maxI = 0;
   for (int l = 0; l < a.nlev; ++l) maxI = a.lev[l].I > maxI ? a.lev[l].I : maxI;
-  const size_t lds = (size_t)maxI * sizeof(cx<T>);
-  const dim3 grid(a.nitems);
   const int nm = maxN + 1;
-#define SHT_ZLAUNCH(NT_, MS_)                                                   \
-  do {                                                                          \
-    if (analysis)                                                               \
-      hipLaunchKernelGGL((k_zonal_analysis<T, NT_, FB, MS_>), grid, dim3(NT_), \
-                         lds, st, a);                                           \
-    else                                                                        \
-      hipLaunchKernelGGL((k_zonal_synthesis<T, NT_, FB, MS_>), grid,           \
-                         dim3(NT_), lds, st, a);                                \
-  } while (0)
-  if (nm <= 256)
-    SHT_ZLAUNCH(256, 1);
-  else if (nm <= 512)
-    SHT_ZLAUNCH(512, 1);
-  else if (nm <= 1024)
-    SHT_ZLAUNCH(512, 2);
-  else if (nm <= 1536)
-    SHT_ZLAUNCH(512, 3);
-  else
-    SHT_ZLAUNCH(512, 4);
-#undef SHT_ZLAUNCH
-  return hipGetLastError();
+  if (maxI <= 1024 && nm <= 512) {
+    if (nm <= 256) return launch_cfg<T, 256, FB, FC, 1, 1024>(analysis, a, maxI, st);
+    return launch_cfg<T, 256, FB, FC, 2, 1024>(analysis, a, maxI, st);
+  }
+  if (maxI <= 2048 && nm <= 1024) {
+    if (nm <= 512) return launch_cfg<T, 512, FB, FC, 1, 2048>(analysis, a, maxI, st);
+    return launch_cfg<T, 512, FB, FC, 2, 2048>(analysis, a, maxI, st);
+  }
+  if (nm <= 1024) return launch_cfg<T, 1024, FB, FC, 1, 4096>(analysis, a, maxI, st);
+  return launch_cfg<T, 1024, FB, FC, 2, 4096>(analysis, a, maxI, st);
 }
 
 int zonal_fields_per_block(int form) { return form == SHT_FORM_FP64 ? 4 : 8; }
 
-int launch_zonal(int form, bool analysis, const FftArgs& a, int maxN,
-                 void* stream) {
+int launch_zonal(int form, bool analysis, const FftArgs& a, int maxN, void* stream) {
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if (form == SHT_FORM_FP64) return (int)launch_zonal_t<double, 4>(analysis, a, maxN, st);
-  return (int)launch_zonal_t<float, 8>(analysis, a, maxN, st);
+  if (form == SHT_FORM_FP64) return (int)launch_zonal_t<double, 4, 1>(analysis, a, maxN, st);
+  return (int)launch_zonal_t<float, 8, 2>(analysis, a, maxN, st);
 }
 
 }  // namespace sht
