@@ -267,6 +267,11 @@ int build_plan(int nlev, const int* Nv, const int* Jv, const int* Iv, const int*
     L.Kp = (int)roundup(L.Jh, SHT_K_PAD);
     L.Cp = (int)roundup(2LL * L.F, std::max(BN, 2 * FB));
     factor_radices(L.I, L.rad, &L.nrad);
+    for (int q = 0, ns = 1; q < L.nrad; ns *= L.rad[q], ++q) {
+      L.pns[q] = ns;
+      L.ptw[q] = L.I / (ns * L.rad[q]);
+      L.pmag[q] = ns > 1 ? 0xFFFFFFFFu / (unsigned)ns + 1u : 0u;
+    }
     L.nfb = (L.F + FB - 1) / FB;
     L.fft_item0 = (int)item;
     item += (long long)L.Jh * L.nfb;

@@ -137,13 +137,11 @@ __device__ __forceinline__ int fastdiv(int j, unsigned magic) {
 // of the radices of the earlier passes.  Butterfly u covers sequence
 // f = u / (I/R) (FC is 1 or 2) and position j = u mod (I/R).
 template <typename T, int NT, int FC, int MAXI, int R>
-__device__ __forceinline__ void stockham_pass(cx<T>* buf, int I, int Ns,
-                                              const cx<T>* __restrict__ tw) {
+__device__ __forceinline__ void stockham_pass(cx<T>* buf, int I, int Ns, int twstep,
+                                              unsigned magic, const cx<T>* __restrict__ tw) {
   constexpr int BPT = (FC * MAXI / R + NT - 1) / NT;
-  const int nb = I / R;
+  const int nb = twstep * Ns;  // I / R
   const int tot = FC * nb;
-  const int twstep = I / (Ns * R);
-  const unsigned magic = Ns > 1 ? 0xFFFFFFFFu / (unsigned)Ns + 1u : 0u;
   cx<T> v[BPT][R];
 #pragma unroll
   for (int b = 0; b < BPT; ++b) {
@@ -186,18 +184,17 @@ __device__ __forceinline__ void stockham_pass(cx<T>* buf, int I, int Ns,
 // and out.  Every thread of the block must call it.
 template <typename T, int NT, int FC, int MAXI>
 __device__ void fft_lds(cx<T>* buf, const LevelDesc& L, const cx<T>* tw) {
-  int Ns = 1;
   for (int p = 0; p < L.nrad; ++p) {
-    const int R = L.rad[p];
+    const int R = L.rad[p], Ns = L.pns[p], tws = L.ptw[p];
+    const unsigned mg = L.pmag[p];
     if (R == 4)
-      stockham_pass<T, NT, FC, MAXI, 4>(buf, L.I, Ns, tw);
+      stockham_pass<T, NT, FC, MAXI, 4>(buf, L.I, Ns, tws, mg, tw);
     else if (R == 2)
-      stockham_pass<T, NT, FC, MAXI, 2>(buf, L.I, Ns, tw);
+      stockham_pass<T, NT, FC, MAXI, 2>(buf, L.I, Ns, tws, mg, tw);
     else if (R == 3)
-      stockham_pass<T, NT, FC, MAXI, 3>(buf, L.I, Ns, tw);
+      stockham_pass<T, NT, FC, MAXI, 3>(buf, L.I, Ns, tws, mg, tw);
     else
-      stockham_pass<T, NT, FC, MAXI, 5>(buf, L.I, Ns, tw);
-    Ns *= R;
+      stockham_pass<T, NT, FC, MAXI, 5>(buf, L.I, Ns, tws, mg, tw);
   }
 }
 

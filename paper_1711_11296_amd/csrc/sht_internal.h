@@ -8,7 +8,7 @@
 #include "../../include/sht.h"
 
 #define SHT_MAX_LEVELS 8
-#define SHT_MAX_RADICES 16
+#define SHT_MAX_RADICES 12
 #define SHT_MAX_I 4096
 
 // Table rows of one m are padded to a multiple of this (forward tile height).
@@ -38,7 +38,10 @@ struct LevelDesc {
   int Kp;      // Jh padded to SHT_K_PAD
   int Cp;      // workspace row length (columns = 2F padded)
   int nrad;
-  int rad[SHT_MAX_RADICES];
+  int rad[SHT_MAX_RADICES];   // radix of each Stockham pass
+  int pns[SHT_MAX_RADICES];   // product of the radices of the earlier passes
+  int ptw[SHT_MAX_RADICES];   // twiddle index stride I / (pns * rad)
+  unsigned pmag[SHT_MAX_RADICES];  // floor((2^32-1)/pns) + 1 (0 when pns == 1)
   int fft_item0;   // first FFT work item of this level
   int nfb;         // field blocks of the FFT kernels
   int m_base;      // index of (level, m=0) in the per-m offset arrays

@@ -108,7 +108,7 @@ __global__ __launch_bounds__(256) void k_legendre_analysis(const GemmArgs g) {
   constexpr int NB = 2 * KB * BN / E / 256;        // B vectors per thread
 
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* As = reinterpret_cast<T*>(smem_raw);          // [64][AS]
+  T* As = reinterpret_cast<T*>(smem_raw);          // [2 parity][32][AS]
   T* Bs = As + 64 * AS;                            // [2][KB][BS]
 
   const Tile t = g.tiles[blockIdx.x];
@@ -160,7 +160,7 @@ __global__ __launch_bounds__(256) void k_legendre_analysis(const GemmArgs g) {
     for (int i = 0; i < NA; ++i) {
       const int q = tid + i * 256;
       const int row = q / (KB / E), cv = q % (KB / E);
-      *reinterpret_cast<V*>(As + row * AS + cv * E) = ra[i];
+      *reinterpret_cast<V*>(As + ((row & 1) * 32 + (row >> 1)) * AS + cv * E) = ra[i];
     }
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
@@ -182,7 +182,7 @@ __global__ __launch_bounds__(256) void k_legendre_analysis(const GemmArgs g) {
     T av[2][KQ];
 #pragma unroll
     for (int rb2 = 0; rb2 < 2; ++rb2) {
-      const T* Ap = As + (2 * (16 * rb2 + li) + p) * AS + lg * KQ;
+      const T* Ap = As + (p * 32 + 16 * rb2 + li) * AS + lg * KQ;
 #pragma unroll
       for (int v = 0; v < KQ / E; ++v) {
         const V x = *reinterpret_cast<const V*>(Ap + v * E);
@@ -211,7 +211,8 @@ __global__ __launch_bounds__(256) void k_legendre_analysis(const GemmArgs g) {
   }
 
   // stage the 64 x BN tile in LDS, then write spec rows contiguously
-  T* Cs = As;  // [64][BN]
+  constexpr int CS = BN + 1;
+  T* Cs = As;  // [64][CS]
 #pragma unroll
   for (int rb2 = 0; rb2 < 2; ++rb2)
 #pragma unroll
@@ -221,7 +222,7 @@ __global__ __launch_bounds__(256) void k_legendre_analysis(const GemmArgs g) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int rl = 2 * (16 * rb2 + out_row<T>(lg, i)) + p;
-          Cs[rl * BN + cb * 16 + li] = acc[rb2][c][i];
+          Cs[rl * CS + cb * 16 + li] = acc[rb2][c][i];
         }
       }
     }
@@ -234,8 +235,8 @@ __global__ __launch_bounds__(256) void k_legendre_analysis(const GemmArgs g) {
     const int f = (c0 >> 1) + fl;
     if (r0 + rl < nm && f < L.F) {
       T* d = spec + ((long long)f * nc + base + rl) * 2;
-      d[0] = Cs[rl * BN + 2 * fl];
-      d[1] = Cs[rl * BN + 2 * fl + 1];
+      d[0] = Cs[rl * CS + 2 * fl];
+      d[1] = Cs[rl * CS + 2 * fl + 1];
     }
   }
 }
@@ -406,7 +407,7 @@ static size_t lds_analysis(int ncb) {
   const int KB = sizeof(T) == 4 ? 32 : 16;
   const int BN = 16 * ncb;
   size_t stage = (size_t)(64 * (KB + E) + 2 * KB * (BN + 2)) * sizeof(T);
-  size_t cst = (size_t)64 * BN * sizeof(T);
+  size_t cst = (size_t)64 * (BN + 1) * sizeof(T);
   return stage > cst ? stage : cst;
 }
 
@@ -418,18 +419,31 @@ static size_t lds_synthesis(int ncb) {
   return (size_t)(2 * 64 * (16 + E) + 2 * 16 * BS) * sizeof(T);
 }
 
+template <auto Kernel>
+static void lds_optin(size_t bytes) {
+  static size_t done = 0;  // one flag per kernel instantiation
+  if (bytes > 65536 && bytes > done) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(Kernel),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    done = bytes;
+  }
+}
+
 template <typename T>
 static hipError_t launch_legendre_t(bool analysis, const GemmArgs& g, int ncb,
                                     hipStream_t st) {
   const dim3 grid(g.ntiles), block(256);
 #define SHT_LLAUNCH(NCB_)                                                        \
   case NCB_:                                                                    \
-    if (analysis)                                                               \
+    if (analysis) {                                                             \
+      lds_optin<k_legendre_analysis<T, NCB_>>(lds_analysis<T>(NCB_));          \
       hipLaunchKernelGGL((k_legendre_analysis<T, NCB_>), grid, block,          \
                          lds_analysis<T>(NCB_), st, g);                         \
-    else                                                                        \
+    } else {                                                                    \
+      lds_optin<k_legendre_synthesis<T, NCB_>>(lds_synthesis<T>(NCB_));        \
       hipLaunchKernelGGL((k_legendre_synthesis<T, NCB_>), grid, block,         \
                          lds_synthesis<T>(NCB_), st, g);                        \
+    }                                                                           \
     break;
   switch (ncb) {
     SHT_LLAUNCH(1)
