@@ -50,7 +50,9 @@ struct sht_plan_s {
   int use_graph = 0;
   int device = 0;
   int nlev = 0;
-  int ncb = 1;
+  int ncb = 1;                 // column blocking that fixes the workspace layout
+  int ncb_fwd = 1, ncb_inv = 1;   // column blocking used by each Legendre kernel
+  int sched_fwd = 0, sched_inv = 0;
   int maxN = 0;
   int nitems = 0;
   int ntiles_fwd = 0, ntiles_inv = 0;
@@ -74,6 +76,17 @@ struct sht_plan_s {
   size_t alloc_bytes = 0;
   // optional per-stage timing with events on the caller's stream
   int profile = 0;
+  // graph replay: one captured graph per (direction, input, output)
+  hipStream_t cap_stream = nullptr;
+  struct GraphEntry {
+    int dir;
+    const void* in;
+    void* out;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+  };
+  std::vector<GraphEntry> graphs;
+  bool capturing = false;
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   std::vector<int> ev_stage;  // stage of each recorded (start, stop) pair
@@ -104,6 +117,13 @@ int dev_alloc(sht_plan_s* P, void** out, size_t bytes) {
 }
 
 void free_plan(sht_plan_s* P) {
+  for (auto& g : P->graphs) {
+    (void)hipGraphExecDestroy(g.exec);
+    (void)hipGraphDestroy(g.graph);
+  }
+  P->graphs.clear();
+  if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
+  P->cap_stream = nullptr;
   for (hipEvent_t e : P->ev_pool) (void)hipEventDestroy(e);
   P->ev_pool.clear();
   for (void* p : P->allocs) (void)hipFree(p);
@@ -181,6 +201,39 @@ std::vector<Tile> xcd_schedule(const std::vector<Tile>& tiles, const std::vector
 //  analysis copy: per m, rows r = n - m padded to SHT_ROWS_PAD, Kp columns;
 //  synthesis copy: per m, blocks (64-row j block, 32-row r block), each
 //  laid out [parity][64 j][16 r'] with r = 32 kb + 2 r' + parity.
+// Tile list of one Legendre kernel for column blocking ncb (16*ncb columns
+// per tile; the workspace row length Cp must be a multiple of it).
+// sched 0: the list in locality order (m, column block, row block) cut into
+// 8 chunks of equal cost, chunk x dealt to block ids == x (mod 8), i.e. to
+// XCD x; sched 1: the same order dealt round robin.
+std::vector<Tile> build_tiles(const sht_plan_s* P, bool analysis, int ncb, int sched) {
+  const int BN = 16 * ncb;
+  std::vector<Tile> t;
+  std::vector<double> c;
+  for (int l = 0; l < P->nlev; ++l) {
+    const LevelDesc& L = P->lev[l];
+    const int ncol = L.Cp / BN;
+    for (int m = 0; m <= L.N; ++m) {
+      const int nm = L.N - m + 1;
+      for (int cb = 0; cb < ncol; ++cb) {
+        if (analysis) {
+          for (int rb = 0; rb < (nm + 63) / 64; ++rb) {
+            t.push_back(Tile{l, m, rb, cb});
+            c.push_back((double)L.Kp * BN);
+          }
+        } else {
+          for (int jb = 0; jb < (L.Jh + 63) / 64; ++jb) {
+            t.push_back(Tile{l, m, jb, cb});
+            c.push_back(((double)roundup(nm, 32) + 16.0) * BN);
+          }
+        }
+      }
+    }
+  }
+  if (sched == 1) return t;
+  return xcd_schedule(t, c);
+}
+
 template <typename T>
 void fill_table_level(const LevelDesc& L, const double* mu, const double* sint,
                       T* dst, const long long* off_a, T* dsyn, const long long* off_s) {
@@ -219,6 +272,8 @@ void fill_table_level(const LevelDesc& L, const double* mu, const double* sint,
   }
   for (auto& th : pool) th.join();
 }
+
+int autotune(sht_plan_s* P);
 
 int build_plan(int nlev, const int* Nv, const int* Jv, const int* Iv, const int* Fv,
                const sht_options* opts, sht_plan_t* out) {
@@ -347,27 +402,9 @@ int build_plan(int nlev, const int* Nv, const int* Jv, const int* Iv, const int*
     tw_total += roundup((long long)htw[l].size(), 256);
   }
 
-  // ---- tile schedules ----
-  std::vector<Tile> tf, ti;
-  std::vector<double> cf, ci;
-  for (int l = 0; l < nlev; ++l) {
-    const LevelDesc& L = P->lev[l];
-    const int ncol = L.Cp / BN;
-    for (int m = 0; m <= L.N; ++m) {
-      const int nm = L.N - m + 1;
-      for (int cb = 0; cb < ncol; ++cb) {
-        for (int rb = 0; rb < (nm + 63) / 64; ++rb) {
-          tf.push_back(Tile{l, m, rb, cb});
-          cf.push_back((double)L.Kp);
-        }
-        for (int jb = 0; jb < (L.Jh + 63) / 64; ++jb) {
-          ti.push_back(Tile{l, m, jb, cb});
-          ci.push_back((double)roundup(nm, 32) + 16.0);
-        }
-      }
-    }
-  }
-  std::vector<Tile> sf = xcd_schedule(tf, cf), si = xcd_schedule(ti, ci);
+  // ---- tile schedules (default; the autotuner may replace them) ----
+  P->ncb_fwd = P->ncb_inv = P->ncb;
+  std::vector<Tile> sf = build_tiles(P, true, P->ncb, 0), si = build_tiles(P, false, P->ncb, 0);
   P->ntiles_fwd = (int)sf.size();
   P->ntiles_inv = (int)si.size();
 
@@ -414,6 +451,7 @@ int build_plan(int nlev, const int* Nv, const int* Jv, const int* Iv, const int*
   if (!rc) rc = hip_check(hipMemcpy(dtf, sf.data(), sf.size() * sizeof(Tile), hipMemcpyHostToDevice), "upload tiles");
   if (!rc) rc = hip_check(hipMemcpy(dti, si.data(), si.size() * sizeof(Tile), hipMemcpyHostToDevice), "upload tiles");
   if (!rc) rc = hip_check(hipDeviceSynchronize(), "plan synchronize");
+  if (!rc && o.autotune) rc = autotune(P);
   if (rc) {
     free_plan(P);
     delete P;
@@ -482,7 +520,7 @@ hipEvent_t next_event(sht_plan_s* P) {
 }
 
 void prof_mark(sht_plan_s* P, void* stream, int stage, bool start) {
-  if (!P->profile) return;
+  if (!P->profile || P->capturing) return;
   hipEvent_t e = next_event(P);
   if (!e) return;
   (void)hipEventRecord(e, static_cast<hipStream_t>(stream));
@@ -499,7 +537,7 @@ int run_analysis(sht_plan_s* P, const void* grid, void* spec, void* stream, int 
   if (e) return hip_check((hipError_t)e, "zonal analysis launch");
   GemmArgs g = gemm_args(P, true, nullptr, spec);
   prof_mark(P, stream, ST_LEG_A, true);
-  e = launch_legendre(P->form, true, g, P->ncb, stream);
+  e = launch_legendre(P->form, true, g, P->ncb_fwd, stream);
   prof_mark(P, stream, ST_LEG_A, false);
   if (e) return hip_check((hipError_t)e, "Legendre analysis launch");
   return SHT_OK;
@@ -509,7 +547,7 @@ int run_synthesis(sht_plan_s* P, const void* spec, void* grid, void* stream, int
                   double mscale) {
   GemmArgs g = gemm_args(P, false, spec, nullptr);
   prof_mark(P, stream, ST_LEG_S, true);
-  int e = launch_legendre(P->form, false, g, P->ncb, stream);
+  int e = launch_legendre(P->form, false, g, P->ncb_inv, stream);
   prof_mark(P, stream, ST_LEG_S, false);
   if (e) return hip_check((hipError_t)e, "Legendre synthesis launch");
   FftArgs a = fft_args(P, P->d_ws, grid, use_w, use_inv_I, mscale);
@@ -518,6 +556,188 @@ int run_synthesis(sht_plan_s* P, const void* spec, void* grid, void* stream, int
   prof_mark(P, stream, ST_ZONAL_S, false);
   if (e) return hip_check((hipError_t)e, "zonal synthesis launch");
   return SHT_OK;
+}
+
+enum { DIR_FWD = 0, DIR_INV = 1, DIR_FWD_ADJ = 2, DIR_INV_ADJ = 3 };
+
+int run_eager(sht_plan_s* P, int dir, const void* in, void* out, void* stream) {
+  switch (dir) {
+    case DIR_FWD: return run_analysis(P, in, out, stream, 1, 1, 1.0);
+    case DIR_INV: return run_synthesis(P, in, out, stream, 0, 0, 1.0);
+    case DIR_FWD_ADJ: return run_synthesis(P, in, out, stream, 1, 1, 0.5);
+    default: return run_analysis(P, in, out, stream, 0, 0, 2.0);
+  }
+}
+
+// With use_graph, the first call for a (direction, input, output) triple
+// runs eagerly and records its launches into a hipGraph on a private
+// stream; later calls replay the graph on the caller's stream.
+int run_dir(sht_plan_s* P, int dir, const void* in, void* out, void* stream) {
+  if (!P->use_graph) return run_eager(P, dir, in, out, stream);
+  for (auto& g : P->graphs)
+    if (g.dir == dir && g.in == in && g.out == out)
+      return hip_check(hipGraphLaunch(g.exec, static_cast<hipStream_t>(stream)), "hipGraphLaunch");
+  int rc = run_eager(P, dir, in, out, stream);
+  if (rc) return rc;
+  if (!P->cap_stream && (rc = hip_check(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking),
+                                        "create capture stream")))
+    return rc;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  P->capturing = true;
+  rc = hip_check(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+  if (!rc) {
+    int rc2 = run_eager(P, dir, in, out, P->cap_stream);
+    rc = hip_check(hipStreamEndCapture(P->cap_stream, &graph), "end capture");
+    if (!rc) rc = rc2;
+  }
+  P->capturing = false;
+  if (!rc) rc = hip_check(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "instantiate graph");
+  if (rc) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
+  if (P->graphs.size() >= 16) {
+    (void)hipGraphExecDestroy(P->graphs.front().exec);
+    (void)hipGraphDestroy(P->graphs.front().graph);
+    P->graphs.erase(P->graphs.begin());
+  }
+  P->graphs.push_back({dir, in, out, graph, exec});
+  return SHT_OK;
+}
+
+// ---- autotuner ----
+
+std::string tune_path() {
+  if (const char* e = std::getenv("SHT_TUNE_CACHE")) return e;
+  const char* h = std::getenv("HOME");
+  return std::string(h ? h : "/tmp") + "/.cache/sht_tune.txt";
+}
+
+std::string tune_key(const sht_plan_s* P) {
+  hipDeviceProp_t prop;
+  std::string arch = "unknown";
+  if (hipGetDeviceProperties(&prop, P->device) == hipSuccess) arch = prop.gcnArchName;
+  for (auto& ch : arch)
+    if (ch == ' ') ch = '_';
+  std::string k = arch + " v1 form" + std::to_string(P->form) + " lev" + std::to_string(P->nlev);
+  for (int l = 0; l < P->nlev; ++l)
+    k += " " + std::to_string(P->lev[l].N) + "," + std::to_string(P->lev[l].J) + "," + std::to_string(P->lev[l].I) +
+         "," + std::to_string(P->lev[l].F);
+  return k;
+}
+
+bool tune_lookup(const std::string& key, int v[4]) {
+  FILE* f = std::fopen(tune_path().c_str(), "r");
+  if (!f) return false;
+  char line[4096];
+  bool found = false;
+  while (std::fgets(line, sizeof line, f)) {
+    std::string l(line);
+    size_t bar = l.find('|');
+    if (bar == std::string::npos || l.substr(0, bar) != key) continue;
+    found = std::sscanf(l.c_str() + bar + 1, "%d %d %d %d", &v[0], &v[1], &v[2], &v[3]) == 4;
+  }
+  std::fclose(f);
+  return found;
+}
+
+void tune_store(const std::string& key, const int v[4]) {
+  FILE* f = std::fopen(tune_path().c_str(), "a");
+  if (!f) return;  // the cache is optional
+  std::fprintf(f, "%s|%d %d %d %d\n", key.c_str(), v[0], v[1], v[2], v[3]);
+  std::fclose(f);
+}
+
+int upload_tiles(sht_plan_s* P, bool analysis, const std::vector<Tile>& t) {
+  Tile** slot = analysis ? &P->d_tiles_fwd : &P->d_tiles_inv;
+  int* cnt = analysis ? &P->ntiles_fwd : &P->ntiles_inv;
+  if ((size_t)*cnt < t.size()) {
+    void* p = nullptr;
+    int rc = dev_alloc(P, &p, t.size() * sizeof(Tile));
+    if (rc) return rc;
+    *slot = static_cast<Tile*>(p);  // the old buffer is freed with the plan
+  }
+  *cnt = (int)t.size();
+  return hip_check(hipMemcpy(*slot, t.data(), t.size() * sizeof(Tile), hipMemcpyHostToDevice), "upload tiles");
+}
+
+// Time the Legendre kernels for every column blocking that keeps the
+// workspace layout and both tile orders; keep the fastest per direction.
+int autotune(sht_plan_s* P) {
+  const std::string key = tune_key(P);
+  int v[4];
+  if (!tune_lookup(key, v)) {
+    const int all64[] = {1, 2, 4, 8}, all32[] = {1, 2, 4, 8, 10};
+    const int* all = P->form == SHT_FORM_FP64 ? all64 : all32;
+    const int na = P->form == SHT_FORM_FP64 ? 4 : 5;
+    std::vector<int> cands;
+    for (int k = 0; k < na; ++k) {
+      bool ok = true;
+      for (int l = 0; l < P->nlev; ++l)
+        if (P->lev[l].Cp % (16 * all[k]) || roundup(2LL * P->lev[l].F, 16LL * all[k]) != P->lev[l].Cp) ok = false;
+      if (ok) cands.push_back(all[k]);
+    }
+    void* spec = nullptr;
+    hipStream_t st = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = SHT_OK;
+    if ((rc = hip_check(hipMalloc(&spec, P->spec_elems * P->elem + 16), "tune alloc"))) return rc;
+    (void)hipMemset(spec, 0, P->spec_elems * P->elem);
+    (void)hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    const int saved_profile = P->profile;
+    P->profile = 0;
+    for (int dir = 0; dir < 2 && !rc; ++dir) {
+      const bool analysis = dir == 0;
+      float best = 1e30f;
+      int bc = P->ncb, bs = 0;
+      for (int c : cands)
+        for (int sched = 0; sched < 2 && !rc; ++sched) {
+          std::vector<Tile> t = build_tiles(P, analysis, c, sched);
+          Tile* dt = nullptr;
+          if ((rc = hip_check(hipMalloc(reinterpret_cast<void**>(&dt), t.size() * sizeof(Tile)), "tune alloc"))) break;
+          (void)hipMemcpy(dt, t.data(), t.size() * sizeof(Tile), hipMemcpyHostToDevice);
+          GemmArgs g = gemm_args(P, analysis, spec, spec);
+          g.tiles = dt;
+          g.ntiles = (int)t.size();
+          int e = launch_legendre(P->form, analysis, g, c, st);
+          (void)hipEventRecord(e0, st);
+          for (int r = 0; r < 3 && !e; ++r) e = launch_legendre(P->form, analysis, g, c, st);
+          (void)hipEventRecord(e1, st);
+          (void)hipEventSynchronize(e1);
+          float ms = 0.f;
+          (void)hipEventElapsedTime(&ms, e0, e1);
+          (void)hipFree(dt);
+          if (e) {
+            rc = hip_check((hipError_t)e, "tune launch");
+            break;
+          }
+          if (ms < best) {
+            best = ms;
+            bc = c;
+            bs = sched;
+          }
+        }
+      v[2 * dir] = bc;
+      v[2 * dir + 1] = bs;
+    }
+    P->profile = saved_profile;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipStreamDestroy(st);
+    (void)hipFree(spec);
+    if (rc) return rc;
+    tune_store(key, v);
+  }
+  P->ncb_fwd = v[0];
+  P->sched_fwd = v[1];
+  P->ncb_inv = v[2];
+  P->sched_inv = v[3];
+  int rc = upload_tiles(P, true, build_tiles(P, true, P->ncb_fwd, P->sched_fwd));
+  if (!rc) rc = upload_tiles(P, false, build_tiles(P, false, P->ncb_inv, P->sched_inv));
+  return rc;
 }
 
 }  // namespace
@@ -544,27 +764,27 @@ int sht_plan_multi(int nlevels, const int* N, const int* J, const int* I, const 
 int sht_forward(sht_plan_t plan, const void* grid, void* spec, void* stream) {
   int rc;
   if ((rc = check_plan(plan)) || (rc = check_ptr(grid, "grid")) || (rc = check_ptr(spec, "spec"))) return rc;
-  return run_analysis(plan, grid, spec, stream, 1, 1, 1.0);
+  return run_dir(plan, DIR_FWD, grid, spec, stream);
 }
 
 int sht_inverse(sht_plan_t plan, const void* spec, void* grid, void* stream) {
   int rc;
   if ((rc = check_plan(plan)) || (rc = check_ptr(spec, "spec")) || (rc = check_ptr(grid, "grid"))) return rc;
-  return run_synthesis(plan, spec, grid, stream, 0, 0, 1.0);
+  return run_dir(plan, DIR_INV, spec, grid, stream);
 }
 
 int sht_forward_adjoint(sht_plan_t plan, const void* spec_bar, void* grid_bar, void* stream) {
   int rc;
   if ((rc = check_plan(plan)) || (rc = check_ptr(spec_bar, "spec_bar")) || (rc = check_ptr(grid_bar, "grid_bar")))
     return rc;
-  return run_synthesis(plan, spec_bar, grid_bar, stream, 1, 1, 0.5);
+  return run_dir(plan, DIR_FWD_ADJ, spec_bar, grid_bar, stream);
 }
 
 int sht_inverse_adjoint(sht_plan_t plan, const void* grid_bar, void* spec_bar, void* stream) {
   int rc;
   if ((rc = check_plan(plan)) || (rc = check_ptr(grid_bar, "grid_bar")) || (rc = check_ptr(spec_bar, "spec_bar")))
     return rc;
-  return run_analysis(plan, grid_bar, spec_bar, stream, 0, 0, 2.0);
+  return run_dir(plan, DIR_INV_ADJ, grid_bar, spec_bar, stream);
 }
 
 int sht_plan_query(sht_plan_t plan, int key, void* out) {

@@ -1,0 +1,127 @@
+"""The nested hierarchy batched in one launch per stage (Sec. 3.2 nesting):
+N = 32..512, J = 2N+1 on the grid with the poles, I = 100..1600, 32 fields
+per level, FP32, autotuned Legendre tiles, graph replay.  Each level is
+checked against the oracle; a coarse level fed the injected fine grid must
+return the truncated spectrum."""
+
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1711_11296_amd import inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+LEVELS = [(32, 65, 100, 32), (64, 129, 200, 32), (128, 257, 400, 32),
+          (256, 513, 800, 32), (512, 1025, 1600, 32)]
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+def _np(t):
+    torch.cuda.synchronize()
+    return t.detach().to("cpu", torch.float64).numpy()
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.fixture(scope="module")
+def plan(tmp_path_factory):
+    from paper_1711_11296_amd import Plan
+    _dev()
+    os.environ["SHT_TUNE_CACHE"] = str(tmp_path_factory.mktemp("tune") / "cache.txt")
+    p = Plan(levels=LEVELS, grid="cc_poles", form="fp32", autotune=True, use_graph=True)
+    yield p
+    p.close()
+
+
+def _split(p, buf, kind):
+    out = []
+    for k, (N, J, I, F) in enumerate(p.levels):
+        if kind == "spec":
+            o, n = p.spec_offsets[k], F * (N + 1) * (N + 2)
+            out.append(buf[o:o + n].reshape(F, (N + 1) * (N + 2) // 2, 2))
+        else:
+            o, n = p.grid_offsets[k], F * J * I
+            out.append(buf[o:o + n].reshape(F, J, I))
+    return out
+
+
+def test_hierarchy_against_oracle(plan):
+    specs = [inputs.random_spectra(N, F, seed=k, profile="k3") for k, (N, J, I, F) in enumerate(LEVELS)]
+    a = torch.from_numpy(np.concatenate([s.ravel() for s in specs])).to(_dev(), torch.float32)
+    g = plan.inverse(a)
+    s = plan.forward(g)
+    gl = _split(plan, _np(g), "grid")
+    sl = _split(plan, _np(s), "spec")
+    al = _split(plan, _np(a), "spec")
+    for k, (N, J, I, F) in enumerate(LEVELS):
+        fs = slice(0, F) if N <= 128 else slice(0, 2)
+        g_ref = O.inverse(al[k][fs], N, J, I, "cc_poles")
+        assert rel(gl[k][fs], g_ref) < 1e-6, ("inverse", N)
+        s_ref = O.forward(gl[k][fs], N, "cc_poles")
+        assert rel(sl[k][fs], s_ref) < 1e-6, ("forward", N)
+        assert rel(sl[k], al[k]) < 2e-6, ("round trip", N)
+
+
+def test_graph_replay_matches_eager(plan):
+    specs = [inputs.random_spectra(N, F, seed=10 + k, profile="k3") for k, (N, J, I, F) in enumerate(LEVELS)]
+    a = torch.from_numpy(np.concatenate([s.ravel() for s in specs])).to(_dev(), torch.float32)
+    g = torch.empty(plan.grid_elems, device=_dev(), dtype=torch.float32)
+    s = torch.empty(plan.spec_elems, device=_dev(), dtype=torch.float32)
+    plan.inverse(a, out=g)           # eager, then captured
+    plan.forward(g, out=s)
+    torch.cuda.synchronize()
+    g0, s0 = g.clone(), s.clone()
+    for _ in range(3):               # replays, with eager host work between
+        g.zero_()
+        s.zero_()
+        torch.cuda.synchronize()
+        plan.inverse(a, out=g)
+        plan.forward(g, out=s)
+        torch.cuda.synchronize()
+        assert torch.equal(g, g0) and torch.equal(s, s0)
+
+
+def test_injection_equals_truncation(plan):
+    """Level k's grid taken as every other row and column of level k+1's grid
+    (both synthesised from a spectrum band-limited to N_k) analyses back to
+    that spectrum."""
+    F = 32
+    base = [inputs.random_spectra(N, F, seed=20 + k, profile="k3") for k, (N, J, I, F) in enumerate(LEVELS)]
+    # level k+1 carries level k's spectrum zero-padded to N_{k+1}
+    specs = [base[0]]
+    for k in range(1, len(LEVELS)):
+        Nc, Nf = LEVELS[k - 1][0], LEVELS[k][0]
+        padded = np.zeros((F, O.ncoef(Nf), 2))
+        for m in range(Nc + 1):
+            padded[:, O.spec_index(Nf, m, m):O.spec_index(Nf, m, Nc) + 1] = \
+                base[k - 1][:, O.spec_index(Nc, m, m):O.spec_index(Nc, m, Nc) + 1]
+        specs.append(padded)
+    a = torch.from_numpy(np.concatenate([s.ravel() for s in specs])).to(_dev(), torch.float32)
+    g = plan.inverse(a)
+    gl = _split(plan, g, "grid")
+    inj = torch.empty_like(g)
+    il = _split(plan, inj, "grid")
+    il[-1].copy_(gl[-1])
+    for k in range(len(LEVELS) - 1):
+        il[k].copy_(gl[k + 1][:, ::2, ::2])
+    s = _np(plan.forward(inj))
+    sl = _split(plan, s, "spec")
+    for k in range(len(LEVELS) - 1):
+        assert rel(sl[k], base[k]) < 2e-6, LEVELS[k]
+
+
+def test_autotune_cache_written(plan):
+    path = os.environ["SHT_TUNE_CACHE"]
+    txt = open(path).read()
+    assert "form1 lev5" in txt and "|" in txt
