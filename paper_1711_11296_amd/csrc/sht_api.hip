@@ -156,9 +156,9 @@ int check_level_args(int N, int J, int I, int F, int grid) {
 // (weighted by the Legendre work), preferring wider tiles on ties.
 int choose_ncb(int form, int nlev, const int* N, const int* J, const int* F) {
   const int cand64[] = {8, 4, 2, 1};
-  const int cand32[] = {10, 8, 4, 2, 1};
+  const int cand32[] = {10, 8, 5, 4, 2, 1};
   const int* cand = form == SHT_FORM_FP64 ? cand64 : cand32;
-  const int nc = form == SHT_FORM_FP64 ? 4 : 5;
+  const int nc = form == SHT_FORM_FP64 ? 4 : 6;
   int best = 1;
   double bestc = 1e300;
   for (int k = 0; k < nc; ++k) {
@@ -273,6 +273,78 @@ void fill_table_level(const LevelDesc& L, const double* mu, const double* sint,
   for (auto& th : pool) th.join();
 }
 
+// bfloat16 of a float, round to nearest even (finite inputs)
+uint16_t bf16_rne(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+double bf16_value(uint16_t h) {
+  uint32_t u = (uint32_t)h << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return (double)f;
+}
+
+// three bfloat16 pieces v ~ p0 + p1 + p2, each the rounding of the remainder
+void split3(double v, uint16_t* pc) {
+  double r = v;
+  for (int k = 0; k < 3; ++k) {
+    pc[k] = bf16_rne((float)r);
+    r -= bf16_value(pc[k]);
+  }
+}
+
+// As fill_table_level, for the split form: three bfloat16 planes per copy;
+// the synthesis copy is blocked per (64-row j block, 64-row r block) as
+// [parity][64 j][32 r'] with r = 64 kb + 2 r' + parity.
+void fill_table_level_bf16(const LevelDesc& L, const double* mu, const double* sint, uint16_t* dst,
+                           const long long* off_a, size_t plane_a, uint16_t* dsyn, const long long* off_s,
+                           size_t plane_s) {
+  const int N = L.N, Jh = L.Jh, Kp = L.Kp;
+  const int JB = (Jh + 63) / 64;
+  int nth = (int)std::thread::hardware_concurrency();
+  nth = std::max(1, std::min(nth, 64));
+  std::vector<std::thread> pool;
+  for (int t = 0; t < nth; ++t) {
+    pool.emplace_back([=]() {
+      std::vector<double> col;
+      uint16_t pc[3];
+      for (int k = t; k <= N; k += nth) {
+        const int m = (k % 2 == 0) ? k / 2 : N - k / 2;
+        const int nm = N - m + 1;
+        col.assign((size_t)nm * Jh, 0.0);
+        alf_column(N, m, Jh, mu, sint, col.data(), Jh);
+        const int R = (int)roundup(nm, SHT_ROWS_PAD);
+        for (int r = 0; r < R; ++r)
+          for (int j = 0; j < Kp; ++j) {
+            const double v = (r < nm && j < Jh) ? col[(size_t)r * Jh + j] : 0.0;
+            split3(v, pc);
+            const size_t e = (size_t)off_a[m] + (size_t)r * Kp + j;
+            for (int q = 0; q < 3; ++q) dst[q * plane_a + e] = pc[q];
+          }
+        const int nkb = (nm + 63) / 64;
+        for (int jb = 0; jb < JB; ++jb)
+          for (int kb = 0; kb < nkb; ++kb) {
+            const size_t b = (size_t)off_s[m] + ((size_t)jb * nkb + kb) * 4096;
+            for (int par = 0; par < 2; ++par)
+              for (int jl = 0; jl < 64; ++jl)
+                for (int kl = 0; kl < 32; ++kl) {
+                  const int r = kb * 64 + 2 * kl + par, j = jb * 64 + jl;
+                  const double v = (r < nm && j < Jh) ? col[(size_t)r * Jh + j] : 0.0;
+                  split3(v, pc);
+                  const size_t e = b + (par * 64 + jl) * 32 + kl;
+                  for (int q = 0; q < 3; ++q) dsyn[q * plane_s + e] = pc[q];
+                }
+          }
+      }
+    });
+  }
+  for (auto& th : pool) th.join();
+}
+
 int autotune(sht_plan_s* P);
 
 int build_plan(int nlev, const int* Nv, const int* Jv, const int* Iv, const int* Fv,
@@ -284,7 +356,6 @@ int build_plan(int nlev, const int* Nv, const int* Jv, const int* Iv, const int*
   sht_options o{SHT_GRID_CC_POLES, SHT_FORM_FP64, 0, 0};
   if (opts) o = *opts;
   if (o.form < SHT_FORM_FP64 || o.form > SHT_FORM_BF16X6) return fail(SHT_EINVAL, "unknown form");
-  if (o.form == SHT_FORM_BF16X6) return fail(SHT_EINVAL, "the split-bfloat16 form is not built in this library version");
   for (int l = 0; l < nlev; ++l) {
     int rc = check_level_args(Nv[l], Jv[l], Iv[l], Fv[l], o.grid);
     if (rc) return rc;
@@ -342,7 +413,10 @@ int build_plan(int nlev, const int* Nv, const int* Jv, const int* Iv, const int*
       taboff.push_back(tab);
       tab += roundup(L.N - m + 1, SHT_ROWS_PAD) * L.Kp;
       taboff_syn.push_back(tabs);
-      tabs += (long long)((L.Jh + 63) / 64) * ((L.N - m + 1 + 31) / 32) * 2048;
+      if (o.form == SHT_FORM_BF16X6)
+        tabs += (long long)((L.Jh + 63) / 64) * ((L.N - m + 1 + 63) / 64) * 4096;
+      else
+        tabs += (long long)((L.Jh + 63) / 64) * ((L.N - m + 1 + 31) / 32) * 2048;
     }
     P->maxN = std::max(P->maxN, L.N);
     P->flops += 2.0 * L.Jh * (double)(L.N + 1) * (L.N + 2) * L.F;
@@ -358,11 +432,13 @@ int build_plan(int nlev, const int* Nv, const int* Jv, const int* Iv, const int*
   P->ws_elems = (size_t)woff;
   P->table_elems = (size_t)tab;
   P->table_syn_elems = (size_t)tabs;
-  P->table_bytes = (P->table_elems + P->table_syn_elems) * P->elem;
+  // bytes per table element: the data type, or three bfloat16 planes
+  const size_t tel = o.form == SHT_FORM_BF16X6 ? 6 : P->elem;
+  P->table_bytes = (P->table_elems + P->table_syn_elems) * tel;
   P->ws_bytes = P->ws_elems * P->elem;
 
   // ---- host tables ----
-  std::vector<unsigned char> htab(P->table_elems * P->elem), htabs(P->table_syn_elems * P->elem);
+  std::vector<unsigned char> htab(P->table_elems * tel), htabs(P->table_syn_elems * tel);
   std::vector<double> hw;
   std::vector<std::vector<unsigned char>> htw(nlev);
   size_t tw_total = 0;
@@ -381,6 +457,9 @@ int build_plan(int nlev, const int* Nv, const int* Jv, const int* Iv, const int*
     if (o.form == SHT_FORM_FP64)
       fill_table_level<double>(L, mu.data(), sint.data(), reinterpret_cast<double*>(htab.data()), to,
                                reinterpret_cast<double*>(htabs.data()), ts);
+    else if (o.form == SHT_FORM_BF16X6)
+      fill_table_level_bf16(L, mu.data(), sint.data(), reinterpret_cast<uint16_t*>(htab.data()), to,
+                            P->table_elems, reinterpret_cast<uint16_t*>(htabs.data()), ts, P->table_syn_elems);
     else
       fill_table_level<float>(L, mu.data(), sint.data(), reinterpret_cast<float*>(htab.data()), to,
                               reinterpret_cast<float*>(htabs.data()), ts);
@@ -404,14 +483,27 @@ int build_plan(int nlev, const int* Nv, const int* Jv, const int* Iv, const int*
 
   // ---- tile schedules (default; the autotuner may replace them) ----
   P->ncb_fwd = P->ncb_inv = P->ncb;
-  std::vector<Tile> sf = build_tiles(P, true, P->ncb, 0), si = build_tiles(P, false, P->ncb, 0);
+  if (o.form == SHT_FORM_BF16X6 && P->ncb > 5) {
+    // the split synthesis kernel keeps 4 row blocks of all three pieces in
+    // registers: use at most 5 column blocks per tile when the layout allows
+    for (int c = 5; c >= 1; --c) {
+      bool ok = true;
+      for (int l = 0; l < nlev; ++l)
+        if (P->lev[l].Cp % (16 * c)) ok = false;
+      if (ok) {
+        P->ncb_inv = c;
+        break;
+      }
+    }
+  }
+  std::vector<Tile> sf = build_tiles(P, true, P->ncb_fwd, 0), si = build_tiles(P, false, P->ncb_inv, 0);
   P->ntiles_fwd = (int)sf.size();
   P->ntiles_inv = (int)si.size();
 
   // ---- device buffers ----
   void *dtw = nullptr, *dw = nullptr, *dto = nullptr, *dtf = nullptr, *dti = nullptr, *dtos = nullptr;
-  if ((rc = dev_alloc(P, &P->d_table, P->table_elems * P->elem)) ||
-      (rc = dev_alloc(P, &P->d_table_syn, P->table_syn_elems * P->elem)) ||
+  if ((rc = dev_alloc(P, &P->d_table, htab.size())) ||
+      (rc = dev_alloc(P, &P->d_table_syn, htabs.size())) ||
       (rc = dev_alloc(P, &dtos, taboff_syn.size() * sizeof(long long))) ||
       (rc = dev_alloc(P, &P->d_ws, P->ws_bytes)) ||
       (rc = dev_alloc(P, &dtw, tw_total)) ||
@@ -501,6 +593,7 @@ GemmArgs gemm_args(const sht_plan_s* P, bool analysis, const void* spec_in, void
   g.tiles = analysis ? P->d_tiles_fwd : P->d_tiles_inv;
   g.tab_off = analysis ? P->d_taboff : P->d_taboff_syn;
   g.table = analysis ? P->d_table : P->d_table_syn;
+  g.table_plane = (long long)(analysis ? P->table_elems : P->table_syn_elems);
   g.spec_in = spec_in;
   g.spec_out = spec_out;
   g.ws = P->d_ws;
@@ -668,9 +761,9 @@ int autotune(sht_plan_s* P) {
   const std::string key = tune_key(P);
   int v[4];
   if (!tune_lookup(key, v)) {
-    const int all64[] = {1, 2, 4, 8}, all32[] = {1, 2, 4, 8, 10};
+    const int all64[] = {1, 2, 4, 8}, all32[] = {1, 2, 4, 5, 8, 10};
     const int* all = P->form == SHT_FORM_FP64 ? all64 : all32;
-    const int na = P->form == SHT_FORM_FP64 ? 4 : 5;
+    const int na = P->form == SHT_FORM_FP64 ? 4 : 6;
     std::vector<int> cands;
     for (int k = 0; k < na; ++k) {
       bool ok = true;

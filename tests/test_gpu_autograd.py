@@ -49,7 +49,7 @@ def test_dot_product(form, tol, kind):
     p.close()
 
 
-@pytest.mark.parametrize("form,tol", [("fp64", 1e-12), ("fp32", 1e-6)])
+@pytest.mark.parametrize("form,tol", [("fp64", 1e-12), ("fp32", 1e-6), ("bf16x6", 1e-6)])
 @pytest.mark.parametrize("kind", O.GRID_KINDS)
 def test_autograd_matches_oracle_transpose(form, tol, kind):
     from paper_1711_11296_amd import sht_forward, sht_inverse

@@ -1,6 +1,7 @@
 """GPU parity: the HIP path through the C ABI against the FP64 oracle on the
 same seeded inputs.  Bounds: rel-L2 <= 1e-12 for the FP64 form, <= 1e-6 for
-the FP32 form (the oracle receives the FP32 inputs promoted to FP64)."""
+the FP32 and split-bfloat16 forms (the oracle receives the FP32 inputs
+promoted to FP64)."""
 
 import numpy as np
 import pytest
@@ -12,7 +13,8 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
-TOL = {"fp64": 1e-12, "fp32": 1e-6}
+TOL = {"fp64": 1e-12, "fp32": 1e-6, "bf16x6": 1e-6}
+FORMS = ["fp64", "fp32", "bf16x6"]
 
 
 def _dev():
@@ -65,7 +67,7 @@ def test_c1_fp64_round_trip(kind):
     _roundtrip_case(21, 43, 64, 1, kind, "fp64")
 
 
-@pytest.mark.parametrize("form", ["fp64", "fp32"])
+@pytest.mark.parametrize("form", FORMS)
 @pytest.mark.parametrize("kind", O.GRID_KINDS)
 @pytest.mark.parametrize("N", [0, 1, 2, 5, 8])
 def test_tiny_sweep(form, kind, N):
@@ -76,7 +78,7 @@ def test_tiny_sweep(form, kind, N):
         _roundtrip_case(N, J, I, 3, kind, form, seed=N * 100 + J)
 
 
-@pytest.mark.parametrize("form", ["fp64", "fp32"])
+@pytest.mark.parametrize("form", FORMS)
 @pytest.mark.parametrize("kind,N,J,I,F", [
     ("cc_poles", 100, 203, 216, 5),     # several row and K tiles, ragged tails, 2^3 3^3
     ("fejer2", 130, 250, 300, 9),       # even J (no equator row), F not a multiple of 8
@@ -87,7 +89,7 @@ def test_multi_tile_parity(form, kind, N, J, I, F):
     _roundtrip_case(N, J, I, F, kind, form, profile="k3", seed=N)
 
 
-@pytest.mark.parametrize("form", ["fp64", "fp32"])
+@pytest.mark.parametrize("form", FORMS)
 @pytest.mark.parametrize("kind", O.GRID_KINDS)
 def test_random_grid_forward(form, kind):
     """Analysis of a grid that is not band-limited is still the oracle's map."""
@@ -99,7 +101,7 @@ def test_random_grid_forward(form, kind):
     p.close()
 
 
-@pytest.mark.parametrize("form", ["fp64", "fp32"])
+@pytest.mark.parametrize("form", FORMS)
 @pytest.mark.parametrize("kind", O.GRID_KINDS)
 def test_adjoints_against_oracle(form, kind):
     N, J, I, F = 30, 61, 64, 3
@@ -168,3 +170,46 @@ def test_error_paths_on_device():
     p.close()  # idempotent in Python
     with pytest.raises(SHTError):
         Plan(10, 21, 20, 2)      # I < 2N+1
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_c3_batch_sampled_fields(form):
+    """N=479, J=959, I=1440, 400 fields (100 levels x 4 variables): the whole
+    batch runs on the GPU; fields 0, 1, 199 and 399 are compared with the
+    oracle (fields are independent columns of every stage)."""
+    N, J, I, F = 479, 959, 1440, 400
+    p = _plan(N, J, I, F, "fejer2", form)
+    a = inputs.random_spectra(N, F, seed=0, profile="k3")
+    a_d = _to_dev(a, form)
+    g_d = p.inverse(a_d)
+    s_d = p.forward(g_d)
+    sel = [0, 1, 199, 399]
+    a_in = _host(a_d)[sel]
+    g_in = _host(g_d)[sel]
+    g_ref = O.inverse(a_in, N, J, I, "fejer2")
+    e_inv = rel(g_in, g_ref)
+    s_ref = O.forward(g_in, N, "fejer2")
+    e_fwd = rel(_host(s_d)[sel], s_ref)
+    print("C3 %s: inverse rel-L2 %.3e, forward rel-L2 %.3e" % (form, e_inv, e_fwd))
+    assert e_inv < TOL[form] and e_fwd < TOL[form]
+    p.close()
+
+
+@pytest.mark.parametrize("form", ["fp32", "bf16x6", "fp64"])
+def test_c5_batch_field0(form):
+    """N=959, J=1919, I=2880, 64 fields on the grid with the poles, in the
+    launch configuration the benchmark times; field 0 of both directions is
+    compared with the oracle."""
+    N, J, I, F = 959, 1919, 2880, 64
+    p = _plan(N, J, I, F, "cc_poles", form)
+    a = inputs.random_spectra(N, F, seed=0, profile="k3")
+    a_d = _to_dev(a, form)
+    g_d = p.inverse(a_d)
+    s_d = p.forward(g_d)
+    g_ref = O.inverse(_host(a_d[0:1]), N, J, I, "cc_poles")
+    e_inv = rel(_host(g_d[0:1]), g_ref)
+    s_ref = O.forward(_host(g_d[0:1]), N, "cc_poles")
+    e_fwd = rel(_host(s_d[0:1]), s_ref)
+    print("C5 %s: inverse rel-L2 %.3e, forward rel-L2 %.3e" % (form, e_inv, e_fwd))
+    assert e_inv < TOL[form] and e_fwd < TOL[form]
+    p.close()
