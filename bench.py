@@ -21,7 +21,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}
+PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6, "bf16x6": 2516.6 / 6}
+# (N, J, I, fields, grid, form) of the workloads; t959 is the headline batch
+CONFIGS = {
+    "t959": (959, 1919, 2880, 64, "cc_poles", "fp32"),
+    "t479": (479, 959, 1440, 400, "fejer2", "bf16x6"),
+    "t159": (159, 319, 480, 64, "cc_poles", "fp32"),
+}
 HBM_PEAK_GBS = 8000.0
 
 
@@ -30,15 +36,27 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--N", type=int, default=959)
-    ap.add_argument("--J", type=int, default=1919)
-    ap.add_argument("--I", type=int, default=2880)
-    ap.add_argument("--F", type=int, default=64)
-    ap.add_argument("--grid", default="cc_poles")
-    ap.add_argument("--form", default="fp32")
+    ap.add_argument("--config", default="t959", choices=sorted(CONFIGS),
+                    help="workload: t959 (headline), t479 (400 fields), t159 (64 fields)")
+    ap.add_argument("--grid", default=None)
+    ap.add_argument("--form", default=None)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-form comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy a 1 GiB buffer 3 times (calibrates HBM byte counters)")
     return ap.parse_args()
+
+
+def copy_probe(torch):
+    """A plain device copy of known size: 2^28 floats read and written."""
+    n = 1 << 28
+    src = torch.ones(n, device="cuda:0", dtype=torch.float32)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print("copy probe: %d bytes read and %d bytes written per copy" % (4 * n, 4 * n), flush=True)
 
 
 def time_pairs(plan, g, steps, warmup, torch):
@@ -70,10 +88,15 @@ def main():
     import numpy as np
     import torch
 
+    if args.copy_probe:
+        copy_probe(torch)
+        return
     from paper_1711_11296_amd import Plan, inputs
 
     torch.cuda.set_device(0)
-    N, J, I, F = args.N, args.J, args.I, args.F
+    N, J, I, F, grid0, form0 = CONFIGS[args.config]
+    args.grid = args.grid or grid0
+    args.form = args.form or form0
     dt = torch.float64 if args.form == "fp64" else torch.float32
 
     # ---- workload: grids synthesised from k^-3 band-limited spectra ----
@@ -157,8 +180,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if args.form == "fp32" else ("f64" if args.form == "fp64" else "bf16x6/f32"),
         "data": "synthetic: grids synthesised from k^-3 random spectra (seed 0)",
-        "config": {"workload": "T959 batch: N=%d J=%d I=%d, %d fields, %s grid, %s form, forward+inverse"
-                               % (N, J, I, F, args.grid, args.form),
+        "config": {"workload": "T%d batch: N=%d J=%d I=%d, %d fields, %s grid, %s form, forward+inverse"
+                               % (N, N, J, I, F, args.grid, args.form),
                    "N": N, "J": J, "I": I, "fields": F, "grid": args.grid, "form": args.form},
         "legendre_tflops": leg_tflops,
         "legendre_mfma_frac": leg_tflops / peak,
