@@ -59,6 +59,34 @@ def copy_probe(torch):
     print("copy probe: %d bytes read and %d bytes written per copy" % (4 * n, 4 * n), flush=True)
 
 
+KERNEL_PREFIX = {("legendre_analysis", "fp32"): "sht::k_legendre_analysis<float,",
+                 ("legendre_synthesis", "fp32"): "sht::k_legendre_synthesis<float,",
+                 ("legendre_analysis", "fp64"): "sht::k_legendre_analysis<double,",
+                 ("legendre_synthesis", "fp64"): "sht::k_legendre_synthesis<double,",
+                 ("legendre_analysis", "bf16x6"): "sht::k_legendre_analysis_bf16<",
+                 ("legendre_synthesis", "bf16x6"): "sht::k_legendre_synthesis_bf16<"}
+
+
+def counted_traffic(stage, form, config):
+    """HBM bytes per launch of the stage's kernel from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE runs, scaled by a plain-copy
+    calibration), or None when there is none or the kernel source changed
+    since the counters were taken."""
+    import glob
+    import hashlib
+    prefix = KERNEL_PREFIX.get((stage, form))
+    if prefix is None:
+        return None
+    src = os.path.join(ROOT, "paper_1711_11296_amd", "csrc", "sht_legendre.hip")
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "%s_%s_hbm_counters.md" % (config, form)))):
+        for line in open(path):
+            parts = line.split()
+            if len(parts) == 4 and parts[0] == "traffic_bytes" and parts[1].startswith(prefix):
+                return float(parts[2]) if parts[3] == digest else None
+    return None
+
+
 def time_pairs(plan, g, steps, warmup, torch):
     s = plan.forward(g)
     g2 = plan.inverse(s)
@@ -190,7 +218,7 @@ def main():
         "rel_err_vs_oracle_field0": err,
         "fp64_form": fp64,
         "roofline": {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak, "traffic": counted_traffic(dom, args.form, args.config),
                      "algorithmic_flops_per_launch": flops_dir},
         "cpu_baseline": cpu,
     }
