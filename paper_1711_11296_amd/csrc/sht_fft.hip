@@ -102,6 +102,29 @@ struct Dft<T, 4> {
 };
 
 template <typename T>
+struct Dft<T, 8> {
+  static __device__ __forceinline__ void run(cx<T>* v) {
+    const T r = (T)0.70710678118654752440084436210484904;  // 1/sqrt(2)
+    cx<T> e[4] = {v[0], v[2], v[4], v[6]};
+    cx<T> o[4] = {v[1], v[3], v[5], v[7]};
+    Dft<T, 4>::run(e);
+    Dft<T, 4>::run(o);
+    // o_k *= exp(-2 pi i k / 8)
+    const cx<T> o1 = {r * (o[1].x + o[1].y), r * (o[1].y - o[1].x)};
+    const cx<T> o2 = {o[2].y, -o[2].x};
+    const cx<T> o3 = {r * (o[3].y - o[3].x), -r * (o[3].x + o[3].y)};
+    v[0] = cadd(e[0], o[0]);
+    v[4] = csub(e[0], o[0]);
+    v[1] = cadd(e[1], o1);
+    v[5] = csub(e[1], o1);
+    v[2] = cadd(e[2], o2);
+    v[6] = csub(e[2], o2);
+    v[3] = cadd(e[3], o3);
+    v[7] = csub(e[3], o3);
+  }
+};
+
+template <typename T>
 struct Dft<T, 5> {
   static __device__ __forceinline__ void run(cx<T>* v) {
     const T c1 = (T)0.30901699437494742410229341718281906;   // cos(2 pi/5)
@@ -125,6 +148,9 @@ struct Dft<T, 5> {
   }
 };
 
+// LDS position of element i of the FFT buffers (dense).
+__device__ __forceinline__ int lp(int i) { return i; }
+
 // q = floor(j / d) for 0 <= j < 2^13 and 2 <= d <= 4096, with
 // magic = floor((2^32 - 1) / d) + 1 (exhaustively checked over that range).
 __device__ __forceinline__ int fastdiv(int j, unsigned magic) {
@@ -134,47 +160,57 @@ __device__ __forceinline__ int fastdiv(int j, unsigned magic) {
 // One Stockham pass of radix R over FC sequences of length I that lie one
 // after the other in LDS, in place: every thread first loads and transforms
 // all its butterflies, then (after a barrier) stores them.  Ns is the product
-// of the radices of the earlier passes.  Butterfly u covers sequence
-// f = u / (I/R) (FC is 1 or 2) and position j = u mod (I/R).
+// of the radices of the earlier passes.  A thread owns butterfly position j
+// in all FC sequences, so the index arithmetic and the twiddles are shared by
+// the FC transforms.  With q = floor(j / Ns) and k = j - q Ns the inputs are
+// j + t I/R and the outputs q Ns R + k + t Ns = j R - k (R-1) + t Ns.
 template <typename T, int NT, int FC, int MAXI, int R>
 __device__ __forceinline__ void stockham_pass(cx<T>* buf, int I, int Ns, int twstep,
                                               unsigned magic, const cx<T>* __restrict__ tw) {
-  constexpr int BPT = (FC * MAXI / R + NT - 1) / NT;
+  constexpr int BPT = (MAXI / R + NT - 1) / NT;
   const int nb = twstep * Ns;  // I / R
-  const int tot = FC * nb;
-  cx<T> v[BPT][R];
+  cx<T> v[BPT][FC][R];
 #pragma unroll
   for (int b = 0; b < BPT; ++b) {
-    const int u = threadIdx.x + b * NT;
-    if (u < tot) {
-      const int f = (FC == 2 && u >= nb) ? 1 : 0;
-      const int j = u - f * nb;
-      const cx<T>* src = buf + f * I + j;
-#pragma unroll
-      for (int t = 0; t < R; ++t) v[b][t] = src[t * nb];
+    const int j = threadIdx.x + b * NT;
+    if (j < nb) {
+      cx<T> w[R];
       if (Ns > 1) {
         const int k = j - fastdiv(j, magic) * Ns;
+        const int step = k * twstep;
+        int idx = step;
 #pragma unroll
-        for (int t = 1; t < R; ++t) v[b][t] = cmul(v[b][t], tw[t * k * twstep]);
+        for (int t = 1; t < R; ++t) {
+          w[t] = tw[idx];
+          idx += step;
+        }
       }
-      Dft<T, R>::run(v[b]);
+#pragma unroll
+      for (int f = 0; f < FC; ++f) {
+        const int src = f * I + j;
+#pragma unroll
+        for (int t = 0; t < R; ++t) v[b][f][t] = buf[lp(src + t * nb)];
+        if (Ns > 1) {
+#pragma unroll
+          for (int t = 1; t < R; ++t) v[b][f][t] = cmul(v[b][f][t], w[t]);
+        }
+        Dft<T, R>::run(v[b][f]);
+      }
     }
   }
   __syncthreads();
 #pragma unroll
   for (int b = 0; b < BPT; ++b) {
-    const int u = threadIdx.x + b * NT;
-    if (u < tot) {
-      const int f = (FC == 2 && u >= nb) ? 1 : 0;
-      const int j = u - f * nb;
-      int q = j, k = 0;
-      if (Ns > 1) {
-        q = fastdiv(j, magic);
-        k = j - q * Ns;
-      }
-      cx<T>* dst = buf + f * I + q * Ns * R + k;
+    const int j = threadIdx.x + b * NT;
+    if (j < nb) {
+      int out = j * R;
+      if (Ns > 1) out -= (j - fastdiv(j, magic) * Ns) * (R - 1);
 #pragma unroll
-      for (int t = 0; t < R; ++t) dst[t * Ns] = v[b][t];
+      for (int f = 0; f < FC; ++f) {
+        const int dst = f * I + out;
+#pragma unroll
+        for (int t = 0; t < R; ++t) buf[lp(dst + t * Ns)] = v[b][f][t];
+      }
     }
   }
   __syncthreads();
@@ -187,7 +223,9 @@ __device__ void fft_lds(cx<T>* buf, const LevelDesc& L, const cx<T>* tw) {
   for (int p = 0; p < L.nrad; ++p) {
     const int R = L.rad[p], Ns = L.pns[p], tws = L.ptw[p];
     const unsigned mg = L.pmag[p];
-    if (R == 4)
+    if (R == 8)
+      stockham_pass<T, NT, FC, MAXI, 8>(buf, L.I, Ns, tws, mg, tw);
+    else if (R == 4)
       stockham_pass<T, NT, FC, MAXI, 4>(buf, L.I, Ns, tws, mg, tw);
     else if (R == 2)
       stockham_pass<T, NT, FC, MAXI, 2>(buf, L.I, Ns, tws, mg, tw);
@@ -253,205 +291,262 @@ __device__ __forceinline__ void load_run(const T* src, cx<T> (&v)[FB]) {
   }
 }
 
+// Work item = (level, mirror row pair jp, block fb of FB fields).
+struct Item {
+  int l, jp, fb, js;
+  bool eq;
+};
+
+__device__ __forceinline__ Item decode_item(const FftArgs& a, int item) {
+  Item it;
+  it.l = level_of(a, item);
+  const LevelDesc& L = a.lev[it.l];
+  const int local = item - L.fft_item0;
+  it.jp = local / L.nfb;
+  it.fb = local - it.jp * L.nfb;
+  it.eq = (L.J & 1) && (it.jp == (L.J >> 1));
+  it.js = L.J - 1 - it.jp;
+  return it;
+}
+
+template <typename T>
+__device__ __forceinline__ T row_scale(const FftArgs& a, const LevelDesc& L, int jp) {
+  T r = (T)1;
+  if (a.use_w) r = (T)L.wrow[jp];
+  if (a.use_inv_I) r = (T)((double)r / (double)L.I);
+  return r;
+}
+
 // ---------------------------------------------------------------------------
 // analysis: grid [F][J][I] -> workspace S/A
-// FB fields per workgroup, FC of them transformed together; the rows of the
-// next FC fields are prefetched into registers while the current ones are
-// transformed.  Twiddles are staged in LDS when TWL is set.
+// Persistent workgroups walk the work items with a stride of gridDim.x.
+// FB fields per item, FC of them transformed together; the rows of the next
+// FC fields (of this item, or the first FC of the next item) are prefetched
+// into registers while the current ones are transformed, so loads, FFTs and
+// the stores of the previous item overlap.  Twiddles are staged in LDS when
+// TWL is set (reloaded when the level changes).
 // ---------------------------------------------------------------------------
 template <typename T, int NT, int FB, int FC, int MS, int MAXI, bool TWL>
 __global__ __launch_bounds__(NT) void k_zonal_analysis(const FftArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int item = blockIdx.x;
-  if (item >= a.nitems) return;
-  const int l = level_of(a, item);
-  const LevelDesc& L = a.lev[l];
-  const int local = item - L.fft_item0;
-  const int jp = local / L.nfb;
-  const int fb = local - jp * L.nfb;
-  const int I = L.I, J = L.J, N = L.N;
-  const bool eq = (J & 1) && (jp == (J >> 1));
-  const int js = J - 1 - jp;
-  const T* grid = static_cast<const T*>(a.src) + L.grid_off;
-  T* ws = static_cast<T*>(a.dst) + L.ws_off;
+  constexpr int NRD = FB / FC;
+  constexpr int LPT = (MAXI + NT - 1) / NT;
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
-  const cx<T>* tw = static_cast<const cx<T>*>(L.tw);
-  if (TWL) {
-    cx<T>* twl = buf + FC * I;
-    for (int i = threadIdx.x; i < I; i += NT) twl[i] = tw[i];
-    tw = twl;
-  }
-
-  T rscale = (T)1;
-  if (a.use_w) rscale = (T)L.wrow[jp];
-  if (a.use_inv_I) rscale = (T)((double)rscale / (double)I);
+  const T* grid0 = static_cast<const T*>(a.src);
+  T* ws0 = static_cast<T*>(a.dst);
   const T msc = (T)a.mscale;
 
-  constexpr int LPT = (MAXI + NT - 1) / NT;
   T pn[FC][LPT], ps[FC][LPT];
-  auto load_rows = [&](int rd) {
+  auto load_rows = [&](int item, int rd) {
+    const Item it = decode_item(a, item);
+    const LevelDesc& L = a.lev[it.l];
+    const T* grid = grid0 + L.grid_off;
 #pragma unroll
     for (int fc = 0; fc < FC; ++fc) {
-      const int f = fb * FB + rd * FC + fc;
+      const int f = it.fb * FB + rd * FC + fc;
       const bool valid = f < L.F;
-      const T* rn = grid + ((long long)f * J + jp) * I;
-      const T* rs = grid + ((long long)f * J + js) * I;
+      const T* rn = grid + ((long long)f * L.J + it.jp) * L.I;
+      const T* rs = grid + ((long long)f * L.J + it.js) * L.I;
 #pragma unroll
       for (int e = 0; e < LPT; ++e) {
         const int i = threadIdx.x + e * NT;
-        pn[fc][e] = (valid && i < I) ? rn[i] : (T)0;
-        ps[fc][e] = (valid && !eq && i < I) ? rs[i] : (T)0;
+        pn[fc][e] = (valid && i < L.I) ? rn[i] : (T)0;
+        ps[fc][e] = (valid && !it.eq && i < L.I) ? rs[i] : (T)0;
       }
     }
   };
 
-  cx<T> stS[MS][FB], stA[MS][FB];
-  load_rows(0);
-#pragma unroll
-  for (int rd = 0; rd < FB / FC; ++rd) {
-#pragma unroll
-    for (int fc = 0; fc < FC; ++fc)
-#pragma unroll
-      for (int e = 0; e < LPT; ++e) {
-        const int i = threadIdx.x + e * NT;
-        if (i < I) buf[fc * I + i] = cx<T>{pn[fc][e], ps[fc][e]};
+  int item = blockIdx.x;
+  if (item >= a.nitems) return;
+  int lcur = -1;
+  const cx<T>* tw = nullptr;
+  load_rows(item, 0);
+  for (; item < a.nitems; item += gridDim.x) {
+    const Item it = decode_item(a, item);
+    const LevelDesc& L = a.lev[it.l];
+    const int I = L.I, N = L.N;
+    if (it.l != lcur) {
+      if (TWL) {
+        __syncthreads();  // the previous level's twiddles are no longer read
+        cx<T>* twl = buf + a.tw_lds;
+        const cx<T>* twg = static_cast<const cx<T>*>(L.tw);
+        for (int i = threadIdx.x; i < I; i += NT) twl[i] = twg[i];
+        tw = twl;
+      } else {
+        tw = static_cast<const cx<T>*>(L.tw);
       }
-    __syncthreads();
-    if (rd + 1 < FB / FC) load_rows(rd + 1);
-    fft_lds<T, NT, FC, MAXI>(buf, L, tw);
+      lcur = it.l;
+    }
+    const T rscale = row_scale<T>(a, L, it.jp);
+    const int next = item + (int)gridDim.x;
+
+    cx<T> stS[MS][FB], stA[MS][FB];
+#pragma unroll
+    for (int rd = 0; rd < NRD; ++rd) {
+#pragma unroll
+      for (int fc = 0; fc < FC; ++fc)
+#pragma unroll
+        for (int e = 0; e < LPT; ++e) {
+          const int i = threadIdx.x + e * NT;
+          if (i < I) buf[lp(fc * I + i)] = cx<T>{pn[fc][e], ps[fc][e]};
+        }
+      __syncthreads();
+      if (rd + 1 < NRD)
+        load_rows(item, rd + 1);
+      else if (next < a.nitems)
+        load_rows(next, 0);
+      fft_lds<T, NT, FC, MAXI>(buf, L, tw);
+#pragma unroll
+      for (int s = 0; s < MS; ++s) {
+        const int m = threadIdx.x + s * NT;
+#pragma unroll
+        for (int fc = 0; fc < FC; ++fc) {
+          cx<T> S = {(T)0, (T)0}, A = {(T)0, (T)0};
+          if (m <= N) {
+            const cx<T> P = buf[lp(fc * I + m)];
+            cx<T> Q = buf[lp(fc * I + (m == 0 ? 0 : I - m))];
+            Q.y = -Q.y;  // conj Z^{I-m}
+            const T h = (T)0.5;
+            const cx<T> Xn = {h * (P.x + Q.x), h * (P.y + Q.y)};
+            const cx<T> Xs = {h * (P.y - Q.y), -h * (P.x - Q.x)};
+            const T sc = m == 0 ? rscale : rscale * msc;
+            S = cx<T>{sc * (Xn.x + Xs.x), sc * (Xn.y + Xs.y)};
+            A = cx<T>{sc * (Xn.x - Xs.x), sc * (Xn.y - Xs.y)};
+            if (m == 0) {
+              S.y = (T)0;
+              A.y = (T)0;
+            }
+            if (it.eq) A = cx<T>{(T)0, (T)0};
+          }
+          stS[s][rd * FC + fc] = S;
+          stA[s][rd * FC + fc] = A;
+        }
+      }
+      __syncthreads();
+    }
+
+    T* ws = ws0 + L.ws_off;
+    const long long Cp = L.Cp;
+    const long long plane = (long long)L.Kp * Cp;
 #pragma unroll
     for (int s = 0; s < MS; ++s) {
       const int m = threadIdx.x + s * NT;
-#pragma unroll
-      for (int fc = 0; fc < FC; ++fc) {
-        cx<T> S = {(T)0, (T)0}, A = {(T)0, (T)0};
-        if (m <= N) {
-          const cx<T> P = buf[fc * I + m];
-          cx<T> Q = buf[fc * I + (m == 0 ? 0 : I - m)];
-          Q.y = -Q.y;  // conj Z^{I-m}
-          const T h = (T)0.5;
-          const cx<T> Xn = {h * (P.x + Q.x), h * (P.y + Q.y)};
-          const cx<T> Xs = {h * (P.y - Q.y), -h * (P.x - Q.x)};
-          const T sc = m == 0 ? rscale : rscale * msc;
-          S = cx<T>{sc * (Xn.x + Xs.x), sc * (Xn.y + Xs.y)};
-          A = cx<T>{sc * (Xn.x - Xs.x), sc * (Xn.y - Xs.y)};
-          if (m == 0) {
-            S.y = (T)0;
-            A.y = (T)0;
-          }
-          if (eq) A = cx<T>{(T)0, (T)0};
-        }
-        stS[s][rd * FC + fc] = S;
-        stA[s][rd * FC + fc] = A;
+      if (m <= N) {
+        T* dS = ws + (2LL * m) * plane + (long long)it.jp * Cp + 2 * it.fb * FB;
+        store_run<T, FB>(dS, stS[s]);
+        store_run<T, FB>(dS + plane, stA[s]);
       }
-    }
-    __syncthreads();
-  }
-
-  const long long Cp = L.Cp;
-  const long long plane = (long long)L.Kp * Cp;
-#pragma unroll
-  for (int s = 0; s < MS; ++s) {
-    const int m = threadIdx.x + s * NT;
-    if (m <= N) {
-      T* dS = ws + (2LL * m) * plane + (long long)jp * Cp + 2 * fb * FB;
-      store_run<T, FB>(dS, stS[s]);
-      store_run<T, FB>(dS + plane, stA[s]);
     }
   }
 }
 
 // ---------------------------------------------------------------------------
 // synthesis: workspace S/A -> grid [F][J][I]
+// Persistent like the analysis; the workspace runs of the next item are
+// loaded as soon as the last round of the current item has filled its
+// buffers, so they overlap that round's FFT and row stores.
 // ---------------------------------------------------------------------------
 template <typename T, int NT, int FB, int FC, int MS, int MAXI, bool TWL>
 __global__ __launch_bounds__(NT) void k_zonal_synthesis(const FftArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int item = blockIdx.x;
-  if (item >= a.nitems) return;
-  const int l = level_of(a, item);
-  const LevelDesc& L = a.lev[l];
-  const int local = item - L.fft_item0;
-  const int jp = local / L.nfb;
-  const int fb = local - jp * L.nfb;
-  const int I = L.I, J = L.J, N = L.N;
-  const bool eq = (J & 1) && (jp == (J >> 1));
-  const int js = J - 1 - jp;
-  const T* ws = static_cast<const T*>(a.src) + L.ws_off;
-  T* grid = static_cast<T*>(a.dst) + L.grid_off;
+  constexpr int NRD = FB / FC;
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
-  const cx<T>* tw = static_cast<const cx<T>*>(L.tw);
-  if (TWL) {
-    cx<T>* twl = buf + FC * I;
-    for (int i = threadIdx.x; i < I; i += NT) twl[i] = tw[i];
-    tw = twl;
-  }
-
-  T rscale = (T)1;
-  if (a.use_w) rscale = (T)L.wrow[jp];
-  if (a.use_inv_I) rscale = (T)((double)rscale / (double)I);
+  const T* ws0 = static_cast<const T*>(a.src);
+  T* grid0 = static_cast<T*>(a.dst);
   const T msc = (T)a.mscale;
 
-  const long long Cp = L.Cp;
-  const long long plane = (long long)L.Kp * Cp;
   cx<T> stS[MS][FB], stA[MS][FB];
+  auto load_ws = [&](int item) {
+    const Item it = decode_item(a, item);
+    const LevelDesc& L = a.lev[it.l];
+    const T* ws = ws0 + L.ws_off;
+    const long long Cp = L.Cp;
+    const long long plane = (long long)L.Kp * Cp;
 #pragma unroll
-  for (int s = 0; s < MS; ++s) {
-    const int m = threadIdx.x + s * NT;
-    if (m <= N) {
-      const T* sS = ws + (2LL * m) * plane + (long long)jp * Cp + 2 * fb * FB;
-      load_run<T, FB>(sS, stS[s]);
-      load_run<T, FB>(sS + plane, stA[s]);
-    } else {
+    for (int s = 0; s < MS; ++s) {
+      const int m = threadIdx.x + s * NT;
+      if (m <= L.N) {
+        const T* sS = ws + (2LL * m) * plane + (long long)it.jp * Cp + 2 * it.fb * FB;
+        load_run<T, FB>(sS, stS[s]);
+        load_run<T, FB>(sS + plane, stA[s]);
+      } else {
 #pragma unroll
-      for (int q = 0; q < FB; ++q) stS[s][q] = stA[s][q] = cx<T>{(T)0, (T)0};
+        for (int q = 0; q < FB; ++q) stS[s][q] = stA[s][q] = cx<T>{(T)0, (T)0};
+      }
     }
-  }
+  };
+
+  int item = blockIdx.x;
+  if (item >= a.nitems) return;
+  int lcur = -1;
+  const cx<T>* tw = nullptr;
+  load_ws(item);
+  for (; item < a.nitems; item += gridDim.x) {
+    const Item it = decode_item(a, item);
+    const LevelDesc& L = a.lev[it.l];
+    const int I = L.I, J = L.J, N = L.N;
+    if (it.l != lcur) {
+      if (TWL) {
+        __syncthreads();
+        cx<T>* twl = buf + a.tw_lds;
+        const cx<T>* twg = static_cast<const cx<T>*>(L.tw);
+        for (int i = threadIdx.x; i < I; i += NT) twl[i] = twg[i];
+        tw = twl;
+      } else {
+        tw = static_cast<const cx<T>*>(L.tw);
+      }
+      lcur = it.l;
+    }
+    const T rscale = row_scale<T>(a, L, it.jp);
+    const int next = item + (int)gridDim.x;
+    T* grid = grid0 + L.grid_off;
 
 #pragma unroll
-  for (int rd = 0; rd < FB / FC; ++rd) {
+    for (int rd = 0; rd < NRD; ++rd) {
 #pragma unroll
-    for (int fc = 0; fc < FC; ++fc) {
-      cx<T>* bf = buf + fc * I;
-      // zero the bins no thread fills: N < i < I-N
-      for (int i = N + 1 + threadIdx.x; i < I - N; i += NT) bf[i] = cx<T>{(T)0, (T)0};
+      for (int fc = 0; fc < FC; ++fc) {
+        const int bf = fc * I;
+        // zero the bins no thread fills: N < i < I-N
+        for (int i = N + 1 + threadIdx.x; i < I - N; i += NT) buf[lp(bf + i)] = cx<T>{(T)0, (T)0};
 #pragma unroll
-      for (int s = 0; s < MS; ++s) {
-        const int m = threadIdx.x + s * NT;
-        if (m <= N) {
-          const cx<T> S = stS[s][rd * FC + fc], A = stA[s][rd * FC + fc];
-          const T sc = m == 0 ? (T)1 : msc;
-          cx<T> Xn = {sc * (S.x + A.x), sc * (S.y + A.y)};
-          cx<T> Xs = {sc * (S.x - A.x), sc * (S.y - A.y)};
-          if (m == 0) {
-            Xn.y = (T)0;
-            Xs.y = (T)0;
+        for (int s = 0; s < MS; ++s) {
+          const int m = threadIdx.x + s * NT;
+          if (m <= N) {
+            const cx<T> S = stS[s][rd * FC + fc], A = stA[s][rd * FC + fc];
+            const T sc = m == 0 ? (T)1 : msc;
+            cx<T> Xn = {sc * (S.x + A.x), sc * (S.y + A.y)};
+            cx<T> Xs = {sc * (S.x - A.x), sc * (S.y - A.y)};
+            if (m == 0) {
+              Xn.y = (T)0;
+              Xs.y = (T)0;
+            }
+            // the buffer holds conj(Z): the forward FFT of conj(Z) is the
+            // conjugate of the inverse transform of Z, with
+            // Z^m = Xn + i Xs and Z^{I-m} = conj(Xn) + i conj(Xs)
+            buf[lp(bf + m)] = cx<T>{Xn.x - Xs.y, -(Xn.y + Xs.x)};
+            if (m > 0) buf[lp(bf + I - m)] = cx<T>{Xn.x + Xs.y, Xn.y - Xs.x};
           }
-          // the buffer holds conj(Z): the forward FFT of conj(Z) is the
-          // conjugate of the inverse transform of Z, with
-          // Z^m = Xn + i Xs and Z^{I-m} = conj(Xn) + i conj(Xs)
-          bf[m] = cx<T>{Xn.x - Xs.y, -(Xn.y + Xs.x)};
-          if (m > 0) bf[I - m] = cx<T>{Xn.x + Xs.y, Xn.y - Xs.x};
         }
       }
-    }
-    __syncthreads();
-    fft_lds<T, NT, FC, MAXI>(buf, L, tw);
+      __syncthreads();
+      if (rd + 1 == NRD && next < a.nitems) load_ws(next);
+      fft_lds<T, NT, FC, MAXI>(buf, L, tw);
 #pragma unroll
-    for (int fc = 0; fc < FC; ++fc) {
-      const int f = fb * FB + rd * FC + fc;
-      if (f < L.F) {
-        const cx<T>* bf = buf + fc * I;
-        T* rn = grid + ((long long)f * J + jp) * I;
-        T* rs = grid + ((long long)f * J + js) * I;
-        for (int i = threadIdx.x; i < I; i += NT) {
-          const cx<T> y = bf[i];
-          rn[i] = rscale * y.x;
-          if (!eq) rs[i] = -rscale * y.y;
+      for (int fc = 0; fc < FC; ++fc) {
+        const int f = it.fb * FB + rd * FC + fc;
+        if (f < L.F) {
+          const int bf = fc * I;
+          T* rn = grid + ((long long)f * J + it.jp) * I;
+          T* rs = grid + ((long long)f * J + it.js) * I;
+          for (int i = threadIdx.x; i < I; i += NT) {
+            const cx<T> y = buf[lp(bf + i)];
+            rn[i] = rscale * y.x;
+            if (!it.eq) rs[i] = -rscale * y.y;
+          }
         }
       }
+      __syncthreads();
     }
-    __syncthreads();
   }
 }
 
@@ -471,28 +566,48 @@ static void lds_optin(size_t bytes) {
   }
 }
 
+static int g_num_cu = 0;
+
 template <typename T, int NT, int FB, int FC, int MS, int MAXI>
 static hipError_t launch_cfg(bool analysis, const FftArgs& a, int maxI, hipStream_t st) {
-  const size_t buf = (size_t)FC * maxI * sizeof(cx<T>);
+  // FC padded buffers sized for the largest level, then the twiddles
+  FftArgs a2 = a;
+  const int belems = (FC * maxI + 1) & ~1;
+  a2.tw_lds = belems;
+  const size_t buf = (size_t)belems * sizeof(cx<T>);
   const size_t twb = (size_t)maxI * sizeof(cx<T>);
   const bool twl = buf + twb <= kMaxLds;
   const size_t lds = buf + (twl ? twb : 0);
-  const dim3 grid(a.nitems), block(NT);
+  if (g_num_cu == 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&g_num_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        g_num_cu <= 0)
+      g_num_cu = 256;
+  }
+  // persistent workgroups: as many as fit on the device at once
+  int per_cu = (int)(kMaxLds / lds);
+  const int by_waves = 2048 / NT;
+  per_cu = per_cu < by_waves ? per_cu : by_waves;
+  per_cu = per_cu < 1 ? 1 : per_cu;
+  int nwg = g_num_cu * per_cu;
+  nwg = nwg < a.nitems ? nwg : a.nitems;
+  const dim3 grid(nwg), block(NT);
   if (analysis) {
     if (twl) {
       lds_optin<k_zonal_analysis<T, NT, FB, FC, MS, MAXI, true>>(lds);
-      hipLaunchKernelGGL((k_zonal_analysis<T, NT, FB, FC, MS, MAXI, true>), grid, block, lds, st, a);
+      hipLaunchKernelGGL((k_zonal_analysis<T, NT, FB, FC, MS, MAXI, true>), grid, block, lds, st, a2);
     } else {
       lds_optin<k_zonal_analysis<T, NT, FB, FC, MS, MAXI, false>>(lds);
-      hipLaunchKernelGGL((k_zonal_analysis<T, NT, FB, FC, MS, MAXI, false>), grid, block, lds, st, a);
+      hipLaunchKernelGGL((k_zonal_analysis<T, NT, FB, FC, MS, MAXI, false>), grid, block, lds, st, a2);
     }
   } else {
     if (twl) {
       lds_optin<k_zonal_synthesis<T, NT, FB, FC, MS, MAXI, true>>(lds);
-      hipLaunchKernelGGL((k_zonal_synthesis<T, NT, FB, FC, MS, MAXI, true>), grid, block, lds, st, a);
+      hipLaunchKernelGGL((k_zonal_synthesis<T, NT, FB, FC, MS, MAXI, true>), grid, block, lds, st, a2);
     } else {
       lds_optin<k_zonal_synthesis<T, NT, FB, FC, MS, MAXI, false>>(lds);
-      hipLaunchKernelGGL((k_zonal_synthesis<T, NT, FB, FC, MS, MAXI, false>), grid, block, lds, st, a);
+      hipLaunchKernelGGL((k_zonal_synthesis<T, NT, FB, FC, MS, MAXI, false>), grid, block, lds, st, a2);
     }
   }
   return hipGetLastError();
@@ -511,8 +626,11 @@ static hipError_t launch_zonal_t(bool analysis, const FftArgs& a, int maxN, hipS
     if (nm <= 512) return launch_cfg<T, 512, FB, FC, 1, 2048>(analysis, a, maxI, st);
     return launch_cfg<T, 512, FB, FC, 2, 2048>(analysis, a, maxI, st);
   }
-  if (nm <= 1024) return launch_cfg<T, 1024, FB, FC, 1, 4096>(analysis, a, maxI, st);
-  return launch_cfg<T, 1024, FB, FC, 2, 4096>(analysis, a, maxI, st);
+  // one 512-thread workgroup per CU: 256 registers per lane, no spilling
+  if (nm <= 512) return launch_cfg<T, 512, FB, FC, 1, 4096>(analysis, a, maxI, st);
+  if (nm <= 1024) return launch_cfg<T, 512, FB, FC, 2, 4096>(analysis, a, maxI, st);
+  if (nm <= 1536) return launch_cfg<T, 512, FB, FC, 3, 4096>(analysis, a, maxI, st);
+  return launch_cfg<T, 512, FB, FC, 4, 4096>(analysis, a, maxI, st);
 }
 
 int zonal_fields_per_block(int form) { return form == SHT_FORM_FP64 ? 4 : 8; }
@@ -520,7 +638,7 @@ int zonal_fields_per_block(int form) { return form == SHT_FORM_FP64 ? 4 : 8; }
 int launch_zonal(int form, bool analysis, const FftArgs& a, int maxN, void* stream) {
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (form == SHT_FORM_FP64) return (int)launch_zonal_t<double, 4, 1>(analysis, a, maxN, st);
-  return (int)launch_zonal_t<float, 8, 2>(analysis, a, maxN, st);
+  return (int)launch_zonal_t<float, 8, 4>(analysis, a, maxN, st);
 }
 
 }  // namespace sht

@@ -207,6 +207,10 @@ void alf_table(int N, int nr, const double* mu, const double* sint,
 
 bool factor_radices(int I, int* rad, int* nrad) {
   int n = I, k = 0;
+  while (n % 8 == 0) {
+    rad[k++] = 8;
+    n /= 8;
+  }
   while (n % 4 == 0) {
     rad[k++] = 4;
     n /= 4;

@@ -63,6 +63,7 @@ struct FftArgs {
   int use_w;
   int use_inv_I;
   double mscale;
+  int tw_lds;        // element offset of the LDS twiddle table (set at launch)
 };
 
 // One work tile of a Legendre kernel; level < 0 marks an idle slot.
