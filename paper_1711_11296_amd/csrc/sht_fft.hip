@@ -28,6 +28,9 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+#include <utility>
+
 #include "sht_internal.h"
 
 namespace sht {
@@ -147,6 +150,96 @@ struct Dft<T, 5> {
     v[3] = {r2.x - i2.y, r2.y + i2.x};
   }
 };
+
+// ---------------------------------------------------------------------------
+// Composite in-register DFTs, R = R1 * R2 (Cooley-Tukey): R2 DFTs of length
+// R1 over the inputs n = R2 n1 + n2, the internal twiddles
+// exp(-2 pi i n2 k1 / R), then R1 DFTs of length R2; output index
+// k = k1 + R1 k2.  The twiddles are compile-time constants.
+// ---------------------------------------------------------------------------
+constexpr double kTwoPi = 6.283185307179586476925286766559005768;
+
+// sin(x) for |x| <= pi/2 by its Taylor series (accurate to double rounding)
+constexpr double csin_small(double x) {
+  double x2 = x * x, term = x, sum = x;
+  for (int k = 1; k < 14; ++k) {
+    term *= -x2 / ((2.0 * k) * (2.0 * k + 1.0));
+    sum += term;
+  }
+  return sum;
+}
+
+// sin(2 pi e / R) and cos(2 pi e / R) with exact integer range reduction
+constexpr double csin2pi(int e, int R) {
+  e %= R;
+  if (e < 0) e += R;
+  // reduce to the first half turn by symmetry: sin(2 pi - x) = -sin(x)
+  if (2 * e > R) return -csin2pi(R - e, R);
+  // x = 2 pi e / R in [0, pi]; sin(x) = sin(pi - x)
+  if (4 * e > R) return csin_small(kTwoPi * (double)(R - 2 * e) / (2.0 * R));
+  return csin_small(kTwoPi * (double)e / (double)R);
+}
+
+constexpr double ccos2pi(int e, int R) { return csin2pi(4 * e + R, 4 * R); }
+
+// Calls f(integral_constant<int, i>) for i = 0..N-1, so that f can form
+// constant expressions from i.
+template <class F, int... Is>
+__device__ __forceinline__ void static_for_impl(F& f, std::integer_sequence<int, Is...>) {
+  (f(std::integral_constant<int, Is>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+template <typename T, int R1, int R2>
+struct DftCT {
+  static constexpr int R = R1 * R2;
+  static __device__ __forceinline__ void run(cx<T>* v) {
+    cx<T> y[R2][R1];
+    static_for<R2>([&](auto n2c) {
+      constexpr int n2 = decltype(n2c)::value;
+      cx<T> t[R1];
+#pragma unroll
+      for (int n1 = 0; n1 < R1; ++n1) t[n1] = v[R2 * n1 + n2];
+      Dft<T, R1>::run(t);
+      static_for<R1>([&](auto k1c) {
+        constexpr int k1 = decltype(k1c)::value;
+        if constexpr (n2 == 0 || k1 == 0) {
+          y[n2][k1] = t[k1];
+        } else {
+          constexpr T c = (T)ccos2pi(n2 * k1, R), sn = (T)-csin2pi(n2 * k1, R);
+          y[n2][k1] = cx<T>{t[k1].x * c - t[k1].y * sn, t[k1].x * sn + t[k1].y * c};
+        }
+      });
+    });
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1) {
+      cx<T> t[R2];
+#pragma unroll
+      for (int n2 = 0; n2 < R2; ++n2) t[n2] = y[n2][k1];
+      Dft<T, R2>::run(t);
+#pragma unroll
+      for (int k2 = 0; k2 < R2; ++k2) v[k1 + R1 * k2] = t[k2];
+    }
+  }
+};
+
+template <typename T>
+struct Dft<T, 6> : DftCT<T, 3, 2> {};
+template <typename T>
+struct Dft<T, 9> : DftCT<T, 3, 3> {};
+template <typename T>
+struct Dft<T, 10> : DftCT<T, 5, 2> {};
+template <typename T>
+struct Dft<T, 12> : DftCT<T, 4, 3> {};
+template <typename T>
+struct Dft<T, 15> : DftCT<T, 5, 3> {};
+template <typename T>
+struct Dft<T, 16> : DftCT<T, 4, 4> {};
+template <typename T>
+struct Dft<T, 20> : DftCT<T, 5, 4> {};
 
 // LDS position of element i of the FFT buffers (dense).
 __device__ __forceinline__ int lp(int i) { return i; }
@@ -551,6 +644,365 @@ __global__ __launch_bounds__(NT) void k_zonal_synthesis(const FftArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Fixed-length transforms: I = 16 R2 R3 in three passes with compile-time
+// radices, twiddle strides and index arithmetic.
+//
+// The FC sequences of a round lie in LDS with a field stride of IP = 17 I/16
+// complex values.  The output of the radix-16 first pass (Ns = 1, element
+// 16 j + t of the natural order) is stored at the padded position 17 j + t,
+// so that the 64 lanes of a wave, which own consecutive j, hit distinct
+// banks; the second pass reads that padded order (its inputs j + t I/R2 sit
+// at j + j/16 + t (17/16)(I/R2), since I/R2 is a multiple of 16) and writes
+// the natural order; the third pass reads and writes the natural order.
+// The twiddles of passes two and three are staged in LDS as [t-1][k]
+// (k = butterfly position within its Ns-block), so that consecutive lanes
+// read consecutive entries.
+//
+// Analysis loads the grid rows straight into the registers of the first
+// pass (thread of butterfly j loads elements j + t I/16 of both rows, which
+// is coalesced across the lanes); synthesis stores the last pass straight to
+// the grid rows (element j + t Ns3 of each of the two rows).
+// ---------------------------------------------------------------------------
+template <int I_, int R2_, int R3_>
+struct Plan3 {
+  static constexpr int I = I_, R1 = 16, R2 = R2_, R3 = R3_;
+  static_assert(R1 * R2 * R3 == I, "radices must multiply to I");
+  static constexpr int nb1 = I / R1, nb2 = I / R2, nb3 = I / R3;
+  static constexpr int Ns2 = R1, Ns3 = R1 * R2;
+  static_assert(nb3 == Ns3, "last pass");
+  static_assert(I % 16 == 0 && nb2 % 16 == 0, "padded layout");
+  static constexpr int IP = I + I / 16;        // padded field stride
+  static constexpr int S2P = nb2 + nb2 / 16;   // padded stride of pass-2 inputs
+  static constexpr int tw2 = 0, tw3 = (R2 - 1) * Ns2, ntw = tw3 + (R3 - 1) * Ns3;
+};
+
+template <typename T, class P, int NT, int FC>
+struct Fft3 {
+  static constexpr int S1 = (FC * P::nb1 + NT - 1) / NT;
+  static constexpr int S2 = (FC * P::nb2 + NT - 1) / NT;
+  static constexpr int S3 = (FC * P::nb3 + NT - 1) / NT;
+
+  // twiddles of passes two and three from the table exp(-2 pi i e / I)
+  static __device__ void stage_twiddles(cx<T>* twl, const cx<T>* __restrict__ twg) {
+    for (int x = threadIdx.x; x < P::ntw; x += NT) {
+      int e;
+      if (x < P::tw3) {
+        const int t = x / P::Ns2 + 1, k = x - (t - 1) * P::Ns2;
+        e = t * k * P::R3;
+      } else {
+        const int y = x - P::tw3;
+        const int t = y / P::Ns3 + 1, k = y - (t - 1) * P::Ns3;
+        e = t * k;
+      }
+      twl[x] = twg[e];
+    }
+  }
+
+  // first pass on values already in registers (v[s] = inputs j + t nb1 of
+  // slot s); results stored in the padded order
+  static __device__ __forceinline__ void pass1_store(cx<T> (&v)[S1][16], cx<T>* buf) {
+#pragma unroll
+    for (int s = 0; s < S1; ++s) {
+      const int u = threadIdx.x + s * NT;
+      if (u < FC * P::nb1) {
+        const int f = u / P::nb1, j = u - f * P::nb1;
+        Dft<T, 16>::run(v[s]);
+        cx<T>* d = buf + f * P::IP + 17 * j;
+#pragma unroll
+        for (int t = 0; t < 16; ++t) d[t] = v[s][t];
+      }
+    }
+  }
+
+  // first pass from the natural order in LDS (in place, padded result)
+  static __device__ __forceinline__ void pass1_lds(cx<T>* buf) {
+    cx<T> v[S1][16];
+#pragma unroll
+    for (int s = 0; s < S1; ++s) {
+      const int u = threadIdx.x + s * NT;
+      if (u < FC * P::nb1) {
+        const int f = u / P::nb1, j = u - f * P::nb1;
+        const cx<T>* src = buf + f * P::IP + j;
+#pragma unroll
+        for (int t = 0; t < 16; ++t) v[s][t] = src[t * P::nb1];
+      }
+    }
+    __syncthreads();
+    pass1_store(v, buf);
+    __syncthreads();
+  }
+
+  // second pass: padded order in, natural order out (in place)
+  static __device__ __forceinline__ void pass2(cx<T>* buf, const cx<T>* twl) {
+    constexpr int R = P::R2;
+    cx<T> v[S2][R];
+#pragma unroll
+    for (int s = 0; s < S2; ++s) {
+      const int u = threadIdx.x + s * NT;
+      if (u < FC * P::nb2) {
+        const int f = u / P::nb2, j = u - f * P::nb2;
+        const cx<T>* src = buf + f * P::IP + j + (j >> 4);
+#pragma unroll
+        for (int t = 0; t < R; ++t) v[s][t] = src[t * P::S2P];
+        const cx<T>* w = twl + P::tw2 + (j & 15);
+#pragma unroll
+        for (int t = 1; t < R; ++t) v[s][t] = cmul(v[s][t], w[(t - 1) * P::Ns2]);
+        Dft<T, R>::run(v[s]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < S2; ++s) {
+      const int u = threadIdx.x + s * NT;
+      if (u < FC * P::nb2) {
+        const int f = u / P::nb2, j = u - f * P::nb2;
+        cx<T>* d = buf + f * P::IP + (j >> 4) * (16 * R) + (j & 15);
+#pragma unroll
+        for (int t = 0; t < R; ++t) d[t * 16] = v[s][t];
+      }
+    }
+    __syncthreads();
+  }
+
+  // third pass into registers: v[s][t] is element j + t Ns3 of field f,
+  // (f, j) = slot s of this thread
+  static __device__ __forceinline__ void pass3_regs(cx<T> (&v)[S3][P::R3], const cx<T>* buf,
+                                                    const cx<T>* twl) {
+    constexpr int R = P::R3;
+#pragma unroll
+    for (int s = 0; s < S3; ++s) {
+      const int u = threadIdx.x + s * NT;
+      if (u < FC * P::nb3) {
+        const int f = u / P::nb3, j = u - f * P::nb3;
+        const cx<T>* src = buf + f * P::IP + j;
+#pragma unroll
+        for (int t = 0; t < R; ++t) v[s][t] = src[t * P::nb3];
+        const cx<T>* w = twl + P::tw3 + j;
+#pragma unroll
+        for (int t = 1; t < R; ++t) v[s][t] = cmul(v[s][t], w[(t - 1) * P::Ns3]);
+        Dft<T, R>::run(v[s]);
+      }
+    }
+  }
+};
+
+template <typename T, class P, int NT, int FB, int FC, int MS>
+__global__ __launch_bounds__(NT) void k_zonal_analysis_p3(const FftArgs a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  using F3 = Fft3<T, P, NT, FC>;
+  constexpr int NRD = FB / FC, I = P::I;
+  cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+  cx<T>* twl = buf + FC * P::IP;
+  const LevelDesc& L = a.lev[0];
+  const T* grid = static_cast<const T*>(a.src) + L.grid_off;
+  T* ws = static_cast<T*>(a.dst) + L.ws_off;
+  const T msc = (T)a.mscale;
+  const int N = L.N, J = L.J;
+
+  int item = blockIdx.x;
+  if (item >= a.nitems) return;
+  F3::stage_twiddles(twl, static_cast<const cx<T>*>(L.tw));
+
+  cx<T> v1[F3::S1][16];
+  auto load_rows = [&](int itm, int rd) {
+    const int jp = itm / L.nfb, fb = itm - jp * L.nfb;
+    const bool eq = (J & 1) && (jp == (J >> 1));
+#pragma unroll
+    for (int s = 0; s < F3::S1; ++s) {
+      const int u = threadIdx.x + s * NT;
+      if (u < FC * P::nb1) {
+        const int f = u / P::nb1, j = u - f * P::nb1;
+        const int fld = fb * FB + rd * FC + f;
+        const bool valid = fld < L.F;
+        const T* rn = grid + ((long long)fld * J + jp) * I + j;
+        const T* rs = grid + ((long long)fld * J + (J - 1 - jp)) * I + j;
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+          v1[s][t].x = valid ? rn[t * P::nb1] : (T)0;
+          v1[s][t].y = (valid && !eq) ? rs[t * P::nb1] : (T)0;
+        }
+      }
+    }
+  };
+
+  load_rows(item, 0);
+  for (; item < a.nitems; item += gridDim.x) {
+    const int jp = item / L.nfb, fb = item - jp * L.nfb;
+    const bool eq = (J & 1) && (jp == (J >> 1));
+    const T rscale = row_scale<T>(a, L, jp);
+    const int next = item + (int)gridDim.x;
+
+    cx<T> stS[MS][FB], stA[MS][FB];
+#pragma unroll
+    for (int rd = 0; rd < NRD; ++rd) {
+      F3::pass1_store(v1, buf);
+      __syncthreads();
+      if (rd + 1 < NRD)
+        load_rows(item, rd + 1);
+      else if (next < a.nitems)
+        load_rows(next, 0);
+      F3::pass2(buf, twl);
+      {
+        cx<T> v3[F3::S3][P::R3];
+        F3::pass3_regs(v3, buf, twl);
+        __syncthreads();
+        // only the bins m <= N and I - m (m <= N) are used by the fold
+#pragma unroll
+        for (int s = 0; s < F3::S3; ++s) {
+          const int u = threadIdx.x + s * NT;
+          if (u < FC * P::nb3) {
+            const int f = u / P::nb3, j = u - f * P::nb3;
+            cx<T>* d = buf + f * P::IP + j;
+#pragma unroll
+            for (int t = 0; t < P::R3; ++t) {
+              const int pos = j + t * P::Ns3;
+              if (pos <= N || pos >= I - N) d[t * P::Ns3] = v3[s][t];
+            }
+          }
+        }
+        __syncthreads();
+      }
+#pragma unroll
+      for (int s = 0; s < MS; ++s) {
+        const int m = threadIdx.x + s * NT;
+#pragma unroll
+        for (int fc = 0; fc < FC; ++fc) {
+          cx<T> S = {(T)0, (T)0}, A = {(T)0, (T)0};
+          if (m <= N) {
+            const cx<T> Pm = buf[fc * P::IP + m];
+            cx<T> Q = buf[fc * P::IP + (m == 0 ? 0 : I - m)];
+            Q.y = -Q.y;  // conj Z^{I-m}
+            const T h = (T)0.5;
+            const cx<T> Xn = {h * (Pm.x + Q.x), h * (Pm.y + Q.y)};
+            const cx<T> Xs = {h * (Pm.y - Q.y), -h * (Pm.x - Q.x)};
+            const T sc = m == 0 ? rscale : rscale * msc;
+            S = cx<T>{sc * (Xn.x + Xs.x), sc * (Xn.y + Xs.y)};
+            A = cx<T>{sc * (Xn.x - Xs.x), sc * (Xn.y - Xs.y)};
+            if (m == 0) {
+              S.y = (T)0;
+              A.y = (T)0;
+            }
+            if (eq) A = cx<T>{(T)0, (T)0};
+          }
+          stS[s][rd * FC + fc] = S;
+          stA[s][rd * FC + fc] = A;
+        }
+      }
+      __syncthreads();
+    }
+
+    const long long Cp = L.Cp;
+    const long long plane = (long long)L.Kp * Cp;
+#pragma unroll
+    for (int s = 0; s < MS; ++s) {
+      const int m = threadIdx.x + s * NT;
+      if (m <= N) {
+        T* dS = ws + (2LL * m) * plane + (long long)jp * Cp + 2 * fb * FB;
+        store_run<T, FB>(dS, stS[s]);
+        store_run<T, FB>(dS + plane, stA[s]);
+      }
+    }
+  }
+}
+
+template <typename T, class P, int NT, int FB, int FC, int MS>
+__global__ __launch_bounds__(NT) void k_zonal_synthesis_p3(const FftArgs a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  using F3 = Fft3<T, P, NT, FC>;
+  constexpr int NRD = FB / FC, I = P::I;
+  cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+  cx<T>* twl = buf + FC * P::IP;
+  const LevelDesc& L = a.lev[0];
+  const T* ws = static_cast<const T*>(a.src) + L.ws_off;
+  T* grid = static_cast<T*>(a.dst) + L.grid_off;
+  const T msc = (T)a.mscale;
+  const int N = L.N, J = L.J;
+  const long long Cp = L.Cp;
+  const long long plane = (long long)L.Kp * Cp;
+
+  cx<T> stS[MS][FB], stA[MS][FB];
+  auto load_ws = [&](int itm) {
+    const int jp = itm / L.nfb, fb = itm - jp * L.nfb;
+#pragma unroll
+    for (int s = 0; s < MS; ++s) {
+      const int m = threadIdx.x + s * NT;
+      if (m <= N) {
+        const T* sS = ws + (2LL * m) * plane + (long long)jp * Cp + 2 * fb * FB;
+        load_run<T, FB>(sS, stS[s]);
+        load_run<T, FB>(sS + plane, stA[s]);
+      } else {
+#pragma unroll
+        for (int q = 0; q < FB; ++q) stS[s][q] = stA[s][q] = cx<T>{(T)0, (T)0};
+      }
+    }
+  };
+
+  int item = blockIdx.x;
+  if (item >= a.nitems) return;
+  F3::stage_twiddles(twl, static_cast<const cx<T>*>(L.tw));
+  load_ws(item);
+  for (; item < a.nitems; item += gridDim.x) {
+    const int jp = item / L.nfb, fb = item - jp * L.nfb;
+    const bool eq = (J & 1) && (jp == (J >> 1));
+    const T rscale = row_scale<T>(a, L, jp);
+    const int next = item + (int)gridDim.x;
+
+#pragma unroll
+    for (int rd = 0; rd < NRD; ++rd) {
+#pragma unroll
+      for (int fc = 0; fc < FC; ++fc) {
+        cx<T>* bf = buf + fc * P::IP;
+        // zero the bins no thread fills: N < i < I-N
+        for (int i = N + 1 + threadIdx.x; i < I - N; i += NT) bf[i] = cx<T>{(T)0, (T)0};
+#pragma unroll
+        for (int s = 0; s < MS; ++s) {
+          const int m = threadIdx.x + s * NT;
+          if (m <= N) {
+            const cx<T> S = stS[s][rd * FC + fc], A = stA[s][rd * FC + fc];
+            const T sc = m == 0 ? (T)1 : msc;
+            cx<T> Xn = {sc * (S.x + A.x), sc * (S.y + A.y)};
+            cx<T> Xs = {sc * (S.x - A.x), sc * (S.y - A.y)};
+            if (m == 0) {
+              Xn.y = (T)0;
+              Xs.y = (T)0;
+            }
+            // conj(Z) with Z^m = Xn + i Xs and Z^{I-m} = conj(Xn) + i conj(Xs);
+            // the forward FFT of conj(Z) is the conjugate of the inverse one
+            bf[m] = cx<T>{Xn.x - Xs.y, -(Xn.y + Xs.x)};
+            if (m > 0) bf[I - m] = cx<T>{Xn.x + Xs.y, Xn.y - Xs.x};
+          }
+        }
+      }
+      __syncthreads();
+      if (rd + 1 == NRD && next < a.nitems) load_ws(next);
+      F3::pass1_lds(buf);
+      F3::pass2(buf, twl);
+      cx<T> v3[F3::S3][P::R3];
+      F3::pass3_regs(v3, buf, twl);
+#pragma unroll
+      for (int s = 0; s < F3::S3; ++s) {
+        const int u = threadIdx.x + s * NT;
+        if (u < FC * P::nb3) {
+          const int f = u / P::nb3, j = u - f * P::nb3;
+          const int fld = fb * FB + rd * FC + f;
+          if (fld < L.F) {
+            T* rn = grid + ((long long)fld * J + jp) * I + j;
+            T* rs = grid + ((long long)fld * J + (J - 1 - jp)) * I + j;
+#pragma unroll
+            for (int t = 0; t < P::R3; ++t) rn[t * P::Ns3] = rscale * v3[s][t].x;
+            if (!eq) {
+#pragma unroll
+              for (int t = 0; t < P::R3; ++t) rs[t * P::Ns3] = -rscale * v3[s][t].y;
+            }
+          }
+        }
+      }
+      __syncthreads();  // the next round refills the buffer
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 // LDS per workgroup on gfx950 is 160 KiB; above 64 KiB a kernel has to opt in.
@@ -613,8 +1065,70 @@ static hipError_t launch_cfg(bool analysis, const FftArgs& a, int maxI, hipStrea
   return hipGetLastError();
 }
 
+template <typename T, class P, int NT, int FB, int FC, int MS>
+static hipError_t launch_p3_ms(bool analysis, const FftArgs& a, hipStream_t st) {
+  const size_t lds = (size_t)(FC * P::IP + P::ntw) * sizeof(cx<T>);
+  int per_cu = (int)(kMaxLds / lds);
+  const int by_waves = 2048 / NT;
+  per_cu = per_cu < by_waves ? per_cu : by_waves;
+  per_cu = per_cu < 1 ? 1 : per_cu;
+  int nwg = g_num_cu * per_cu;
+  nwg = nwg < a.nitems ? nwg : a.nitems;
+  const dim3 grid(nwg), block(NT);
+  if (analysis) {
+    lds_optin<k_zonal_analysis_p3<T, P, NT, FB, FC, MS>>(lds);
+    hipLaunchKernelGGL((k_zonal_analysis_p3<T, P, NT, FB, FC, MS>), grid, block, lds, st, a);
+  } else {
+    lds_optin<k_zonal_synthesis_p3<T, P, NT, FB, FC, MS>>(lds);
+    hipLaunchKernelGGL((k_zonal_synthesis_p3<T, P, NT, FB, FC, MS>), grid, block, lds, st, a);
+  }
+  return hipGetLastError();
+}
+
+template <typename T, class P, int NT, int FB, int FC>
+static hipError_t launch_p3(bool analysis, const FftArgs& a, int maxN, hipStream_t st) {
+  static_assert(FB % FC == 0, "field rounds");
+  constexpr int MSMAX = ((P::I + 1) / 2 + NT - 1) / NT;  // N + 1 <= (I + 1) / 2
+  static_assert(MSMAX <= 3, "wavenumbers per thread");
+  const int nm = maxN + 1;
+  if constexpr (MSMAX >= 3)
+    if (nm > 2 * NT) return launch_p3_ms<T, P, NT, FB, FC, 3>(analysis, a, st);
+  if constexpr (MSMAX >= 2)
+    if (nm > NT) return launch_p3_ms<T, P, NT, FB, FC, 2>(analysis, a, st);
+  return launch_p3_ms<T, P, NT, FB, FC, 1>(analysis, a, st);
+}
+
+// Single-level plans whose I has a compile-time three-pass plan.
+template <typename T, int FB>
+static bool launch_fixed(bool analysis, const FftArgs& a, int maxN, hipStream_t st, hipError_t* err) {
+  if (a.nlev != 1) return false;
+  constexpr bool dbl = sizeof(T) == 8;
+  switch (a.lev[0].I) {
+    case 2880:
+      *err = launch_p3<T, Plan3<2880, 12, 15>, 512, FB, dbl ? 2 : 4>(analysis, a, maxN, st);
+      return true;
+    case 1440:
+      *err = launch_p3<T, Plan3<1440, 9, 10>, 512, FB, dbl ? 2 : 4>(analysis, a, maxN, st);
+      return true;
+    case 480:
+      *err = launch_p3<T, Plan3<480, 6, 5>, 256, FB, dbl ? 4 : 8>(analysis, a, maxN, st);
+      return true;
+    default:
+      return false;
+  }
+}
+
 template <typename T, int FB, int FC>
 static hipError_t launch_zonal_t(bool analysis, const FftArgs& a, int maxN, hipStream_t st) {
+  if (g_num_cu == 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&g_num_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        g_num_cu <= 0)
+      g_num_cu = 256;
+  }
+  hipError_t err = hipSuccess;
+  if (launch_fixed<T, FB>(analysis, a, maxN, st, &err)) return err;
   int maxI = 0;
   for (int l = 0; l < a.nlev; ++l) maxI = a.lev[l].I > maxI ? a.lev[l].I : maxI;
   const int nm = maxN + 1;

@@ -90,6 +90,29 @@ def test_multi_tile_parity(form, kind, N, J, I, F):
 
 
 @pytest.mark.parametrize("form", FORMS)
+@pytest.mark.parametrize("kind,N,J,I,F", [
+    ("cc_poles", 200, 101, 480, 5),     # I = 16*6*5, one wavenumber per thread
+    ("fejer2", 239, 478, 480, 11),      # N = (I-1)/2, even J, ragged field block
+    ("fejer2", 700, 97, 1440, 9),       # I = 16*9*10, two wavenumbers per thread
+    ("cc_poles", 30, 33, 2880, 2),      # I = 16*12*15, most bins zero
+    ("cc_poles", 1040, 40, 2880, 3),    # N + 1 > 1024: three wavenumbers per thread
+])
+def test_fixed_length_plans(form, kind, N, J, I, F):
+    """Lengths with a compile-time three-pass FFT plan, away from the
+    benchmark truncations: every wavenumber count per thread, ragged field
+    blocks, both grids, odd and even J."""
+    _roundtrip_case(N, J, I, F, kind, form, profile="k3", seed=N + J)
+    p = _plan(N, J, I, F, kind, form)
+    sb = _to_dev(inputs.random_spectra(N, F, seed=6, profile="inv1"), form)
+    gb = _to_dev(inputs.random_grid(F, J, I, seed=7), form)
+    x = p.forward_adjoint(sb)
+    assert rel(_host(x), O.forward_adjoint(_host(sb), N, J, I, kind)) < TOL[form]
+    y = p.inverse_adjoint(gb)
+    assert rel(_host(y), O.inverse_adjoint(_host(gb), N, kind)) < TOL[form]
+    p.close()
+
+
+@pytest.mark.parametrize("form", FORMS)
 @pytest.mark.parametrize("kind", O.GRID_KINDS)
 def test_random_grid_forward(form, kind):
     """Analysis of a grid that is not band-limited is still the oracle's map."""
