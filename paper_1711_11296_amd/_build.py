@@ -23,6 +23,10 @@ CXX_SOURCES = ["sht_host.cpp"]
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-I" + CSRC, "-I" + os.path.join(os.path.dirname(HERE), "include")]
 HIP_FLAGS = COMMON + ["--offload-arch=" + ARCH, "-mcode-object-version=5",
                       "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                      # keep MFMA accumulators in ordinary VGPRs: with the
+                      # accumulation-register form the compiler copies every
+                      # accumulator out and back once per K-block
+                      "-mllvm", "-amdgpu-mfma-vgpr-form=1",
                       "-Wno-unused-result"]
 
 

@@ -198,7 +198,12 @@ std::vector<Tile> xcd_schedule(const std::vector<Tile>& tiles, const std::vector
 }
 
 // Fill both copies of one level's table from FP64 columns of P~:
-//  analysis copy: per m, rows r = n - m padded to SHT_ROWS_PAD, Kp columns;
+//  analysis copy: per m, rows r = n - m padded to 128, blocked in the order
+//  the analysis kernel streams it: per (128-row tile, KB-column block) one
+//  contiguous chunk (KB = 32 for float, 16 for double), inside it one run
+//  per wave (16 rows r = 32 q + 2 i + p), inside that one 64-lane vector
+//  after the other: vector v of lane (i, g) holds columns 4 (v E + e) + g,
+//  e < E = 16 bytes / element size;
 //  synthesis copy: per m, blocks (64-row j block, 32-row r block), each
 //  laid out [parity][64 j][16 r'] with r = 32 kb + 2 r' + parity.
 // Tile list of one Legendre kernel for column blocking ncb (16*ncb columns
@@ -217,7 +222,9 @@ std::vector<Tile> build_tiles(const sht_plan_s* P, bool analysis, int ncb, int s
       const int nm = L.N - m + 1;
       for (int cb = 0; cb < ncol; ++cb) {
         if (analysis) {
-          for (int rb = 0; rb < (nm + 63) / 64; ++rb) {
+          // 128-row tiles for the FP32/FP64 kernels, 64 for the split form
+          const int rows = P->form == SHT_FORM_BF16X6 ? 64 : 128;
+          for (int rb = 0; rb < (nm + rows - 1) / rows; ++rb) {
             t.push_back(Tile{l, m, rb, cb});
             c.push_back((double)L.Kp * BN);
           }
@@ -251,10 +258,20 @@ void fill_table_level(const LevelDesc& L, const double* mu, const double* sint,
         col.assign((size_t)nm * Jh, 0.0);
         alf_column(N, m, Jh, mu, sint, col.data(), Jh);
         T* blk = dst + off_a[m];
-        const int R = (int)roundup(nm, SHT_ROWS_PAD);
+        const int R = (int)roundup(nm, 128);
+        constexpr int KB = sizeof(T) == 4 ? 32 : 16, E = 16 / (int)sizeof(T);
+        const int nkbk = Kp / KB;
         for (int r = 0; r < R; ++r)
-          for (int j = 0; j < Kp; ++j)
-            blk[(size_t)r * Kp + j] = (r < nm && j < Jh) ? (T)col[(size_t)r * Jh + j] : (T)0;
+          for (int j = 0; j < Kp; ++j) {
+            const int rt = r / 128, rr = r % 128;
+            const int q = rr / 32, i = (rr % 32) / 2, p = rr % 2;
+            const int kb = j / KB, jj = j % KB;
+            const int g = jj % 4, kk = jj / 4;
+            const int v = kk / E, e = kk % E;
+            const size_t d = ((size_t)rt * nkbk + kb) * 128 * KB + (size_t)(2 * q + p) * 16 * KB +
+                             (size_t)((v * 4 + g) * 16 + i) * E + e;
+            blk[d] = (r < nm && j < Jh) ? (T)col[(size_t)r * Jh + j] : (T)0;
+          }
         const int nkb = (nm + 31) / 32;
         T* sb = dsyn + off_s[m];
         for (int jb = 0; jb < JB; ++jb)
@@ -411,7 +428,8 @@ int build_plan(int nlev, const int* Nv, const int* Jv, const int* Iv, const int*
     woff += roundup((long long)(L.N + 1) * 2 * L.Kp * L.Cp, 64);
     for (int m = 0; m <= L.N; ++m) {
       taboff.push_back(tab);
-      tab += roundup(L.N - m + 1, SHT_ROWS_PAD) * L.Kp;
+      // analysis copy: rows padded to the row tile (128; 64 in the split form)
+      tab += roundup(L.N - m + 1, o.form == SHT_FORM_BF16X6 ? SHT_ROWS_PAD : 128) * L.Kp;
       taboff_syn.push_back(tabs);
       if (o.form == SHT_FORM_BF16X6)
         tabs += (long long)((L.Jh + 63) / 64) * ((L.N - m + 1 + 63) / 64) * 4096;

@@ -24,6 +24,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "sht_internal.h"
 
 namespace sht {
@@ -62,6 +64,23 @@ __device__ __forceinline__ long long spec_idx(int N, int m, int n) {
   return (long long)m * (2 * N + 3 - m) / 2 + (n - m);
 }
 
+// Instruction-order hint for a K-block body (scheduling groups of the
+// compiler, no effect on results): PRE LDS reads first, then ROUNDS times
+// PER MFMAs followed by one LDS read, then TAIL MFMAs.  It keeps the LDS
+// reads of a k-step ahead of the MFMAs that consume them, which the default
+// schedule (each read right before its first use) does not.
+template <int PRE, int ROUNDS, int PER, int TAIL>
+__device__ __forceinline__ void mfma_lds_pipeline() {
+#pragma unroll
+  for (int i = 0; i < PRE; ++i) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+#pragma unroll
+  for (int i = 0; i < ROUNDS; ++i) {
+    __builtin_amdgcn_sched_group_barrier(0x008, PER, 0);
+    __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+  }
+  if constexpr (TAIL > 0) __builtin_amdgcn_sched_group_barrier(0x008, TAIL, 0);
+}
+
 template <typename T>
 struct V16;
 template <>
@@ -87,157 +106,172 @@ __device__ __forceinline__ void lds_store8(T* dst, const typename V16<T>::type& 
 
 // ---------------------------------------------------------------------------
 // analysis: C[n][c] = P[n][j] * B_par(n)[j][c]
-// tile = 64 consecutive rows r = n - m (both parities) x BN = 16*NCB columns.
-// wave w: parity p = w & 1 and column half ch = w >> 1; it owns the 32 rows
-// r = 2 i + p (two 16-row MFMA blocks) and HC = ceil(NCB/2) column blocks.
-// The contraction runs over j in blocks of KB with a register prefetch of
-// the next block while the matrix cores work on the current one.
+// tile = 128 consecutive rows r = n - m (both parities) x BN = 16*NCB
+// columns, 8 waves.  Wave w: parity p = w & 1, row quarter q = w >> 1; it
+// owns the 16 rows r = 32 q + 2 i + p (one MFMA row block) and all NCB
+// column blocks.
+// The contraction runs over j in blocks of KB.  Lane (i, g) of a wave
+// supplies the k values j = 4 kk + g (kk < KB/4) of its row.  The analysis
+// copy of the table is blocked per (128-row tile, KB columns) and, inside a
+// block, per wave and per 64-lane vector, so that each wave streams its
+// operands with fully contiguous 1 KiB loads straight into registers.
+// The right-hand operand (both parities of the workspace block) goes through
+// LDS in two stages: block kb+1 is fetched into registers while the matrix
+// cores work on block kb and stored into the other stage afterwards, so one
+// barrier per block suffices.
 // ---------------------------------------------------------------------------
 template <typename T, int NCB>
-__global__ __launch_bounds__(256) void k_legendre_analysis(const GemmArgs g) {
+struct AnalysisShape {
+  static constexpr int E = 16 / (int)sizeof(T);        // scalars per 16 bytes
+  static constexpr int KB = sizeof(T) == 4 ? 32 : 16;  // contraction block
+  static constexpr int KQ = KB / 4;                    // k values per lane and block
+  static constexpr int BN = 16 * NCB;
+  // row pitch of the LDS operand: lanes g = 0..3 read rows g + 4 kk; for FP32
+  // a pitch of 16 mod 32 words puts the four groups on alternate bank halves
+  static constexpr int BS = BN + (sizeof(T) == 4 ? 16 : 2);
+  static constexpr int STAGE = 2 * KB * BS;            // elements of one stage
+  static constexpr int BV = 2 * KB * BN / E;           // 16-byte vectors per block
+  static constexpr int NB = (BV + 511) / 512;
+  static constexpr int CS = BN + 1;                    // staging pitch of the output
+  static constexpr size_t lds_bytes() {
+    const size_t main = (size_t)2 * STAGE * sizeof(T);
+    const size_t cst = (size_t)64 * CS * sizeof(T);
+    return main > cst ? main : cst;
+  }
+};
+
+template <typename T, int NCB>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_legendre_analysis(const GemmArgs g) {
   typedef typename Acc<T>::type AccT;
   typedef typename V16<T>::type V;
-  constexpr int E = 16 / (int)sizeof(T);           // scalars per 16 bytes
-  constexpr int KB = sizeof(T) == 4 ? 32 : 16;    // contraction block
-  constexpr int KQ = KB / 4;                       // k-steps per block
-  constexpr int BN = 16 * NCB;
-  constexpr int HC = (NCB + 1) / 2;                // column blocks per wave
-  constexpr int AS = KB + E;                       // odd number of 16-byte units
-  constexpr int BS = BN + 2;                       // conflict-free B reads
-  constexpr int NA = 64 * KB / E / 256;            // A vectors per thread
-  constexpr int NB = 2 * KB * BN / E / 256;        // B vectors per thread
+  using S = AnalysisShape<T, NCB>;
+  constexpr int E = S::E, KB = S::KB, KQ = S::KQ, BN = S::BN, BS = S::BS;
 
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* As = reinterpret_cast<T*>(smem_raw);          // [2 parity][32][AS]
-  T* Bs = As + 64 * AS;                            // [2][KB][BS]
+  T* Bs = reinterpret_cast<T*>(smem_raw);          // [2 stage][2 parity][KB][BS]
 
   const Tile t = g.tiles[blockIdx.x];
   if (t.level < 0) return;
   const LevelDesc& L = g.lev[t.level];
   const int N = L.N, m = t.m;
   const int nm = N - m + 1;
-  const int r0 = t.rb * 64;
+  const int r0 = t.rb * 128;
   const int c0 = t.cb * BN;
   const int Kp = L.Kp;
   const long long Cp = L.Cp;
-  const T* tab = static_cast<const T*>(g.table) + g.tab_off[L.m_base + m] + (long long)r0 * Kp;
   const long long plane = (long long)Kp * Cp;
   const T* wsm = static_cast<const T*>(g.ws) + L.ws_off + (2LL * m) * plane + c0;
 
   const int tid = threadIdx.x;
-  const int w = tid >> 6, lane = tid & 63;
-  const int p = w & 1, ch = w >> 1;
+  // wave-uniform values live in scalar registers
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  const int p = w & 1, q = w >> 1;
   const int li = lane & 15, lg = lane >> 4;
-  bool act[2];
-  act[0] = (r0 + p) < nm;
-  act[1] = (r0 + 32 + p) < nm;
+  const bool active = r0 + 32 * q + p < nm;
+  // this wave's run of the blocked table (see the table layout above)
+  const T* arow = static_cast<const T*>(g.table) + g.tab_off[L.m_base + m] +
+                  (long long)t.rb * Kp * 128 + w * 16 * KB + lane * E;
 
-  AccT acc[2][HC];
+  AccT acc[NCB];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int c = 0; c < HC; ++c) acc[a][c] = AccT{0, 0, 0, 0};
+  for (int c = 0; c < NCB; ++c) acc[c] = AccT{0, 0, 0, 0};
 
-  V ra[NA], rb[NB];
-  auto gload = [&](int k0) {
+  V an[KQ / E], ac[KQ / E];
+  V rb[S::NB];
+  auto gload = [&](int kb) {
+    if (active) {
 #pragma unroll
-    for (int i = 0; i < NA; ++i) {
-      const int q = tid + i * 256;
-      const int row = q / (KB / E), cv = q % (KB / E);
-      ra[i] = *reinterpret_cast<const V*>(tab + (long long)row * Kp + k0 + cv * E);
+      for (int v = 0; v < KQ / E; ++v) an[v] = *reinterpret_cast<const V*>(arow + kb * 128 * KB + v * 64 * E);
     }
 #pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      const int q = tid + i * 256;
-      const int par = q / (KB * BN / E);
-      const int rem = q - par * (KB * BN / E);
-      const int row = rem / (BN / E), cv = rem % (BN / E);
-      rb[i] = *reinterpret_cast<const V*>(wsm + par * plane + (long long)(k0 + row) * Cp + cv * E);
+    for (int i = 0; i < S::NB; ++i) {
+      const int qq = tid + i * 512;
+      if (S::NB * 512 == S::BV || qq < S::BV) {
+        const int par = qq / (KB * BN / E);
+        const int rem = qq - par * (KB * BN / E);
+        const int row = rem / (BN / E), cv = rem % (BN / E);
+        rb[i] = *reinterpret_cast<const V*>(wsm + par * plane + (long long)(kb * KB + row) * Cp + cv * E);
+      }
     }
   };
-  auto lstore = [&]() {
+  auto lstore = [&](int stage) {
+    T* dst = Bs + stage * S::STAGE;
 #pragma unroll
-    for (int i = 0; i < NA; ++i) {
-      const int q = tid + i * 256;
-      const int row = q / (KB / E), cv = q % (KB / E);
-      *reinterpret_cast<V*>(As + ((row & 1) * 32 + (row >> 1)) * AS + cv * E) = ra[i];
-    }
-#pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      const int q = tid + i * 256;
-      const int par = q / (KB * BN / E);
-      const int rem = q - par * (KB * BN / E);
-      const int row = rem / (BN / E), cv = rem % (BN / E);
-      lds_store8<T>(Bs + (par * KB + row) * BS + cv * E, rb[i]);
+    for (int i = 0; i < S::NB; ++i) {
+      const int qq = tid + i * 512;
+      if (S::NB * 512 == S::BV || qq < S::BV) {
+        const int par = qq / (KB * BN / E);
+        const int rem = qq - par * (KB * BN / E);
+        const int row = rem / (BN / E), cv = rem % (BN / E);
+        *reinterpret_cast<V*>(dst + (par * KB + row) * BS + cv * E) = rb[i];
+      }
     }
   };
 
   const int nkb = Kp / KB;
   gload(0);
-  lstore();
+  lstore(0);
+#pragma unroll
+  for (int v = 0; v < KQ / E; ++v) ac[v] = an[v];
   __syncthreads();
   for (int kb = 0; kb < nkb; ++kb) {
-    if (kb + 1 < nkb) gload((kb + 1) * KB);
-    // operands of this wave: rows 2*(16*rb2 + li) + p, k = lg*KQ + kk
-    T av[2][KQ];
+    const bool more = kb + 1 < nkb;
+    if (more) gload(kb + 1);
+    if (active) {
+      T a[KQ];
 #pragma unroll
-    for (int rb2 = 0; rb2 < 2; ++rb2) {
-      const T* Ap = As + (p * 32 + 16 * rb2 + li) * AS + lg * KQ;
+      for (int v = 0; v < KQ / E; ++v)
 #pragma unroll
-      for (int v = 0; v < KQ / E; ++v) {
-        const V x = *reinterpret_cast<const V*>(Ap + v * E);
+        for (int e = 0; e < E; ++e) a[v * E + e] = ac[v][e];
+      const T* Bp = Bs + (kb & 1) * S::STAGE + (p * KB + lg) * BS + li;
 #pragma unroll
-        for (int e = 0; e < E; ++e) av[rb2][v * E + e] = x[e];
+      for (int kk = 0; kk < KQ; ++kk) {
+        T bv[NCB];
+#pragma unroll
+        for (int c = 0; c < NCB; ++c) bv[c] = Bp[4 * kk * BS + c * 16];
+#pragma unroll
+        for (int c = 0; c < NCB; ++c) acc[c] = mfma16(a[kk], bv[c], acc[c]);
       }
+      // B reads run two k-steps ahead (paired reads of two columns)
+      constexpr int RD = (NCB + 1) / 2;
+      mfma_lds_pipeline<2 * RD, (KQ - 2) * RD, (NCB + RD - 1) / RD, 2 * NCB>();
     }
-    const T* Bp = Bs + (p * KB + lg * KQ) * BS + li;
+    if (more) {
+      lstore((kb + 1) & 1);
 #pragma unroll
-    for (int kk = 0; kk < KQ; ++kk) {
-#pragma unroll
-      for (int c = 0; c < HC; ++c) {
-        const int cb = ch * HC + c;
-        if (cb < NCB) {
-          const T b = Bp[kk * BS + cb * 16];
-          if (act[0]) acc[0][c] = mfma16(av[0][kk], b, acc[0][c]);
-          if (act[1]) acc[1][c] = mfma16(av[1][kk], b, acc[1][c]);
-        }
-      }
+      for (int v = 0; v < KQ / E; ++v) ac[v] = an[v];
     }
     __syncthreads();
-    if (kb + 1 < nkb) {
-      lstore();
-      __syncthreads();
-    }
   }
 
-  // stage the 64 x BN tile in LDS, then write spec rows contiguously
-  constexpr int CS = BN + 1;
-  T* Cs = As;  // [64][CS]
-#pragma unroll
-  for (int rb2 = 0; rb2 < 2; ++rb2)
-#pragma unroll
-    for (int c = 0; c < HC; ++c) {
-      const int cb = ch * HC + c;
-      if (cb < NCB) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int rl = 2 * (16 * rb2 + out_row<T>(lg, i)) + p;
-          Cs[rl * CS + cb * 16 + li] = acc[rb2][c][i];
-        }
-      }
-    }
-  __syncthreads();
+  // stage 64 rows at a time in LDS, then write spec rows contiguously
+  T* Cs = Bs;  // [64][CS]
   T* spec = static_cast<T*>(g.spec_out) + L.spec_off;
   const long long nc = (long long)(N + 1) * (N + 2) / 2;
-  const long long base = spec_idx(N, m, m) + r0;
-  for (int q = tid; q < 64 * (BN / 2); q += 256) {
-    const int fl = q >> 6, rl = q & 63;
-    const int f = (c0 >> 1) + fl;
-    if (r0 + rl < nm && f < L.F) {
-      T* d = spec + ((long long)f * nc + base + rl) * 2;
-      d[0] = Cs[rl * CS + 2 * fl];
-      d[1] = Cs[rl * CS + 2 * fl + 1];
+  const long long base = spec_idx(N, m, m);
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    if ((q >> 1) == h) {
+#pragma unroll
+      for (int c = 0; c < NCB; ++c)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int rl = 32 * (q & 1) + 2 * out_row<T>(lg, i) + p;
+          Cs[rl * S::CS + c * 16 + li] = acc[c][i];
+        }
     }
+    __syncthreads();
+    for (int qq = tid; qq < 64 * (BN / 2); qq += 512) {
+      const int fl = qq >> 6, rl = qq & 63;
+      const int f = (c0 >> 1) + fl;
+      const int r = r0 + 64 * h + rl;
+      if (r < nm && f < L.F) {
+        T* d = spec + ((long long)f * nc + base + r) * 2;
+        d[0] = Cs[rl * S::CS + 2 * fl];
+        d[1] = Cs[rl * S::CS + 2 * fl + 1];
+      }
+    }
+    if (h == 0) __syncthreads();
   }
 }
 
@@ -282,9 +316,10 @@ __global__ __launch_bounds__(256) void k_legendre_synthesis(const GemmArgs g) {
   const long long sbase = spec_idx(N, m, m);
 
   const int tid = threadIdx.x;
-  const int w = tid >> 6, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int p = w & 1, ch = w >> 1;
   const int li = lane & 15, lg = lane >> 4;
+  const bool full_cols = ch == 0;  // HC column blocks, else NCB - HC
 
   AccT acc[4][HC];
 #pragma unroll
@@ -345,41 +380,53 @@ __global__ __launch_bounds__(256) void k_legendre_synthesis(const GemmArgs g) {
     }
   };
 
-  gload(0);
-  lstore();
-  __syncthreads();
-  for (int kb = 0; kb < nkb; ++kb) {
-    if (kb + 1 < nkb) gload(kb + 1);
-    T av[4][4];
-#pragma unroll
-    for (int jr = 0; jr < 4; ++jr) {
-      const T* Ap = At + (p * 64 + 16 * jr + li) * AS + lg * 4;
-#pragma unroll
-      for (int v = 0; v < 4 / E + (E > 4 ? 1 : 0); ++v) {
-        const V x = *reinterpret_cast<const V*>(Ap + v * E);
-#pragma unroll
-        for (int e = 0; e < E && v * E + e < 4; ++e) av[jr][v * E + e] = x[e];
-      }
-    }
-    const T* Bp = Bs + (p * KH + lg * 4) * BS + li;
-#pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-#pragma unroll
-      for (int c = 0; c < HC; ++c) {
-        const int cb = ch * HC + c;
-        if (cb < NCB) {
-          const T b = Bp[kk * BS + cb * 16];
-#pragma unroll
-          for (int jr = 0; jr < 4; ++jr) acc[jr][c] = mfma16(av[jr][kk], b, acc[jr][c]);
-        }
-      }
-    }
+  auto kloop = [&](auto ncc) {
+    constexpr int NC = decltype(ncc)::value;
+    gload(0);
+    lstore();
     __syncthreads();
-    if (kb + 1 < nkb) {
-      lstore();
+    for (int kb = 0; kb < nkb; ++kb) {
+      if (kb + 1 < nkb) gload(kb + 1);
+      if constexpr (NC > 0) {
+        T av[4][4];
+#pragma unroll
+        for (int jr = 0; jr < 4; ++jr) {
+          const T* Ap = At + (p * 64 + 16 * jr + li) * AS + lg * 4;
+#pragma unroll
+          for (int v = 0; v < 4 / E + (E > 4 ? 1 : 0); ++v) {
+            const V x = *reinterpret_cast<const V*>(Ap + v * E);
+#pragma unroll
+            for (int e = 0; e < E && v * E + e < 4; ++e) av[jr][v * E + e] = x[e];
+          }
+        }
+        const T* Bp = Bs + (p * KH + lg * 4) * BS + ch * HC * 16 + li;
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          T bv[NC];
+#pragma unroll
+          for (int c = 0; c < NC; ++c) bv[c] = Bp[kk * BS + c * 16];
+#pragma unroll
+          for (int c = 0; c < NC; ++c)
+#pragma unroll
+            for (int jr = 0; jr < 4; ++jr) acc[jr][c] = mfma16(av[jr][kk], bv[c], acc[jr][c]);
+        }
+        // A reads and the B reads of two k-steps first, then the B reads of
+        // the later steps between the MFMAs
+        constexpr int RD = (NC + 1) / 2;
+        constexpr int NAR = 4 * (4 / E > 0 ? 4 / E : 1);
+        mfma_lds_pipeline<NAR + 2 * RD, 2 * RD, (4 * NC + RD - 1) / RD, 8 * NC>();
+      }
       __syncthreads();
+      if (kb + 1 < nkb) {
+        lstore();
+        __syncthreads();
+      }
     }
-  }
+  };
+  if (full_cols || 2 * HC == NCB)
+    kloop(std::integral_constant<int, HC>{});
+  else
+    kloop(std::integral_constant<int, NCB - HC>{});
 
   const long long plane = (long long)L.Kp * Cp;
   T* ws = static_cast<T*>(g.ws) + L.ws_off + (2LL * m + p) * plane;
@@ -489,12 +536,13 @@ __global__ __launch_bounds__(256) void k_legendre_analysis_bf16(const GemmArgs g
   const float* wsm = static_cast<const float*>(g.ws) + L.ws_off + (2LL * m) * plane + c0;
 
   const int tid = threadIdx.x;
-  const int w = tid >> 6, lane = tid & 63;
+  // wave-uniform values live in scalar registers, so the per-wave choices
+  // below are scalar branches around whole K-blocks
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int p = w & 1, ch = w >> 1;
   const int li = lane & 15, lg = lane >> 4;
-  bool act[2];
-  act[0] = (r0 + p) < nm;
-  act[1] = (r0 + 32 + p) < nm;
+  const int nrb = (r0 + 32 + p) < nm ? 2 : ((r0 + p) < nm ? 1 : 0);  // active row blocks
+  const bool full_cols = ch == 0;  // HC column blocks, else NCB - HC
 
   f32x4 acc[2][HC];
 #pragma unroll
@@ -540,36 +588,57 @@ __global__ __launch_bounds__(256) void k_legendre_analysis_bf16(const GemmArgs g
   };
 
   const int nkb = Kp / KB;
-  gload(0);
-  lstore();
-  __syncthreads();
-  for (int kb = 0; kb < nkb; ++kb) {
-    if (kb + 1 < nkb) gload((kb + 1) * KB);
-    bf16x8 av[2][3];
+  auto kloop = [&](auto nrc, auto ncc) {
+    constexpr int NR = decltype(nrc)::value, NC = decltype(ncc)::value;
+    gload(0);
+    lstore();
+    __syncthreads();
+    for (int kb = 0; kb < nkb; ++kb) {
+      if (kb + 1 < nkb) gload((kb + 1) * KB);
+      if constexpr (NR > 0 && NC > 0) {
+        bf16x8 av[NR][3];
 #pragma unroll
-    for (int rb2 = 0; rb2 < 2; ++rb2)
+        for (int rb2 = 0; rb2 < NR; ++rb2)
 #pragma unroll
-      for (int pc = 0; pc < 3; ++pc)
-        av[rb2][pc] = __builtin_bit_cast(
-            bf16x8, *reinterpret_cast<const u32x4*>(As + ((pc * 2 + p) * 32 + 16 * rb2 + li) * AS + 8 * lg));
+          for (int pc = 0; pc < 3; ++pc)
+            av[rb2][pc] = __builtin_bit_cast(
+                bf16x8, *reinterpret_cast<const u32x4*>(As + ((pc * 2 + p) * 32 + 16 * rb2 + li) * AS + 8 * lg));
 #pragma unroll
-    for (int c = 0; c < HC; ++c) {
-      const int cb = ch * HC + c;
-      if (cb < NCB) {
-        float bv[8];
+        for (int c = 0; c < NC; ++c) {
+          const int cb = ch * HC + c;
+          float bv[8];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) bv[e] = Bs[(p * KB + 8 * lg + e) * BS + cb * 16 + li];
-        bf16x8 b0, b1, b2;
-        split3x8(bv, b0, b1, b2);
-        if (act[0]) acc[0][c] = mfma6(av[0], b0, b1, b2, acc[0][c]);
-        if (act[1]) acc[1][c] = mfma6(av[1], b0, b1, b2, acc[1][c]);
+          for (int e = 0; e < 8; ++e) bv[e] = Bs[(p * KB + 8 * lg + e) * BS + cb * 16 + li];
+          bf16x8 b0, b1, b2;
+          split3x8(bv, b0, b1, b2);
+#pragma unroll
+          for (int r = 0; r < NR; ++r) acc[r][c] = mfma6(av[r], b0, b1, b2, acc[r][c]);
+        }
+      }
+      __syncthreads();
+      if (kb + 1 < nkb) {
+        lstore();
+        __syncthreads();
       }
     }
-    __syncthreads();
-    if (kb + 1 < nkb) {
-      lstore();
-      __syncthreads();
-    }
+  };
+  using I0 = std::integral_constant<int, 0>;
+  using I1 = std::integral_constant<int, 1>;
+  using I2 = std::integral_constant<int, 2>;
+  using CH = std::integral_constant<int, HC>;
+  using CL = std::integral_constant<int, NCB - HC>;
+  if (nrb == 0) {
+    kloop(I0{}, CH{});
+  } else if (full_cols || 2 * HC == NCB) {
+    if (nrb == 2)
+      kloop(I2{}, CH{});
+    else
+      kloop(I1{}, CH{});
+  } else {
+    if (nrb == 2)
+      kloop(I2{}, CL{});
+    else
+      kloop(I1{}, CL{});
   }
 
   constexpr int CS = BN + 1;
@@ -636,9 +705,10 @@ __global__ __launch_bounds__(256) void k_legendre_synthesis_bf16(const GemmArgs 
   const long long sbase = spec_idx(N, m, m);
 
   const int tid = threadIdx.x;
-  const int w = tid >> 6, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int p = w & 1, ch = w >> 1;
   const int li = lane & 15, lg = lane >> 4;
+  const bool full_cols = ch == 0;  // HC column blocks, else NCB - HC
 
   f32x4 acc[4][HC];
 #pragma unroll
@@ -701,15 +771,16 @@ __global__ __launch_bounds__(256) void k_legendre_synthesis_bf16(const GemmArgs 
     }
   };
 
-  gload(0);
-  lstore();
-  __syncthreads();
-  for (int kb = 0; kb < nkb; ++kb) {
-    if (kb + 1 < nkb) gload(kb + 1);
+  auto kloop = [&](auto ncc) {
+    constexpr int NC = decltype(ncc)::value;
+    gload(0);
+    lstore();
+    __syncthreads();
+    for (int kb = 0; kb < nkb; ++kb) {
+      if (kb + 1 < nkb) gload(kb + 1);
 #pragma unroll
-    for (int c = 0; c < HC; ++c) {
-      const int cb = ch * HC + c;
-      if (cb < NCB) {
+      for (int c = 0; c < NC; ++c) {
+        const int cb = ch * HC + c;
         float bv[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) bv[e] = Bs[(p * KH + 8 * lg + e) * BS + cb * 16 + li];
@@ -725,13 +796,17 @@ __global__ __launch_bounds__(256) void k_legendre_synthesis_bf16(const GemmArgs 
           acc[jr][c] = mfma6(av, b0, b1, b2, acc[jr][c]);
         }
       }
-    }
-    __syncthreads();
-    if (kb + 1 < nkb) {
-      lstore();
       __syncthreads();
+      if (kb + 1 < nkb) {
+        lstore();
+        __syncthreads();
+      }
     }
-  }
+  };
+  if (full_cols || 2 * HC == NCB)
+    kloop(std::integral_constant<int, HC>{});
+  else
+    kloop(std::integral_constant<int, NCB - HC>{});
 
   const long long plane = (long long)L.Kp * Cp;
   float* ws = static_cast<float*>(g.ws) + L.ws_off + (2LL * m + p) * plane;
@@ -755,12 +830,14 @@ __global__ __launch_bounds__(256) void k_legendre_synthesis_bf16(const GemmArgs 
 // ---------------------------------------------------------------------------
 template <typename T>
 static size_t lds_analysis(int ncb) {
-  const int E = 16 / (int)sizeof(T);
-  const int KB = sizeof(T) == 4 ? 32 : 16;
-  const int BN = 16 * ncb;
-  size_t stage = (size_t)(64 * (KB + E) + 2 * KB * (BN + 2)) * sizeof(T);
-  size_t cst = (size_t)64 * (BN + 1) * sizeof(T);
-  return stage > cst ? stage : cst;
+  switch (ncb) {
+    case 1: return AnalysisShape<T, 1>::lds_bytes();
+    case 2: return AnalysisShape<T, 2>::lds_bytes();
+    case 4: return AnalysisShape<T, 4>::lds_bytes();
+    case 5: return AnalysisShape<T, 5>::lds_bytes();
+    case 8: return AnalysisShape<T, 8>::lds_bytes();
+    default: return AnalysisShape<T, 10>::lds_bytes();
+  }
 }
 
 template <typename T>
@@ -796,12 +873,12 @@ static void lds_optin(size_t bytes) {
 template <typename T>
 static hipError_t launch_legendre_t(bool analysis, const GemmArgs& g, int ncb,
                                     hipStream_t st) {
-  const dim3 grid(g.ntiles), block(256);
+  const dim3 grid(g.ntiles), block(256), block_a(512);
 #define SHT_LLAUNCH(NCB_)                                                        \
   case NCB_:                                                                    \
     if (analysis) {                                                             \
       lds_optin<k_legendre_analysis<T, NCB_>>(lds_analysis<T>(NCB_));          \
-      hipLaunchKernelGGL((k_legendre_analysis<T, NCB_>), grid, block,          \
+      hipLaunchKernelGGL((k_legendre_analysis<T, NCB_>), grid, block_a,        \
                          lds_analysis<T>(NCB_), st, g);                         \
     } else {                                                                    \
       lds_optin<k_legendre_synthesis<T, NCB_>>(lds_synthesis<T>(NCB_));        \
