@@ -204,8 +204,9 @@ std::vector<Tile> xcd_schedule(const std::vector<Tile>& tiles, const std::vector
 //  per wave (16 rows r = 32 q + 2 i + p), inside that one 64-lane vector
 //  after the other: vector v of lane (i, g) holds columns 4 (v E + e) + g,
 //  e < E = 16 bytes / element size;
-//  synthesis copy: per m, blocks (64-row j block, 32-row r block), each
-//  laid out [parity][64 j][16 r'] with r = 32 kb + 2 r' + parity.
+//  synthesis copy: per m, one chunk per (128-latitude tile, K block of 32
+//  natural rows), blocked per wave and lane vector like the analysis copy
+//  (see the loop below).
 // Tile list of one Legendre kernel for column blocking ncb (16*ncb columns
 // per tile; the workspace row length Cp must be a multiple of it).
 // sched 0: the list in locality order (m, column block, row block) cut into
@@ -228,10 +229,17 @@ std::vector<Tile> build_tiles(const sht_plan_s* P, bool analysis, int ncb, int s
             t.push_back(Tile{l, m, rb, cb});
             c.push_back((double)L.Kp * BN);
           }
-        } else {
+        } else if (P->form == SHT_FORM_BF16X6) {
           for (int jb = 0; jb < (L.Jh + 63) / 64; ++jb) {
             t.push_back(Tile{l, m, jb, cb});
             c.push_back(((double)roundup(nm, 32) + 16.0) * BN);
+          }
+        } else {
+          // 128-latitude tiles, K blocks of 32 natural rows
+          const int kr2 = 32;
+          for (int jt = 0; jt < (L.Jh + 127) / 128; ++jt) {
+            t.push_back(Tile{l, m, jt, cb});
+            c.push_back(((double)roundup(nm, kr2) + 32.0) * 2 * BN);
           }
         }
       }
@@ -245,7 +253,6 @@ template <typename T>
 void fill_table_level(const LevelDesc& L, const double* mu, const double* sint,
                       T* dst, const long long* off_a, T* dsyn, const long long* off_s) {
   const int N = L.N, Jh = L.Jh, Kp = L.Kp;
-  const int JB = (Jh + 63) / 64;
   int nth = (int)std::thread::hardware_concurrency();
   nth = std::max(1, std::min(nth, 64));
   std::vector<std::thread> pool;
@@ -272,18 +279,29 @@ void fill_table_level(const LevelDesc& L, const double* mu, const double* sint,
                              (size_t)((v * 4 + g) * 16 + i) * E + e;
             blk[d] = (r < nm && j < Jh) ? (T)col[(size_t)r * Jh + j] : (T)0;
           }
-        const int nkb = (nm + 31) / 32;
+        // synthesis copy: per (128-latitude tile, K block of 2 KR natural
+        // rows) one chunk; inside it one run per wave (parity p, quarter q)
+        // of 64-lane vectors: vector v of lane (i, g) holds latitude
+        // 32 q + 16 (v / (KQ/E)) + i and r' = g KQ + E (v % (KQ/E)) + e
+        constexpr int KR = 16, KQs = KR / 4, NVs = 2 * KQs / E;
+        const int nkbs = (nm + 2 * KR - 1) / (2 * KR);
+        const int JT = (Jh + 127) / 128;
+        const size_t chunk = (size_t)128 * 2 * KR;
         T* sb = dsyn + off_s[m];
-        for (int jb = 0; jb < JB; ++jb)
-          for (int kb = 0; kb < nkb; ++kb) {
-            T* b = sb + ((size_t)jb * nkb + kb) * 2048;
-            for (int par = 0; par < 2; ++par)
-              for (int jl = 0; jl < 64; ++jl)
-                for (int kl = 0; kl < 16; ++kl) {
-                  const int r = kb * 32 + 2 * kl + par, j = jb * 64 + jl;
-                  b[(par * 64 + jl) * 16 + kl] = (r < nm && j < Jh) ? (T)col[(size_t)r * Jh + j] : (T)0;
-                }
-          }
+        for (int jt = 0; jt < JT; ++jt)
+          for (int kb = 0; kb < nkbs; ++kb)
+            for (int w = 0; w < 8; ++w)
+              for (int v = 0; v < NVs; ++v)
+                for (int ln = 0; ln < 64; ++ln)
+                  for (int e = 0; e < E; ++e) {
+                    const int p = w & 1, q = w >> 1, i = ln & 15, g = ln >> 4;
+                    const int jb = v / (KQs / E), kk = (v % (KQs / E)) * E + e;
+                    const int r = kb * 2 * KR + 2 * (g * KQs + kk) + p;
+                    const int j = jt * 128 + 32 * q + 16 * jb + i;
+                    const size_t d = ((size_t)jt * nkbs + kb) * chunk + (size_t)w * (chunk / 8) +
+                                     (size_t)(v * 64 + ln) * E + e;
+                    sb[d] = (r < nm && j < Jh) ? (T)col[(size_t)r * Jh + j] : (T)0;
+                  }
       }
     });
   }
@@ -431,10 +449,12 @@ int build_plan(int nlev, const int* Nv, const int* Jv, const int* Iv, const int*
       // analysis copy: rows padded to the row tile (128; 64 in the split form)
       tab += roundup(L.N - m + 1, o.form == SHT_FORM_BF16X6 ? SHT_ROWS_PAD : 128) * L.Kp;
       taboff_syn.push_back(tabs);
-      if (o.form == SHT_FORM_BF16X6)
+      if (o.form == SHT_FORM_BF16X6) {
         tabs += (long long)((L.Jh + 63) / 64) * ((L.N - m + 1 + 63) / 64) * 4096;
-      else
-        tabs += (long long)((L.Jh + 63) / 64) * ((L.N - m + 1 + 31) / 32) * 2048;
+      } else {
+        const int kr2 = 32;  // natural rows per K block
+        tabs += (long long)((L.Jh + 127) / 128) * ((L.N - m + kr2) / kr2) * 128 * kr2;
+      }
     }
     P->maxN = std::max(P->maxN, L.N);
     P->flops += 2.0 * L.Jh * (double)(L.N + 1) * (L.N + 2) * L.F;

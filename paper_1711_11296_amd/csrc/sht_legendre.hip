@@ -277,170 +277,177 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
 
 // ---------------------------------------------------------------------------
 // synthesis: S_p[j][c] = sum_{r of parity p} P[r][j] * a[r][c]
-// tile = 64 rows j x BN columns, both parities.  The table is read from its
-// synthesis copy, laid out per (m, 64-row j block, 32-row r block) as
-// [parity][64 j][16 r] so that each block is one contiguous 2048-element
-// run that lands in LDS unchanged.
-// wave w: output parity p = w & 1, column half ch = w >> 1; 4 row blocks of
-// 16 j times HC column blocks.
+// tile = 128 latitudes j x BN = 16*NCB columns, both parities, 8 waves.
+// Wave w: parity p = w & 1, latitude quarter q = w >> 1; it owns the 32
+// latitudes j = 32 q + 16 jb + i (jb < 2, two MFMA row blocks) and all NCB
+// column blocks.  The contraction runs over r' (r = 2 r' + p) in blocks of
+// KR per parity; lane (i, g) supplies r' = g KR/4 + kk (kk < KR/4).
+// The table operand comes straight from memory into registers: the
+// synthesis copy is blocked per (m, 128-latitude tile, K block), inside a
+// block per wave and per 64-lane vector (vector v of lane (i, g) holds
+// latitude block jb = v / (KQ/E) and r' = g KQ + E (v % (KQ/E)) + e).
+// The spectral operand goes through LDS in two stages, transposed to
+// [parity][column][r'] so that each lane reads its KR/4 values of a column
+// as 16-byte vectors; one barrier per block.
 // ---------------------------------------------------------------------------
 template <typename T, int NCB>
-__global__ __launch_bounds__(256) void k_legendre_synthesis(const GemmArgs g) {
+struct SynthesisShape {
+  static constexpr int E = 16 / (int)sizeof(T);
+  static constexpr int KR = 16;                         // r' per parity and block
+  static constexpr int KQ = KR / 4;                    // r' per lane and block
+  static constexpr int BN = 16 * NCB;
+  static constexpr int PITCH = KR + 16 / (int)sizeof(T);  // 16-byte pad: 4 mod 32 words
+  static constexpr int STAGE = 2 * BN * PITCH;
+  static constexpr int NV = 2 * KQ / E;                // table vectors per lane and block
+  static constexpr int QUADS = (BN / 2) * (KR / 2);    // 4 natural rows of one field
+  static constexpr int NQ = (QUADS + 511) / 512;
+  static constexpr int CHUNK = 128 * 2 * KR;           // table elements per block
+  static constexpr size_t lds_bytes() { return (size_t)2 * STAGE * sizeof(T); }
+};
+
+template <typename T, int NCB>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2))) void k_legendre_synthesis(const GemmArgs g) {
   typedef typename Acc<T>::type AccT;
   typedef typename V16<T>::type V;
-  constexpr int E = 16 / (int)sizeof(T);
-  constexpr int BN = 16 * NCB;
-  constexpr int HC = (NCB + 1) / 2;
-  constexpr int KH = 16;                          // table rows per parity and block
-  constexpr int AS = KH + E;                      // odd number of 16-byte units
-  constexpr int BS = sizeof(T) == 4 ? BN + 4 : BN + 2;
-  constexpr int NA = 2 * 64 * KH / E / 256;       // table vectors per thread
-  constexpr int NB = (BN / 2) * (KH) / 256 > 0 ? (BN / 2) * KH / 256 : 1;  // row-pair chunks
+  using S = SynthesisShape<T, NCB>;
+  constexpr int E = S::E, KR = S::KR, KQ = S::KQ, BN = S::BN, PITCH = S::PITCH;
 
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* At = reinterpret_cast<T*>(smem_raw);     // [2][64 j][AS]
-  T* Bs = At + 2 * 64 * AS;                   // [2][KH][BS]
+  T* Bs = reinterpret_cast<T*>(smem_raw);  // [2 stage][2 parity][BN][PITCH]
 
   const Tile t = g.tiles[blockIdx.x];
   if (t.level < 0) return;
   const LevelDesc& L = g.lev[t.level];
   const int N = L.N, m = t.m;
   const int nm = N - m + 1;
-  const int nkb = (nm + 31) / 32;
-  const int jb = t.rb;
+  const int nkb = (nm + 2 * KR - 1) / (2 * KR);
+  const int jt = t.rb;
   const int c0 = t.cb * BN;
   const long long Cp = L.Cp;
-  const T* tab = static_cast<const T*>(g.table) + g.tab_off[L.m_base + m] + (long long)jb * nkb * 2048;
   const T* spec = static_cast<const T*>(g.spec_in) + L.spec_off;
   const long long nc = (long long)(N + 1) * (N + 2) / 2;
   const long long sbase = spec_idx(N, m, m);
 
   const int tid = threadIdx.x;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
-  const int p = w & 1, ch = w >> 1;
+  const int p = w & 1, q = w >> 1;
   const int li = lane & 15, lg = lane >> 4;
-  const bool full_cols = ch == 0;  // HC column blocks, else NCB - HC
+  const bool active = jt * 128 + 32 * q < L.Jh;
+  const T* arun = static_cast<const T*>(g.table) + g.tab_off[L.m_base + m] +
+                  (long long)jt * nkb * S::CHUNK + w * (S::CHUNK / 8) + lane * E;
 
-  AccT acc[4][HC];
+  AccT acc[2][NCB];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int jb = 0; jb < 2; ++jb)
 #pragma unroll
-    for (int c = 0; c < HC; ++c) acc[a][c] = AccT{0, 0, 0, 0};
+    for (int c = 0; c < NCB; ++c) acc[jb][c] = AccT{0, 0, 0, 0};
 
-  V ra[NA];
-  T rs[NB][4];  // two consecutive rows (re, im) of one field
+  constexpr int QV = 8 / E;  // vectors per quad: 4 rows (re, im) of one field
+  V an[S::NV], ac[S::NV];
+  V rq[S::NQ][QV];
   auto gload = [&](int kb) {
-    const T* blk = tab + (long long)kb * 2048;
+    if (active) {
 #pragma unroll
-    for (int i = 0; i < NA; ++i) {
-      const int q = tid + i * 256;
-      ra[i] = *reinterpret_cast<const V*>(blk + q * E);
+      for (int v = 0; v < S::NV; ++v)
+        an[v] = *reinterpret_cast<const V*>(arun + (long long)kb * S::CHUNK + v * 64 * E);
     }
-    const int rb0 = kb * 32;
 #pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      const int q = tid + i * 256;
-      const int fl = q / KH, rp = q % KH;
+    for (int i = 0; i < S::NQ; ++i) {
+      const int qq = tid + i * 512;
+      const int fl = qq / (KR / 2), rp = qq % (KR / 2);
       const int f = (c0 >> 1) + fl;
-      const int r = rb0 + 2 * rp;
-      rs[i][0] = rs[i][1] = rs[i][2] = rs[i][3] = (T)0;
-      if (fl < BN / 2 && f < L.F) {
-        const T* s = spec + ((long long)f * nc + sbase + r) * 2;
-        if (r < nm) {
-          rs[i][0] = s[0];
-          rs[i][1] = s[1];
-        }
-        if (r + 1 < nm) {
-          rs[i][2] = s[2];
-          rs[i][3] = s[3];
+      const int r = kb * 2 * KR + 4 * rp;  // first natural row of the quad
+      const T* src = spec + ((long long)f * nc + sbase + r) * 2;
+      const bool okf = (S::NQ * 512 == S::QUADS || qq < S::QUADS) && f < L.F;
+#pragma unroll
+      for (int u = 0; u < QV; ++u) {
+        // vector u holds natural rows r + u E/2 .. r + (u+1) E/2 - 1
+        if (okf && r + (u + 1) * E / 2 <= nm) {
+          rq[i][u] = *reinterpret_cast<const V*>(src + u * E);
+        } else {
+#pragma unroll
+          for (int e = 0; e < E; ++e) rq[i][u][e] = (okf && r + (u * E + e) / 2 < nm) ? src[u * E + e] : (T)0;
         }
       }
     }
   };
-  auto lstore = [&]() {
+  auto lstore = [&](int stage) {
+    T* dst = Bs + stage * S::STAGE;
 #pragma unroll
-    for (int i = 0; i < NA; ++i) {
-      const int q = tid + i * 256;
-      const int e0 = q * E;                       // element offset in the block
-      const int pj = e0 / KH, kv = e0 % KH;       // (parity*64 + j), k
-      *reinterpret_cast<V*>(At + pj * AS + kv) = ra[i];
-    }
+    for (int i = 0; i < S::NQ; ++i) {
+      const int qq = tid + i * 512;
+      if (S::NQ * 512 == S::QUADS || qq < S::QUADS) {
+        const int fl = qq / (KR / 2), rp = qq % (KR / 2);
+        T x[8];
 #pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      const int q = tid + i * 256;
-      const int fl = q / KH, rp = q % KH;
-      if (fl < BN / 2) {
-        T* d0 = Bs + rp * BS + 2 * fl;
-        T* d1 = Bs + (KH + rp) * BS + 2 * fl;
-        d0[0] = rs[i][0];
-        d0[1] = rs[i][1];
-        d1[0] = rs[i][2];
-        d1[1] = rs[i][3];
-      }
-    }
-  };
-
-  auto kloop = [&](auto ncc) {
-    constexpr int NC = decltype(ncc)::value;
-    gload(0);
-    lstore();
-    __syncthreads();
-    for (int kb = 0; kb < nkb; ++kb) {
-      if (kb + 1 < nkb) gload(kb + 1);
-      if constexpr (NC > 0) {
-        T av[4][4];
+        for (int u = 0; u < QV; ++u)
 #pragma unroll
-        for (int jr = 0; jr < 4; ++jr) {
-          const T* Ap = At + (p * 64 + 16 * jr + li) * AS + lg * 4;
+          for (int e = 0; e < E; ++e) x[u * E + e] = rq[i][u][e];
+        // x = re, im of natural rows r, r+1, r+2, r+3: parity par, r' = 2 rp + h
 #pragma unroll
-          for (int v = 0; v < 4 / E + (E > 4 ? 1 : 0); ++v) {
-            const V x = *reinterpret_cast<const V*>(Ap + v * E);
+        for (int par = 0; par < 2; ++par)
 #pragma unroll
-            for (int e = 0; e < E && v * E + e < 4; ++e) av[jr][v * E + e] = x[e];
+          for (int ri = 0; ri < 2; ++ri) {
+            typedef T T2 __attribute__((ext_vector_type(2)));
+            *reinterpret_cast<T2*>(dst + (par * BN + 2 * fl + ri) * PITCH + 2 * rp) =
+                T2{x[2 * par + ri], x[4 + 2 * par + ri]};
           }
-        }
-        const T* Bp = Bs + (p * KH + lg * 4) * BS + ch * HC * 16 + li;
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
-          T bv[NC];
-#pragma unroll
-          for (int c = 0; c < NC; ++c) bv[c] = Bp[kk * BS + c * 16];
-#pragma unroll
-          for (int c = 0; c < NC; ++c)
-#pragma unroll
-            for (int jr = 0; jr < 4; ++jr) acc[jr][c] = mfma16(av[jr][kk], bv[c], acc[jr][c]);
-        }
-        // A reads and the B reads of two k-steps first, then the B reads of
-        // the later steps between the MFMAs
-        constexpr int RD = (NC + 1) / 2;
-        constexpr int NAR = 4 * (4 / E > 0 ? 4 / E : 1);
-        mfma_lds_pipeline<NAR + 2 * RD, 2 * RD, (4 * NC + RD - 1) / RD, 8 * NC>();
-      }
-      __syncthreads();
-      if (kb + 1 < nkb) {
-        lstore();
-        __syncthreads();
       }
     }
   };
-  if (full_cols || 2 * HC == NCB)
-    kloop(std::integral_constant<int, HC>{});
-  else
-    kloop(std::integral_constant<int, NCB - HC>{});
 
+  gload(0);
+  lstore(0);
+#pragma unroll
+  for (int v = 0; v < S::NV; ++v) ac[v] = an[v];
+  __syncthreads();
+  for (int kb = 0; kb < nkb; ++kb) {
+    const bool more = kb + 1 < nkb;
+    if (more) gload(kb + 1);
+    if (active) {
+      T a[2][KQ];
+#pragma unroll
+      for (int v = 0; v < S::NV; ++v)
+#pragma unroll
+        for (int e = 0; e < E; ++e) a[v / (KQ / E)][(v % (KQ / E)) * E + e] = ac[v][e];
+      const T* Bp = Bs + (kb & 1) * S::STAGE + (p * BN + li) * PITCH + lg * KQ;
+#pragma unroll
+      for (int c = 0; c < NCB; ++c) {
+        T bv[KQ];
+#pragma unroll
+        for (int v = 0; v < KQ / E; ++v) {
+          const V x = *reinterpret_cast<const V*>(Bp + c * 16 * PITCH + v * E);
+#pragma unroll
+          for (int e = 0; e < E; ++e) bv[v * E + e] = x[e];
+        }
+#pragma unroll
+        for (int kk = 0; kk < KQ; ++kk)
+#pragma unroll
+          for (int jb = 0; jb < 2; ++jb) acc[jb][c] = mfma16(a[jb][kk], bv[kk], acc[jb][c]);
+      }
+      // the reads of a column block are issued two column blocks ahead
+      constexpr int RDC = KQ / E;
+      mfma_lds_pipeline<2 * RDC, (NCB - 2) * RDC, (2 * KQ + RDC - 1) / RDC, 4 * KQ>();
+    }
+    if (more) {
+      lstore((kb + 1) & 1);
+#pragma unroll
+      for (int v = 0; v < S::NV; ++v) ac[v] = an[v];
+    }
+    __syncthreads();
+  }
+
+  if (!active) return;
   const long long plane = (long long)L.Kp * Cp;
   T* ws = static_cast<T*>(g.ws) + L.ws_off + (2LL * m + p) * plane;
 #pragma unroll
-  for (int jr = 0; jr < 4; ++jr)
+  for (int jb = 0; jb < 2; ++jb)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int j = jb * 64 + 16 * jr + out_row<T>(lg, i);
+      const int j = jt * 128 + 32 * q + 16 * jb + out_row<T>(lg, i);
       if (j < L.Jh) {
 #pragma unroll
-        for (int c = 0; c < HC; ++c) {
-          const int cb = ch * HC + c;
-          if (cb < NCB) ws[(long long)j * Cp + c0 + cb * 16 + li] = acc[jr][c][i];
-        }
+        for (int c = 0; c < NCB; ++c) ws[(long long)j * Cp + c0 + c * 16 + li] = acc[jb][c][i];
       }
     }
 }
@@ -842,10 +849,14 @@ static size_t lds_analysis(int ncb) {
 
 template <typename T>
 static size_t lds_synthesis(int ncb) {
-  const int E = 16 / (int)sizeof(T);
-  const int BN = 16 * ncb;
-  const int BS = sizeof(T) == 4 ? BN + 4 : BN + 2;
-  return (size_t)(2 * 64 * (16 + E) + 2 * 16 * BS) * sizeof(T);
+  switch (ncb) {
+    case 1: return SynthesisShape<T, 1>::lds_bytes();
+    case 2: return SynthesisShape<T, 2>::lds_bytes();
+    case 4: return SynthesisShape<T, 4>::lds_bytes();
+    case 5: return SynthesisShape<T, 5>::lds_bytes();
+    case 8: return SynthesisShape<T, 8>::lds_bytes();
+    default: return SynthesisShape<T, 10>::lds_bytes();
+  }
 }
 
 static size_t lds_analysis_bf16(int ncb) {
@@ -882,7 +893,7 @@ static hipError_t launch_legendre_t(bool analysis, const GemmArgs& g, int ncb,
                          lds_analysis<T>(NCB_), st, g);                         \
     } else {                                                                    \
       lds_optin<k_legendre_synthesis<T, NCB_>>(lds_synthesis<T>(NCB_));        \
-      hipLaunchKernelGGL((k_legendre_synthesis<T, NCB_>), grid, block,         \
+      hipLaunchKernelGGL((k_legendre_synthesis<T, NCB_>), grid, block_a,       \
                          lds_synthesis<T>(NCB_), st, g);                        \
     }                                                                           \
     break;
