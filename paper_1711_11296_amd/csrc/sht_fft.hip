@@ -390,8 +390,22 @@ struct Item {
   bool eq;
 };
 
-__device__ __forceinline__ Item decode_item(const FftArgs& a, int item) {
+// Workgroup b runs on XCD b mod 8 and walks the items b, b + G, ...
+// (G = gridDim.x, a multiple of 8 on a full device).  Item index i is
+// mapped to list position x R' + k (x = i mod 8, k = i / 8, R' the length
+// of the x-th eighth of the list): every XCD works through one contiguous
+// eighth, so the field blocks of one latitude pair run on one XCD at about
+// the same time and fill whole workspace lines in its L2.  The map is a
+// permutation of [0, n).
+__device__ __forceinline__ int xcd_map(int i, int n) {
+  const int x = i & 7, k = i >> 3;
+  const int R = n >> 3, rem = n & 7;
+  return x * R + (x < rem ? x : rem) + k;
+}
+
+__device__ __forceinline__ Item decode_item(const FftArgs& a, int slot) {
   Item it;
+  const int item = xcd_map(slot, a.nitems);
   it.l = level_of(a, item);
   const LevelDesc& L = a.lev[it.l];
   const int local = item - L.fft_item0;
@@ -804,7 +818,8 @@ __global__ __launch_bounds__(NT) void k_zonal_analysis_p3(const FftArgs a) {
   F3::stage_twiddles(twl, static_cast<const cx<T>*>(L.tw));
 
   cx<T> v1[F3::S1][16];
-  auto load_rows = [&](int itm, int rd) {
+  auto load_rows = [&](int slot, int rd) {
+    const int itm = xcd_map(slot, a.nitems);
     const int jp = itm / L.nfb, fb = itm - jp * L.nfb;
     const bool eq = (J & 1) && (jp == (J >> 1));
 #pragma unroll
@@ -827,7 +842,8 @@ __global__ __launch_bounds__(NT) void k_zonal_analysis_p3(const FftArgs a) {
 
   load_rows(item, 0);
   for (; item < a.nitems; item += gridDim.x) {
-    const int jp = item / L.nfb, fb = item - jp * L.nfb;
+    const int itm = xcd_map(item, a.nitems);
+    const int jp = itm / L.nfb, fb = itm - jp * L.nfb;
     const bool eq = (J & 1) && (jp == (J >> 1));
     const T rscale = row_scale<T>(a, L, jp);
     const int next = item + (int)gridDim.x;
@@ -921,7 +937,8 @@ __global__ __launch_bounds__(NT) void k_zonal_synthesis_p3(const FftArgs a) {
   const long long plane = (long long)L.Kp * Cp;
 
   cx<T> stS[MS][FB], stA[MS][FB];
-  auto load_ws = [&](int itm) {
+  auto load_ws = [&](int slot) {
+    const int itm = xcd_map(slot, a.nitems);
     const int jp = itm / L.nfb, fb = itm - jp * L.nfb;
 #pragma unroll
     for (int s = 0; s < MS; ++s) {
@@ -942,7 +959,8 @@ __global__ __launch_bounds__(NT) void k_zonal_synthesis_p3(const FftArgs a) {
   F3::stage_twiddles(twl, static_cast<const cx<T>*>(L.tw));
   load_ws(item);
   for (; item < a.nitems; item += gridDim.x) {
-    const int jp = item / L.nfb, fb = item - jp * L.nfb;
+    const int itm = xcd_map(item, a.nitems);
+    const int jp = itm / L.nfb, fb = itm - jp * L.nfb;
     const bool eq = (J & 1) && (jp == (J >> 1));
     const T rscale = row_scale<T>(a, L, jp);
     const int next = item + (int)gridDim.x;
