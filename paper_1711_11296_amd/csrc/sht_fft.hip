@@ -384,6 +384,71 @@ __device__ __forceinline__ void load_run(const T* src, cx<T> (&v)[FB]) {
   }
 }
 
+// The workspace run of one (wavenumber, parity, latitude pair, field block)
+// is 2 FB values = 64 bytes, and the thread of wavenumber m holds the whole
+// run; consecutive lanes hold consecutive m, whose runs are a plane apart.
+// Before storing, the four lanes of each quad exchange 16-byte pieces so
+// that lane j holds piece j of the four runs of its quad; a 16-byte store
+// instruction then covers 16 whole runs instead of touching 64 cache lines.
+constexpr int kQuadXor1 = 0xB1;  // DPP quad_perm [1,0,3,2]
+constexpr int kQuadXor2 = 0x4E;  // DPP quad_perm [2,3,0,1]
+
+// 4x4 transpose of 16-byte pieces across a quad; its own inverse.  Every
+// lane of the quad must take part.
+__device__ __forceinline__ void quad_transpose(int (&x)[4][4]) {
+  const int j = threadIdx.x & 3;
+  const bool h1 = (j & 1) != 0, h2 = (j & 2) != 0;
+#pragma unroll
+  for (int p = 0; p < 4; p += 2)
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      const int v = h1 ? x[p][d] : x[p + 1][d];
+      const int r = __builtin_amdgcn_update_dpp(0, v, kQuadXor1, 0xF, 0xF, false);
+      if (h1)
+        x[p][d] = r;
+      else
+        x[p + 1][d] = r;
+    }
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      const int v = h2 ? x[p][d] : x[p + 2][d];
+      const int r = __builtin_amdgcn_update_dpp(0, v, kQuadXor2, 0xF, 0xF, false);
+      if (h2)
+        x[p][d] = r;
+      else
+        x[p + 2][d] = r;
+    }
+}
+
+// Store the runs v of the quad's four wavenumbers m - j .. m - j + 3
+// (j = lane in quad) at dst(m') = base + (2 m') * plane; runs with m' > N
+// are skipped.  All lanes of the quad must call it.  base is uniform and the
+// level's workspace is below 4 GiB: the per-lane part of each address is a
+// 32-bit byte offset.
+template <typename T, int FB>
+__device__ __forceinline__ void store_runs_quad(T* base, long long plane, int m, int N,
+                                                const cx<T> (&v)[FB]) {
+  static_assert(2 * FB * sizeof(T) == 64, "64-byte runs");
+  int x[4][4];
+  __builtin_memcpy(x, v, 64);
+  quad_transpose(x);
+  const int j = threadIdx.x & 3;
+  char* b = reinterpret_cast<char*>(base);
+  const unsigned step = (unsigned)(2 * plane * (long long)sizeof(T));
+  unsigned off = (unsigned)(m - j) * step + 16u * (unsigned)j;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int mr = m - j + r;
+    if (mr <= N) {
+      typedef int i32x4 __attribute__((ext_vector_type(4)));
+      *reinterpret_cast<i32x4*>(b + off) = i32x4{x[r][0], x[r][1], x[r][2], x[r][3]};
+    }
+    off += step;
+  }
+}
+
 // Work item = (level, mirror row pair jp, block fb of FB fields).
 struct Item {
   int l, jp, fb, js;
@@ -909,14 +974,12 @@ __global__ __launch_bounds__(NT) void k_zonal_analysis_p3(const FftArgs a) {
 
     const long long Cp = L.Cp;
     const long long plane = (long long)L.Kp * Cp;
+    T* wrow = ws + (long long)jp * Cp + 2 * fb * FB;
 #pragma unroll
     for (int s = 0; s < MS; ++s) {
       const int m = threadIdx.x + s * NT;
-      if (m <= N) {
-        T* dS = ws + (2LL * m) * plane + (long long)jp * Cp + 2 * fb * FB;
-        store_run<T, FB>(dS, stS[s]);
-        store_run<T, FB>(dS + plane, stA[s]);
-      }
+      store_runs_quad<T, FB>(wrow, plane, m, N, stS[s]);
+      store_runs_quad<T, FB>(wrow + plane, plane, m, N, stA[s]);
     }
   }
 }
@@ -1120,6 +1183,9 @@ static hipError_t launch_p3(bool analysis, const FftArgs& a, int maxN, hipStream
 template <typename T, int FB>
 static bool launch_fixed(bool analysis, const FftArgs& a, int maxN, hipStream_t st, hipError_t* err) {
   if (a.nlev != 1) return false;
+  // the fixed-length kernels address the workspace with 32-bit offsets
+  const LevelDesc& L = a.lev[0];
+  if ((double)(L.N + 1) * 2.0 * L.Kp * L.Cp * sizeof(T) >= 4294967296.0) return false;
   constexpr bool dbl = sizeof(T) == 8;
   switch (a.lev[0].I) {
     case 2880:
