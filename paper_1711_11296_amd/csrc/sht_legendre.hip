@@ -64,6 +64,16 @@ __device__ __forceinline__ long long spec_idx(int N, int m, int n) {
   return (long long)m * (2 * N + 3 - m) / 2 + (n - m);
 }
 
+// One 16-byte piece per lane from global memory straight into LDS
+// (global_load_lds_dwordx4): the wave's 64 pieces land contiguously at
+// lds_base, lane l at byte 16 l; lds_base must be uniform across the wave.
+// Completion is awaited with s_waitcnt vmcnt.
+__device__ __forceinline__ void load_to_lds16(const void* src, void* lds_base) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)lds_base, 16, 0, 0);
+#endif
+}
+
 // Instruction-order hint for a K-block body (scheduling groups of the
 // compiler, no effect on results): PRE LDS reads first, then ROUNDS times
 // PER MFMAs followed by one LDS read, then TAIL MFMAs.  It keeps the LDS
@@ -126,9 +136,15 @@ struct AnalysisShape {
   static constexpr int KB = sizeof(T) == 4 ? 32 : 16;  // contraction block
   static constexpr int KQ = KB / 4;                    // k values per lane and block
   static constexpr int BN = 16 * NCB;
-  // row pitch of the LDS operand: lanes g = 0..3 read rows g + 4 kk; for FP32
-  // a pitch of 16 mod 32 words puts the four groups on alternate bank halves
-  static constexpr int BS = BN + (sizeof(T) == 4 ? 16 : 2);
+  // With an even number of column blocks the right-hand operand goes from
+  // memory to LDS directly (global_load_lds, 64 x 16 bytes per instruction,
+  // contiguous in LDS), in rows of BN elements whose 16-column blocks are
+  // swapped in pairs on odd rows (column c sits at c ^ 16 when k is odd):
+  // the lane groups g = 0, 1 that one LDS cycle serves read rows of
+  // different parity and so hit different bank halves.  Otherwise it is
+  // staged through registers into rows padded to a pitch of 16 mod 32 words.
+  static constexpr bool DMA = NCB % 2 == 0;
+  static constexpr int BS = DMA ? BN : BN + (sizeof(T) == 4 ? 16 : 2);
   static constexpr int STAGE = 2 * KB * BS;            // elements of one stage
   static constexpr int BV = 2 * KB * BN / E;           // 16-byte vectors per block
   static constexpr int NB = (BV + 511) / 512;
@@ -177,12 +193,13 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
   for (int c = 0; c < NCB; ++c) acc[c] = AccT{0, 0, 0, 0};
 
   V an[KQ / E], ac[KQ / E];
-  V rb[S::NB];
+  V rb[S::DMA ? 1 : S::NB];
   auto gload = [&](int kb) {
     if (active) {
 #pragma unroll
       for (int v = 0; v < KQ / E; ++v) an[v] = *reinterpret_cast<const V*>(arow + kb * 128 * KB + v * 64 * E);
     }
+    if constexpr (S::DMA) return;
 #pragma unroll
     for (int i = 0; i < S::NB; ++i) {
       const int qq = tid + i * 512;
@@ -195,6 +212,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     }
   };
   auto lstore = [&](int stage) {
+    if constexpr (S::DMA) return;
     T* dst = Bs + stage * S::STAGE;
 #pragma unroll
     for (int i = 0; i < S::NB; ++i) {
@@ -207,16 +225,39 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
       }
     }
   };
+  // memory -> LDS without registers: instruction i of wave w fills the
+  // 1 KiB chunk number i*8 + w of the stage; lane l takes its 16-byte piece
+  // (row, physical column) and fetches the logical column under the swizzle
+  auto dma = [&](int kb, int stage) {
+    if constexpr (S::DMA) {
+      static_assert(S::BV % 512 == 0, "whole chunks per wave");
+      T* dst = Bs + stage * S::STAGE;
+#pragma unroll
+      for (int i = 0; i < S::NB; ++i) {
+        const int chunk = i * 8 + w;
+        const int L = chunk * 64 + lane;
+        const int rr = L / (BN / E), col = (L - rr * (BN / E)) * E;
+        const int par = rr / KB, k = rr - par * KB;
+        const T* src = wsm + par * plane + (long long)(kb * KB + k) * Cp + (col ^ ((k & 1) << 4));
+        load_to_lds16(src, dst + chunk * 64 * E);
+      }
+    }
+  };
 
   const int nkb = Kp / KB;
   gload(0);
+  dma(0, 0);
   lstore(0);
+  if constexpr (S::DMA) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 #pragma unroll
   for (int v = 0; v < KQ / E; ++v) ac[v] = an[v];
   __syncthreads();
   for (int kb = 0; kb < nkb; ++kb) {
     const bool more = kb + 1 < nkb;
-    if (more) gload(kb + 1);
+    if (more) {
+      gload(kb + 1);
+      dma(kb + 1, (kb + 1) & 1);
+    }
     if (active) {
       T a[KQ];
 #pragma unroll
@@ -224,11 +265,13 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
 #pragma unroll
         for (int e = 0; e < E; ++e) a[v * E + e] = ac[v][e];
       const T* Bp = Bs + (kb & 1) * S::STAGE + (p * KB + lg) * BS + li;
+      // swizzled column-block offsets (rows g + 4 kk have the parity of g)
+      const int sw = (S::DMA && (lg & 1)) ? 16 : 0;
 #pragma unroll
       for (int kk = 0; kk < KQ; ++kk) {
         T bv[NCB];
 #pragma unroll
-        for (int c = 0; c < NCB; ++c) bv[c] = Bp[4 * kk * BS + c * 16];
+        for (int c = 0; c < NCB; ++c) bv[c] = Bp[4 * kk * BS + c * 16 + ((c & 1) ? -sw : sw)];
 #pragma unroll
         for (int c = 0; c < NCB; ++c) acc[c] = mfma16(a[kk], bv[c], acc[c]);
       }
@@ -238,6 +281,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     }
     if (more) {
       lstore((kb + 1) & 1);
+      if constexpr (S::DMA) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 #pragma unroll
       for (int v = 0; v < KQ / E; ++v) ac[v] = an[v];
     }
