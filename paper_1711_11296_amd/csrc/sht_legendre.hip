@@ -387,13 +387,17 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
     for (int c = 0; c < NCB; ++c) acc[jb][c] = AccT{0, 0, 0, 0};
 
   constexpr int QV = 8 / E;  // vectors per quad: 4 rows (re, im) of one field
-  V an[S::NV], ac[S::NV];
-  V rq[S::NQ][QV];
-  auto gload = [&](int kb) {
+  // Operands are fetched two K blocks ahead into two register sets used in
+  // turn (the loop is unrolled by two so that the set is a compile-time
+  // choice): block kb + 2 is requested while block kb is multiplied, and
+  // block kb + 1, requested one block earlier, goes to LDS afterwards.
+  V an[2][S::NV], ac[S::NV];
+  V rq[2][S::NQ][QV];
+  auto gload = [&](int kb, V (&av)[S::NV], V (&bq)[S::NQ][QV]) {
     if (active) {
 #pragma unroll
       for (int v = 0; v < S::NV; ++v)
-        an[v] = *reinterpret_cast<const V*>(arun + (long long)kb * S::CHUNK + v * 64 * E);
+        av[v] = *reinterpret_cast<const V*>(arun + (long long)kb * S::CHUNK + v * 64 * E);
     }
 #pragma unroll
     for (int i = 0; i < S::NQ; ++i) {
@@ -407,15 +411,15 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
       for (int u = 0; u < QV; ++u) {
         // vector u holds natural rows r + u E/2 .. r + (u+1) E/2 - 1
         if (okf && r + (u + 1) * E / 2 <= nm) {
-          rq[i][u] = *reinterpret_cast<const V*>(src + u * E);
+          bq[i][u] = *reinterpret_cast<const V*>(src + u * E);
         } else {
 #pragma unroll
-          for (int e = 0; e < E; ++e) rq[i][u][e] = (okf && r + (u * E + e) / 2 < nm) ? src[u * E + e] : (T)0;
+          for (int e = 0; e < E; ++e) bq[i][u][e] = (okf && r + (u * E + e) / 2 < nm) ? src[u * E + e] : (T)0;
         }
       }
     }
   };
-  auto lstore = [&](int stage) {
+  auto lstore = [&](int stage, const V (&bq)[S::NQ][QV]) {
     T* dst = Bs + stage * S::STAGE;
 #pragma unroll
     for (int i = 0; i < S::NQ; ++i) {
@@ -426,7 +430,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
 #pragma unroll
         for (int u = 0; u < QV; ++u)
 #pragma unroll
-          for (int e = 0; e < E; ++e) x[u * E + e] = rq[i][u][e];
+          for (int e = 0; e < E; ++e) x[u * E + e] = bq[i][u][e];
         // x = re, im of natural rows r, r+1, r+2, r+3: parity par, r' = 2 rp + h
 #pragma unroll
         for (int par = 0; par < 2; ++par)
@@ -439,46 +443,54 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
       }
     }
   };
-
-  gload(0);
-  lstore(0);
+  auto compute = [&](int stage) {
+    T a[2][KQ];
 #pragma unroll
-  for (int v = 0; v < S::NV; ++v) ac[v] = an[v];
-  __syncthreads();
-  for (int kb = 0; kb < nkb; ++kb) {
-    const bool more = kb + 1 < nkb;
-    if (more) gload(kb + 1);
-    if (active) {
-      T a[2][KQ];
+    for (int v = 0; v < S::NV; ++v)
 #pragma unroll
-      for (int v = 0; v < S::NV; ++v)
+      for (int e = 0; e < E; ++e) a[v / (KQ / E)][(v % (KQ / E)) * E + e] = ac[v][e];
+    const T* Bp = Bs + stage * S::STAGE + (p * BN + li) * PITCH + lg * KQ;
 #pragma unroll
-        for (int e = 0; e < E; ++e) a[v / (KQ / E)][(v % (KQ / E)) * E + e] = ac[v][e];
-      const T* Bp = Bs + (kb & 1) * S::STAGE + (p * BN + li) * PITCH + lg * KQ;
+    for (int c = 0; c < NCB; ++c) {
+      T bv[KQ];
 #pragma unroll
-      for (int c = 0; c < NCB; ++c) {
-        T bv[KQ];
+      for (int v = 0; v < KQ / E; ++v) {
+        const V x = *reinterpret_cast<const V*>(Bp + c * 16 * PITCH + v * E);
 #pragma unroll
-        for (int v = 0; v < KQ / E; ++v) {
-          const V x = *reinterpret_cast<const V*>(Bp + c * 16 * PITCH + v * E);
-#pragma unroll
-          for (int e = 0; e < E; ++e) bv[v * E + e] = x[e];
-        }
-#pragma unroll
-        for (int kk = 0; kk < KQ; ++kk)
-#pragma unroll
-          for (int jb = 0; jb < 2; ++jb) acc[jb][c] = mfma16(a[jb][kk], bv[kk], acc[jb][c]);
+        for (int e = 0; e < E; ++e) bv[v * E + e] = x[e];
       }
-      // the reads of a column block are issued two column blocks ahead
-      constexpr int RDC = KQ / E;
-      mfma_lds_pipeline<2 * RDC, (NCB - 2) * RDC, (2 * KQ + RDC - 1) / RDC, 4 * KQ>();
-    }
-    if (more) {
-      lstore((kb + 1) & 1);
 #pragma unroll
-      for (int v = 0; v < S::NV; ++v) ac[v] = an[v];
+      for (int kk = 0; kk < KQ; ++kk)
+#pragma unroll
+        for (int jb = 0; jb < 2; ++jb) acc[jb][c] = mfma16(a[jb][kk], bv[kk], acc[jb][c]);
+    }
+    // the reads of a column block are issued two column blocks ahead
+    constexpr int RDC = KQ / E;
+    mfma_lds_pipeline<2 * RDC, (NCB - 2) * RDC, (2 * KQ + RDC - 1) / RDC, 4 * KQ>();
+  };
+  // one K block; H = kb & 1 selects the register set of block kb (and of
+  // kb + 2), 1 - H that of block kb + 1
+  auto step = [&](auto hc, int kb) {
+    constexpr int H = decltype(hc)::value;
+    if (kb + 2 < nkb) gload(kb + 2, an[H], rq[H]);
+    if (active) compute(H);
+    if (kb + 1 < nkb) {
+      lstore(1 - H, rq[1 - H]);
+#pragma unroll
+      for (int v = 0; v < S::NV; ++v) ac[v] = an[1 - H][v];
     }
     __syncthreads();
+  };
+
+  gload(0, an[0], rq[0]);
+  if (nkb > 1) gload(1, an[1], rq[1]);
+  lstore(0, rq[0]);
+#pragma unroll
+  for (int v = 0; v < S::NV; ++v) ac[v] = an[0][v];
+  __syncthreads();
+  for (int kb = 0; kb < nkb; kb += 2) {
+    step(std::integral_constant<int, 0>{}, kb);
+    if (kb + 1 < nkb) step(std::integral_constant<int, 1>{}, kb + 1);
   }
 
   if (!active) return;
