@@ -74,6 +74,11 @@ __device__ __forceinline__ void load_to_lds16(const void* src, void* lds_base) {
 #endif
 }
 
+// Workgroup barrier for LDS hand-offs only: waits for this wave's LDS
+// operations, not for its outstanding global loads (which __syncthreads'
+// fence would also drain, defeating loads issued blocks ahead).
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 // Instruction-order hint for a K-block body (scheduling groups of the
 // compiler, no effect on results): PRE LDS reads first, then ROUNDS times
 // PER MFMAs followed by one LDS read, then TAIL MFMAs.  It keeps the LDS
@@ -192,13 +197,19 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
 #pragma unroll
   for (int c = 0; c < NCB; ++c) acc[c] = AccT{0, 0, 0, 0};
 
-  V an[KQ / E], ac[KQ / E];
+  // The table operand is fetched two K blocks ahead into two register sets
+  // used in turn (loop unrolled by two); the workspace operand one block
+  // ahead (LDS stages).
+  V an[2][KQ / E], ac[KQ / E];
   V rb[S::DMA ? 1 : S::NB];
-  auto gload = [&](int kb) {
-    if (active) {
+  // (issued unconditionally, also by waves without rows in this tile and
+  // for blocks past the end, clamped: with straight-line loads the wait
+  // counts cover exactly the block that is consumed)
+  auto gload_a = [&](int kb, V (&av)[KQ / E]) {
 #pragma unroll
-      for (int v = 0; v < KQ / E; ++v) an[v] = *reinterpret_cast<const V*>(arow + kb * 128 * KB + v * 64 * E);
-    }
+    for (int v = 0; v < KQ / E; ++v) av[v] = *reinterpret_cast<const V*>(arow + kb * 128 * KB + v * 64 * E);
+  };
+  auto gload_b = [&](int kb) {
     if constexpr (S::DMA) return;
 #pragma unroll
     for (int i = 0; i < S::NB; ++i) {
@@ -243,49 +254,70 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
       }
     }
   };
-
+  // Wait for this wave's LDS fills: they were issued before the two table
+  // loads of the block after next, which may stay in flight (vector memory
+  // operations of a wave complete in issue order).
+  auto wait_fills = [&]() {
+    if constexpr (S::DMA) {
+      static_assert(KQ / E == 2, "two table loads per block");
+      asm volatile("s_waitcnt vmcnt(2)" ::: "memory");
+    }
+  };
+  auto compute = [&](int stage) {
+    T a[KQ];
+#pragma unroll
+    for (int v = 0; v < KQ / E; ++v)
+#pragma unroll
+      for (int e = 0; e < E; ++e) a[v * E + e] = ac[v][e];
+    const T* Bp = Bs + stage * S::STAGE + (p * KB + lg) * BS + li;
+    // swizzled column-block offsets (rows g + 4 kk have the parity of g)
+    const int sw = (S::DMA && (lg & 1)) ? 16 : 0;
+#pragma unroll
+    for (int kk = 0; kk < KQ; ++kk) {
+      T bv[NCB];
+#pragma unroll
+      for (int c = 0; c < NCB; ++c) bv[c] = Bp[4 * kk * BS + c * 16 + ((c & 1) ? -sw : sw)];
+#pragma unroll
+      for (int c = 0; c < NCB; ++c) acc[c] = mfma16(a[kk], bv[c], acc[c]);
+    }
+    // B reads run two k-steps ahead (paired reads of two columns)
+    constexpr int RD = (NCB + 1) / 2;
+    mfma_lds_pipeline<2 * RD, (KQ - 2) * RD, (NCB + RD - 1) / RD, 2 * NCB>();
+  };
   const int nkb = Kp / KB;
-  gload(0);
+  // one K block; H = kb & 1 selects the table registers of block kb (and of
+  // kb + 2), 1 - H those of block kb + 1
+  auto step = [&](auto hc, int kb) {
+    constexpr int H = decltype(hc)::value;
+    // after the last block the idle stage receives a clamped block that
+    // nothing reads, which keeps the loop free of branches around memory
+    // operations
+    const int kn = kb + 1 < nkb ? kb + 1 : nkb - 1;
+    dma(kn, 1 - H);
+    gload_b(kn);
+    asm volatile("" ::: "memory");  // the table loads below are issued after the fills
+    gload_a(kb + 2 < nkb ? kb + 2 : nkb - 1, an[H]);
+    if (active) compute(H);
+    lstore(1 - H);
+    wait_fills();
+#pragma unroll
+    for (int v = 0; v < KQ / E; ++v) ac[v] = an[1 - H][v];
+    lds_barrier();
+  };
+
   dma(0, 0);
+  gload_b(0);
+  asm volatile("" ::: "memory");
+  gload_a(0, an[0]);
+  gload_a(nkb > 1 ? 1 : 0, an[1]);
   lstore(0);
-  if constexpr (S::DMA) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  wait_fills();
 #pragma unroll
-  for (int v = 0; v < KQ / E; ++v) ac[v] = an[v];
+  for (int v = 0; v < KQ / E; ++v) ac[v] = an[0][v];
   __syncthreads();
-  for (int kb = 0; kb < nkb; ++kb) {
-    const bool more = kb + 1 < nkb;
-    if (more) {
-      gload(kb + 1);
-      dma(kb + 1, (kb + 1) & 1);
-    }
-    if (active) {
-      T a[KQ];
-#pragma unroll
-      for (int v = 0; v < KQ / E; ++v)
-#pragma unroll
-        for (int e = 0; e < E; ++e) a[v * E + e] = ac[v][e];
-      const T* Bp = Bs + (kb & 1) * S::STAGE + (p * KB + lg) * BS + li;
-      // swizzled column-block offsets (rows g + 4 kk have the parity of g)
-      const int sw = (S::DMA && (lg & 1)) ? 16 : 0;
-#pragma unroll
-      for (int kk = 0; kk < KQ; ++kk) {
-        T bv[NCB];
-#pragma unroll
-        for (int c = 0; c < NCB; ++c) bv[c] = Bp[4 * kk * BS + c * 16 + ((c & 1) ? -sw : sw)];
-#pragma unroll
-        for (int c = 0; c < NCB; ++c) acc[c] = mfma16(a[kk], bv[c], acc[c]);
-      }
-      // B reads run two k-steps ahead (paired reads of two columns)
-      constexpr int RD = (NCB + 1) / 2;
-      mfma_lds_pipeline<2 * RD, (KQ - 2) * RD, (NCB + RD - 1) / RD, 2 * NCB>();
-    }
-    if (more) {
-      lstore((kb + 1) & 1);
-      if constexpr (S::DMA) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-#pragma unroll
-      for (int v = 0; v < KQ / E; ++v) ac[v] = an[v];
-    }
-    __syncthreads();
+  for (int kb = 0; kb < nkb; kb += 2) {
+    step(std::integral_constant<int, 0>{}, kb);
+    if (kb + 1 < nkb) step(std::integral_constant<int, 1>{}, kb + 1);
   }
 
   // stage 64 rows at a time in LDS, then write spec rows contiguously
@@ -393,44 +425,48 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
   // block kb + 1, requested one block earlier, goes to LDS afterwards.
   V an[2][S::NV], ac[S::NV];
   V rq[2][S::NQ][QV];
+  // The tile's spectra as a buffer starting at its first field and wave
+  // number: reads past the end of the level's spectra return zero (fields
+  // beyond F), rows beyond n = N are masked; offsets stay below 4 GiB (at
+  // most 16 NCB fields of at most (N+1)(N+2)/2 rows).
+  const long long sfirst = ((long long)(c0 >> 1) * nc + sbase) * 2;
+  const long long sbytes = ((long long)L.F * nc * 2 - sfirst) * (long long)sizeof(T);
+  const __amdgpu_buffer_rsrc_t srs = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<T*>(spec + sfirst), (short)0, (int)(unsigned)(sbytes > 0xFFFFFFFFLL ? 0xFFFFFFFFLL : sbytes),
+      0x00020000);
+  // (issued unconditionally, also by waves without latitudes in this tile
+  // and for blocks past the end, clamped: with straight-line loads the
+  // compiler's wait counts cover exactly the block that is consumed)
   auto gload = [&](int kb, V (&av)[S::NV], V (&bq)[S::NQ][QV]) {
-    if (active) {
 #pragma unroll
-      for (int v = 0; v < S::NV; ++v)
-        av[v] = *reinterpret_cast<const V*>(arun + (long long)kb * S::CHUNK + v * 64 * E);
-    }
+    for (int v = 0; v < S::NV; ++v)
+      av[v] = *reinterpret_cast<const V*>(arun + (long long)kb * S::CHUNK + v * 64 * E);
 #pragma unroll
     for (int i = 0; i < S::NQ; ++i) {
       const int qq = tid + i * 512;
       const int fl = qq / (KR / 2), rp = qq % (KR / 2);
-      const int f = (c0 >> 1) + fl;
       const int r = kb * 2 * KR + 4 * rp;  // first natural row of the quad
-      const T* src = spec + ((long long)f * nc + sbase + r) * 2;
-      const bool okf = (S::NQ * 512 == S::QUADS || qq < S::QUADS) && f < L.F;
+      const unsigned off = ((unsigned)fl * (unsigned)nc + (unsigned)r) * 2u * (unsigned)sizeof(T);
+      // vector u holds natural rows r + u E/2 .. r + (u+1) E/2 - 1; rows
+      // beyond n = N are masked when the quad is stored to LDS
 #pragma unroll
-      for (int u = 0; u < QV; ++u) {
-        // vector u holds natural rows r + u E/2 .. r + (u+1) E/2 - 1
-        if (okf && r + (u + 1) * E / 2 <= nm) {
-          bq[i][u] = *reinterpret_cast<const V*>(src + u * E);
-        } else {
-#pragma unroll
-          for (int e = 0; e < E; ++e) bq[i][u][e] = (okf && r + (u * E + e) / 2 < nm) ? src[u * E + e] : (T)0;
-        }
-      }
+      for (int u = 0; u < QV; ++u)
+        bq[i][u] = __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(srs, (int)(off + 16u * u), 0, 0));
     }
   };
-  auto lstore = [&](int stage, const V (&bq)[S::NQ][QV]) {
+  auto lstore = [&](int stage, const V (&bq)[S::NQ][QV], int kb) {
     T* dst = Bs + stage * S::STAGE;
 #pragma unroll
     for (int i = 0; i < S::NQ; ++i) {
       const int qq = tid + i * 512;
       if (S::NQ * 512 == S::QUADS || qq < S::QUADS) {
         const int fl = qq / (KR / 2), rp = qq % (KR / 2);
+        const int r = kb * 2 * KR + 4 * rp;
         T x[8];
 #pragma unroll
         for (int u = 0; u < QV; ++u)
 #pragma unroll
-          for (int e = 0; e < E; ++e) x[u * E + e] = bq[i][u][e];
+          for (int e = 0; e < E; ++e) x[u * E + e] = r + (u * E + e) / 2 < nm ? bq[i][u][e] : (T)0;
         // x = re, im of natural rows r, r+1, r+2, r+3: parity par, r' = 2 rp + h
 #pragma unroll
         for (int par = 0; par < 2; ++par)
@@ -472,19 +508,20 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
   // kb + 2), 1 - H that of block kb + 1
   auto step = [&](auto hc, int kb) {
     constexpr int H = decltype(hc)::value;
-    if (kb + 2 < nkb) gload(kb + 2, an[H], rq[H]);
+    gload(kb + 2 < nkb ? kb + 2 : nkb - 1, an[H], rq[H]);
     if (active) compute(H);
-    if (kb + 1 < nkb) {
-      lstore(1 - H, rq[1 - H]);
+    // after the last block this fills the idle stage with a clamped block
+    // (nothing reads it), which keeps the loop free of branches around
+    // memory operations
+    lstore(1 - H, rq[1 - H], kb + 1 < nkb ? kb + 1 : nkb - 1);
 #pragma unroll
-      for (int v = 0; v < S::NV; ++v) ac[v] = an[1 - H][v];
-    }
-    __syncthreads();
+    for (int v = 0; v < S::NV; ++v) ac[v] = an[1 - H][v];
+    lds_barrier();
   };
 
   gload(0, an[0], rq[0]);
-  if (nkb > 1) gload(1, an[1], rq[1]);
-  lstore(0, rq[0]);
+  gload(nkb > 1 ? 1 : 0, an[1], rq[1]);
+  lstore(0, rq[0], 0);
 #pragma unroll
   for (int v = 0; v < S::NV; ++v) ac[v] = an[0][v];
   __syncthreads();
