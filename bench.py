@@ -67,18 +67,28 @@ KERNEL_PREFIX = {("legendre_analysis", "fp32"): "sht::k_legendre_analysis<float,
                  ("legendre_synthesis", "bf16x6"): "sht::k_legendre_synthesis_bf16<"}
 
 
+def source_digest(form):
+    """SHA-256 prefix of the sources the form's Legendre kernels are built
+    from (kernel file, then the shared device header)."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_1711_11296_amd", "csrc")
+    files = ["sht_legendre_bf16.hip" if form == "bf16x6" else "sht_legendre.hip", "sht_device.h"]
+    h = hashlib.sha256()
+    for f in files:
+        h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
 def counted_traffic(stage, form, config):
     """HBM bytes per launch of the stage's kernel from the committed counter
     summary (FETCH_SIZE and WRITE_SIZE runs, scaled by a plain-copy
     calibration), or None when there is none or the kernel source changed
     since the counters were taken."""
     import glob
-    import hashlib
     prefix = KERNEL_PREFIX.get((stage, form))
     if prefix is None:
         return None
-    src = os.path.join(ROOT, "paper_1711_11296_amd", "csrc", "sht_legendre.hip")
-    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    digest = source_digest(form)
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "%s_%s_hbm_counters.md" % (config, form)))):
         for line in open(path):
             parts = line.split()

@@ -89,7 +89,6 @@ struct GemmArgs {
 int zonal_fields_per_block(int form);
 int launch_zonal(int form, bool analysis, const FftArgs& a, int maxN, void* stream);
 int launch_legendre(int form, bool analysis, const GemmArgs& g, int ncb, void* stream);
-size_t legendre_lds_bytes(int form, bool analysis, int ncb);
 
 }  // namespace sht
 
