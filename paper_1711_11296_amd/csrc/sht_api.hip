@@ -223,23 +223,17 @@ std::vector<Tile> build_tiles(const sht_plan_s* P, bool analysis, int ncb, int s
       const int nm = L.N - m + 1;
       for (int cb = 0; cb < ncol; ++cb) {
         if (analysis) {
-          // 128-row tiles for the FP32/FP64 kernels, 64 for the split form
-          const int rows = P->form == SHT_FORM_BF16X6 ? 64 : 128;
-          for (int rb = 0; rb < (nm + rows - 1) / rows; ++rb) {
+          for (int rb = 0; rb < (nm + 127) / 128; ++rb) {
             t.push_back(Tile{l, m, rb, cb});
             c.push_back((double)L.Kp * BN);
           }
-        } else if (P->form == SHT_FORM_BF16X6) {
-          for (int jb = 0; jb < (L.Jh + 63) / 64; ++jb) {
-            t.push_back(Tile{l, m, jb, cb});
-            c.push_back(((double)roundup(nm, 32) + 16.0) * BN);
-          }
         } else {
-          // 128-latitude tiles, K blocks of 32 natural rows
-          const int kr2 = 32;
+          // 128-latitude tiles; K blocks of 32 natural rows (64 in the
+          // split form)
+          const int kr2 = P->form == SHT_FORM_BF16X6 ? 64 : 32;
           for (int jt = 0; jt < (L.Jh + 127) / 128; ++jt) {
             t.push_back(Tile{l, m, jt, cb});
-            c.push_back(((double)roundup(nm, kr2) + 32.0) * 2 * BN);
+            c.push_back(((double)roundup(nm, kr2) + kr2) * 2 * BN);
           }
         }
       }
@@ -302,78 +296,6 @@ void fill_table_level(const LevelDesc& L, const double* mu, const double* sint,
                                      (size_t)(v * 64 + ln) * E + e;
                     sb[d] = (r < nm && j < Jh) ? (T)col[(size_t)r * Jh + j] : (T)0;
                   }
-      }
-    });
-  }
-  for (auto& th : pool) th.join();
-}
-
-// bfloat16 of a float, round to nearest even (finite inputs)
-uint16_t bf16_rne(float f) {
-  uint32_t u;
-  std::memcpy(&u, &f, 4);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
-
-double bf16_value(uint16_t h) {
-  uint32_t u = (uint32_t)h << 16;
-  float f;
-  std::memcpy(&f, &u, 4);
-  return (double)f;
-}
-
-// three bfloat16 pieces v ~ p0 + p1 + p2, each the rounding of the remainder
-void split3(double v, uint16_t* pc) {
-  double r = v;
-  for (int k = 0; k < 3; ++k) {
-    pc[k] = bf16_rne((float)r);
-    r -= bf16_value(pc[k]);
-  }
-}
-
-// As fill_table_level, for the split form: three bfloat16 planes per copy;
-// the synthesis copy is blocked per (64-row j block, 64-row r block) as
-// [parity][64 j][32 r'] with r = 64 kb + 2 r' + parity.
-void fill_table_level_bf16(const LevelDesc& L, const double* mu, const double* sint, uint16_t* dst,
-                           const long long* off_a, size_t plane_a, uint16_t* dsyn, const long long* off_s,
-                           size_t plane_s) {
-  const int N = L.N, Jh = L.Jh, Kp = L.Kp;
-  const int JB = (Jh + 63) / 64;
-  int nth = (int)std::thread::hardware_concurrency();
-  nth = std::max(1, std::min(nth, 64));
-  std::vector<std::thread> pool;
-  for (int t = 0; t < nth; ++t) {
-    pool.emplace_back([=]() {
-      std::vector<double> col;
-      uint16_t pc[3];
-      for (int k = t; k <= N; k += nth) {
-        const int m = (k % 2 == 0) ? k / 2 : N - k / 2;
-        const int nm = N - m + 1;
-        col.assign((size_t)nm * Jh, 0.0);
-        alf_column(N, m, Jh, mu, sint, col.data(), Jh);
-        const int R = (int)roundup(nm, SHT_ROWS_PAD);
-        for (int r = 0; r < R; ++r)
-          for (int j = 0; j < Kp; ++j) {
-            const double v = (r < nm && j < Jh) ? col[(size_t)r * Jh + j] : 0.0;
-            split3(v, pc);
-            const size_t e = (size_t)off_a[m] + (size_t)r * Kp + j;
-            for (int q = 0; q < 3; ++q) dst[q * plane_a + e] = pc[q];
-          }
-        const int nkb = (nm + 63) / 64;
-        for (int jb = 0; jb < JB; ++jb)
-          for (int kb = 0; kb < nkb; ++kb) {
-            const size_t b = (size_t)off_s[m] + ((size_t)jb * nkb + kb) * 4096;
-            for (int par = 0; par < 2; ++par)
-              for (int jl = 0; jl < 64; ++jl)
-                for (int kl = 0; kl < 32; ++kl) {
-                  const int r = kb * 64 + 2 * kl + par, j = jb * 64 + jl;
-                  const double v = (r < nm && j < Jh) ? col[(size_t)r * Jh + j] : 0.0;
-                  split3(v, pc);
-                  const size_t e = b + (par * 64 + jl) * 32 + kl;
-                  for (int q = 0; q < 3; ++q) dsyn[q * plane_s + e] = pc[q];
-                }
-          }
       }
     });
   }
@@ -446,15 +368,11 @@ int build_plan(int nlev, const int* Nv, const int* Jv, const int* Iv, const int*
     woff += roundup((long long)(L.N + 1) * 2 * L.Kp * L.Cp, 64);
     for (int m = 0; m <= L.N; ++m) {
       taboff.push_back(tab);
-      // analysis copy: rows padded to the row tile (128; 64 in the split form)
-      tab += roundup(L.N - m + 1, o.form == SHT_FORM_BF16X6 ? SHT_ROWS_PAD : 128) * L.Kp;
+      // analysis copy: rows padded to the row tile of 128
+      tab += roundup(L.N - m + 1, 128) * L.Kp;
       taboff_syn.push_back(tabs);
-      if (o.form == SHT_FORM_BF16X6) {
-        tabs += (long long)((L.Jh + 63) / 64) * ((L.N - m + 1 + 63) / 64) * 4096;
-      } else {
-        const int kr2 = 32;  // natural rows per K block
-        tabs += (long long)((L.Jh + 127) / 128) * ((L.N - m + kr2) / kr2) * 128 * kr2;
-      }
+      const int kr2 = 32;  // natural rows per K block
+      tabs += (long long)((L.Jh + 127) / 128) * ((L.N - m + kr2) / kr2) * 128 * kr2;
     }
     P->maxN = std::max(P->maxN, L.N);
     P->flops += 2.0 * L.Jh * (double)(L.N + 1) * (L.N + 2) * L.F;
@@ -470,8 +388,8 @@ int build_plan(int nlev, const int* Nv, const int* Jv, const int* Iv, const int*
   P->ws_elems = (size_t)woff;
   P->table_elems = (size_t)tab;
   P->table_syn_elems = (size_t)tabs;
-  // bytes per table element: the data type, or three bfloat16 planes
-  const size_t tel = o.form == SHT_FORM_BF16X6 ? 6 : P->elem;
+  // bytes per table element (the split form reads the FP32 copies)
+  const size_t tel = P->elem;
   P->table_bytes = (P->table_elems + P->table_syn_elems) * tel;
   P->ws_bytes = P->ws_elems * P->elem;
 
@@ -495,9 +413,6 @@ int build_plan(int nlev, const int* Nv, const int* Jv, const int* Iv, const int*
     if (o.form == SHT_FORM_FP64)
       fill_table_level<double>(L, mu.data(), sint.data(), reinterpret_cast<double*>(htab.data()), to,
                                reinterpret_cast<double*>(htabs.data()), ts);
-    else if (o.form == SHT_FORM_BF16X6)
-      fill_table_level_bf16(L, mu.data(), sint.data(), reinterpret_cast<uint16_t*>(htab.data()), to,
-                            P->table_elems, reinterpret_cast<uint16_t*>(htabs.data()), ts, P->table_syn_elems);
     else
       fill_table_level<float>(L, mu.data(), sint.data(), reinterpret_cast<float*>(htab.data()), to,
                               reinterpret_cast<float*>(htabs.data()), ts);
@@ -521,10 +436,11 @@ int build_plan(int nlev, const int* Nv, const int* Jv, const int* Iv, const int*
 
   // ---- tile schedules (default; the autotuner may replace them) ----
   P->ncb_fwd = P->ncb_inv = P->ncb;
-  if (o.form == SHT_FORM_BF16X6 && P->ncb > 5) {
-    // the split synthesis kernel keeps 4 row blocks of all three pieces in
-    // registers: use at most 5 column blocks per tile when the layout allows
-    for (int c = 5; c >= 1; --c) {
+  if (P->ncb > max_synthesis_ncb(o.form)) {
+    // the synthesis kernel keeps its whole output tile in registers: take the
+    // widest blocking it supports that divides every level's row length
+    for (int c : {8, 5, 4, 2, 1}) {
+      if (c > max_synthesis_ncb(o.form)) continue;
       bool ok = true;
       for (int l = 0; l < nlev; ++l)
         if (P->lev[l].Cp % (16 * c)) ok = false;
@@ -631,7 +547,6 @@ GemmArgs gemm_args(const sht_plan_s* P, bool analysis, const void* spec_in, void
   g.tiles = analysis ? P->d_tiles_fwd : P->d_tiles_inv;
   g.tab_off = analysis ? P->d_taboff : P->d_taboff_syn;
   g.table = analysis ? P->d_table : P->d_table_syn;
-  g.table_plane = (long long)(analysis ? P->table_elems : P->table_syn_elems);
   g.spec_in = spec_in;
   g.spec_out = spec_out;
   g.ws = P->d_ws;
@@ -823,9 +738,10 @@ int autotune(sht_plan_s* P) {
     for (int dir = 0; dir < 2 && !rc; ++dir) {
       const bool analysis = dir == 0;
       float best = 1e30f;
-      int bc = P->ncb, bs = 0;
+      int bc = analysis ? P->ncb_fwd : P->ncb_inv, bs = 0;
       for (int c : cands)
         for (int sched = 0; sched < 2 && !rc; ++sched) {
+          if (!analysis && c > max_synthesis_ncb(P->form)) continue;
           std::vector<Tile> t = build_tiles(P, analysis, c, sched);
           Tile* dt = nullptr;
           if ((rc = hip_check(hipMalloc(reinterpret_cast<void**>(&dt), t.size() * sizeof(Tile)), "tune alloc"))) break;

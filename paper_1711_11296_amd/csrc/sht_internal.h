@@ -11,8 +11,6 @@
 #define SHT_MAX_RADICES 12
 #define SHT_MAX_I 4096
 
-// Table rows of one m are padded to a multiple of this (forward tile height).
-#define SHT_ROWS_PAD 64
 // Latitude (contraction) dimension of the table and workspace is padded to a
 // multiple of this.
 #define SHT_K_PAD 32
@@ -77,8 +75,7 @@ struct GemmArgs {
   LevelDesc lev[SHT_MAX_LEVELS];
   const Tile* tiles;           // one per workgroup
   const long long* tab_off;    // per (level, m): element offset of the table block
-  const void* table;           // P~ table (data type, or 3 bf16 planes)
-  long long table_plane;       // elements per bf16 plane (split form)
+  const void* table;           // P~ table copy (FP64 in the FP64 form, else FP32)
   const void* spec_in;         // synthesis: spectra
   void* spec_out;              // analysis: spectra
   void* ws;                    // workspace
@@ -89,6 +86,8 @@ struct GemmArgs {
 int zonal_fields_per_block(int form);
 int launch_zonal(int form, bool analysis, const FftArgs& a, int maxN, void* stream);
 int launch_legendre(int form, bool analysis, const GemmArgs& g, int ncb, void* stream);
+// Widest column blocking (16-column units) the synthesis kernel of a form takes.
+int max_synthesis_ncb(int form);
 
 }  // namespace sht
 

@@ -480,39 +480,45 @@ static size_t lds_synthesis(int ncb) {
     case 4: return SynthesisShape<T, 4>::lds_bytes();
     case 5: return SynthesisShape<T, 5>::lds_bytes();
     case 8: return SynthesisShape<T, 8>::lds_bytes();
-    default: return SynthesisShape<T, 10>::lds_bytes();
+    default: return SynthesisShape<T, 8>::lds_bytes();
   }
+}
+
+constexpr int kMaxSynthesisNcb = 8;
+
+template <typename T, int NCB>
+static hipError_t launch_ncb(bool analysis, const GemmArgs& g, hipStream_t st) {
+  const dim3 grid(g.ntiles), block(512);
+  if constexpr (sizeof(T) == 8 && NCB > 8) return hipErrorInvalidValue;  // FP64 takes at most 8
+  else if (analysis) {
+    lds_optin<k_legendre_analysis<T, NCB>>(lds_analysis<T>(NCB));
+    hipLaunchKernelGGL((k_legendre_analysis<T, NCB>), grid, block, lds_analysis<T>(NCB), st, g);
+  } else {
+    // wider synthesis tiles do not fit the register file
+    if constexpr (NCB > kMaxSynthesisNcb) return hipErrorInvalidValue;
+    else {
+      lds_optin<k_legendre_synthesis<T, NCB>>(lds_synthesis<T>(NCB));
+      hipLaunchKernelGGL((k_legendre_synthesis<T, NCB>), grid, block, lds_synthesis<T>(NCB), st, g);
+    }
+  }
+  return hipGetLastError();
 }
 
 template <typename T>
 static hipError_t launch_legendre_t(bool analysis, const GemmArgs& g, int ncb,
                                     hipStream_t st) {
-  const dim3 grid(g.ntiles), block(256), block_a(512);
-#define SHT_LLAUNCH(NCB_)                                                        \
-  case NCB_:                                                                    \
-    if (analysis) {                                                             \
-      lds_optin<k_legendre_analysis<T, NCB_>>(lds_analysis<T>(NCB_));          \
-      hipLaunchKernelGGL((k_legendre_analysis<T, NCB_>), grid, block_a,        \
-                         lds_analysis<T>(NCB_), st, g);                         \
-    } else {                                                                    \
-      lds_optin<k_legendre_synthesis<T, NCB_>>(lds_synthesis<T>(NCB_));        \
-      hipLaunchKernelGGL((k_legendre_synthesis<T, NCB_>), grid, block_a,       \
-                         lds_synthesis<T>(NCB_), st, g);                        \
-    }                                                                           \
-    break;
   switch (ncb) {
-    SHT_LLAUNCH(1)
-    SHT_LLAUNCH(2)
-    SHT_LLAUNCH(4)
-    SHT_LLAUNCH(5)
-    SHT_LLAUNCH(8)
-    SHT_LLAUNCH(10)
-    default:
-      return hipErrorInvalidValue;
+    case 1: return launch_ncb<T, 1>(analysis, g, st);
+    case 2: return launch_ncb<T, 2>(analysis, g, st);
+    case 4: return launch_ncb<T, 4>(analysis, g, st);
+    case 5: return launch_ncb<T, 5>(analysis, g, st);
+    case 8: return launch_ncb<T, 8>(analysis, g, st);
+    case 10: return launch_ncb<T, 10>(analysis, g, st);
+    default: return hipErrorInvalidValue;
   }
-#undef SHT_LLAUNCH
-  return hipGetLastError();
 }
+
+int max_synthesis_ncb(int form) { return form == SHT_FORM_BF16X6 ? 10 : kMaxSynthesisNcb; }
 
 int launch_legendre(int form, bool analysis, const GemmArgs& g, int ncb,
                     void* stream) {

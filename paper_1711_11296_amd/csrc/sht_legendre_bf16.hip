@@ -1,6 +1,7 @@
-// Legendre stage in the split-bfloat16 form (see sht_legendre.hip for the
-// transform and the data layouts): operands carried as three bfloat16
-// pieces, six piece products per term on the bfloat16 matrix cores, FP32
+// Legendre stage in the split-bfloat16 form (the transform, the tile lists
+// and the FP32 table layouts are those of sht_legendre.hip): the FP32
+// operands are split into three bfloat16 pieces inside the kernels, six
+// piece products per term run on the bfloat16 matrix cores, FP32
 // accumulation.
 
 #include <hip/hip_runtime.h>
@@ -13,426 +14,460 @@
 namespace sht {
 
 // ---------------------------------------------------------------------------
-// Split-bfloat16 form: every operand x is carried as three bfloat16 pieces
-// x = x0 + x1 + x2 (8 significant bits each).  The product of two operands
-// is accumulated in FP32 from the six piece products whose piece indices sum
-// to at most 2 (x0 y0, x0 y1, x1 y0, x0 y2, x1 y1, x2 y0), smallest first;
-// the three dropped products are below 2^-24 relative.  Table pieces are
-// split from FP64 on the host; the right-hand operand (FP32) is split in the
-// kernel by truncation, which is exact: x - x0 and (x - x0) - x1 are
-// representable, and the remainder has at most 8 significant bits.
-// MFMA: v_mfma_f32_16x16x32_bf16 (lane l supplies 8 consecutive k values
-// 8*(l/16) + e of row/column l%16; result layout as for the FP32 16x16x4).
+// Split-bfloat16 form.  An FP32 value x is written as x = x0 + x1 + x2 with
+// bfloat16 pieces: x0 = bf16(x), x1 = bf16(x - x0), x2 = x - x0 - x1, each
+// rounded to nearest.  The splitting is exact: x - x0 is a multiple of the
+// FP32 unit of x below half a bfloat16 unit, so it has at most 16
+// significant bits, and the last remainder at most 8, which bfloat16 holds.
+// |x1| <= 2^-8 |x| and |x2| <= 2^-16 |x|.  A product a*b is accumulated in
+// FP32 from the six piece products whose piece indices sum to at most 2,
+// smallest first (a2 b0, a1 b1, a0 b2, a1 b0, a0 b1, a0 b0); every piece
+// product is exact in FP32 and the three dropped ones are below 2^-23 |a b|
+// together, the size of one FP32 rounding.
+//
+// Both operands are split in the kernels: the table from its FP32 copies
+// (the same arrays the FP32 form reads), the workspace or spectra when they
+// are staged in LDS, where they are stored as three bfloat16 planes laid out
+// for the matrix-core reads.  Memory traffic is therefore that of the FP32
+// form, and the matrix work is 6 bfloat16 steps of 16x16x32 per 8 FP32
+// steps of 16x16x4 with each step at 8 times the FP32 rate per cycle.
+//
+// MFMA: v_mfma_f32_16x16x32_bf16.  Lane l supplies 8 values of row (A) or
+// column (B) l%16 in the contraction slots 8*(l/16) .. 8*(l/16)+7; element i
+// of its result is row 4*(l/16) + i, column l%16.  Which contraction index
+// sits in which slot is free as long as A and B agree; the kernels use the
+// assignment the FP32 table copies already have (below).
 // ---------------------------------------------------------------------------
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x8 __attribute__((ext_vector_type(8)));
 
 __device__ __forceinline__ f32x4 mfma_bf16(bf16x8 a, bf16x8 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
-// Split 8 floats into three bfloat16x8 pieces (exact, by truncation).
-__device__ __forceinline__ void split3x8(const float (&x)[8], bf16x8& h, bf16x8& m, bf16x8& l) {
-  unsigned uh[8], um[8], ul[8];
-#pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    const unsigned u = __float_as_uint(x[e]);
-    const float fh = __uint_as_float(u & 0xFFFF0000u);
-    const float r = x[e] - fh;
-    const unsigned ur = __float_as_uint(r);
-    const float fm = __uint_as_float(ur & 0xFFFF0000u);
-    const float r2 = r - fm;
-    uh[e] = u;
-    um[e] = ur;
-    ul[e] = __float_as_uint(r2);
-  }
-  u32x4 ph, pm, pl;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    ph[q] = (uh[2 * q] >> 16) | (uh[2 * q + 1] & 0xFFFF0000u);
-    pm[q] = (um[2 * q] >> 16) | (um[2 * q + 1] & 0xFFFF0000u);
-    pl[q] = (ul[2 * q] >> 16) | (ul[2 * q + 1] & 0xFFFF0000u);
-  }
-  h = __builtin_bit_cast(bf16x8, ph);
-  m = __builtin_bit_cast(bf16x8, pm);
-  l = __builtin_bit_cast(bf16x8, pl);
+// three bfloat16 pieces of n floats (n = 4 or 8), rounded to nearest
+template <typename F, typename B>
+__device__ __forceinline__ void split3(F x, B (&pc)[3]) {
+  pc[0] = __builtin_convertvector(x, B);
+  const F r = x - __builtin_convertvector(pc[0], F);
+  pc[1] = __builtin_convertvector(r, B);
+  pc[2] = __builtin_convertvector(r - __builtin_convertvector(pc[1], F), B);
 }
 
-// acc += a * b with a = (a0, a1, a2) and b = (b0, b1, b2) split operands
-__device__ __forceinline__ f32x4 mfma6(const bf16x8 (&a)[3], bf16x8 b0, bf16x8 b1, bf16x8 b2,
-                                       f32x4 acc) {
-  acc = mfma_bf16(a[2], b0, acc);
-  acc = mfma_bf16(a[1], b1, acc);
-  acc = mfma_bf16(a[0], b2, acc);
-  acc = mfma_bf16(a[1], b0, acc);
-  acc = mfma_bf16(a[0], b1, acc);
-  acc = mfma_bf16(a[0], b0, acc);
+// acc += a * b from the pieces of both operands
+__device__ __forceinline__ f32x4 mfma6(const bf16x8 (&a)[3], const bf16x8 (&b)[3], f32x4 acc) {
+  acc = mfma_bf16(a[2], b[0], acc);
+  acc = mfma_bf16(a[1], b[1], acc);
+  acc = mfma_bf16(a[0], b[2], acc);
+  acc = mfma_bf16(a[1], b[0], acc);
+  acc = mfma_bf16(a[0], b[1], acc);
+  acc = mfma_bf16(a[0], b[0], acc);
   return acc;
 }
 
-// Analysis in the split form.  Same tiling as the FP32 kernel (64 rows x
-// 16*NCB columns, waves (parity, column half)); the contraction advances 32
-// latitudes per block, one 16x16x32 step per piece product.
+// Pieces of the right-hand operand in LDS: [piece][parity][column][PITCH]
+// bfloat16, the 32 contraction slots of a column contiguous and padded to
+// 80 bytes, so that the 16-byte reads of 8 consecutive columns (one LDS
+// cycle) fall on 8 distinct groups of 4 banks.
+constexpr int kX6Pitch = 40;
+
+// ---------------------------------------------------------------------------
+// analysis: C[n][c] = P[n][j] * B_par(n)[j][c]
+// tile = 128 rows r = n - m (both parities) x BN = 16*NCB columns, 4 waves.
+// Wave w: parity p = w & 1, row half q = w >> 1; it owns the 32 rows
+// r = 64 q + 32 h + 2 i + p (h < 2, two MFMA row blocks) and all NCB column
+// blocks; each B read feeds both row blocks.  The contraction runs over
+// latitudes in blocks of 32; lane (i, g) holds, in slot 8 g + e (e < 8),
+// latitude 4 e + g of the block: exactly the values its run of the FP32
+// analysis table copy holds (that copy is blocked for 16-row runs; row
+// block h of wave (q, p) is run 4 q + 2 h + p).
+// The workspace block (both parities, 32 x BN) is fetched into registers one
+// block ahead, split and stored into LDS; one LDS stage per workgroup and
+// two workgroups per CU, one in its split/store phase while the other runs
+// its matrix steps.
+// ---------------------------------------------------------------------------
 template <int NCB>
-__global__ __launch_bounds__(256) void k_legendre_analysis_bf16(const GemmArgs g) {
-  typedef typename V16<float>::type V;
-  constexpr int KB = 32;
-  constexpr int BN = 16 * NCB;
-  constexpr int HC = (NCB + 1) / 2;
-  constexpr int AS = 40;                   // bf16 per LDS row of A (5 x 16 bytes)
-  constexpr int BS = BN + 2;               // conflict-free B reads
-  constexpr int NA = 3 * 64 * KB / 8 / 256;
-  constexpr int NB = 2 * KB * BN / 4 / 256;
+struct X6Analysis {
+  static constexpr int BN = 16 * NCB;
+  static constexpr int KB = 32;                      // latitudes per block
+  static constexpr int PLANE = 2 * BN * kX6Pitch;    // bfloat16 per piece
+  static constexpr int TASKS = 2 * BN;               // (parity, column quad, g)
+  static constexpr int TR = (TASKS + 255) / 256;     // task rounds per thread
+  static constexpr int CS = BN + 1;                  // output staging pitch
+  static constexpr size_t lds_bytes() {
+    const size_t main = (size_t)3 * PLANE * 2;
+    const size_t cst = (size_t)64 * CS * 4;
+    return main > cst ? main : cst;
+  }
+};
+
+template <int NCB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_legendre_analysis_bf16(const GemmArgs g) {
+  using S = X6Analysis<NCB>;
+  constexpr int BN = S::BN, KB = S::KB, P = kX6Pitch;
+  typedef float f4 __attribute__((ext_vector_type(4)));
 
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  unsigned short* As = reinterpret_cast<unsigned short*>(smem_raw);   // [3][2][32][AS]
-  float* Bs = reinterpret_cast<float*>(smem_raw + 3 * 64 * AS * 2);   // [2][KB][BS]
+  __bf16* Bs = reinterpret_cast<__bf16*>(smem_raw);
 
   const Tile t = g.tiles[blockIdx.x];
   if (t.level < 0) return;
   const LevelDesc& L = g.lev[t.level];
   const int N = L.N, m = t.m;
   const int nm = N - m + 1;
-  const int r0 = t.rb * 64;
+  const int r0 = t.rb * 128;
   const int c0 = t.cb * BN;
   const int Kp = L.Kp;
   const long long Cp = L.Cp;
-  const unsigned short* tab = static_cast<const unsigned short*>(g.table) + g.tab_off[L.m_base + m] +
-                              (long long)r0 * Kp;
   const long long plane = (long long)Kp * Cp;
   const float* wsm = static_cast<const float*>(g.ws) + L.ws_off + (2LL * m) * plane + c0;
 
   const int tid = threadIdx.x;
-  // wave-uniform values live in scalar registers, so the per-wave choices
-  // below are scalar branches around whole K-blocks
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
-  const int p = w & 1, ch = w >> 1;
+  const int p = w & 1, q = w >> 1;
   const int li = lane & 15, lg = lane >> 4;
-  const int nrb = (r0 + 32 + p) < nm ? 2 : ((r0 + p) < nm ? 1 : 0);  // active row blocks
-  const bool full_cols = ch == 0;  // HC column blocks, else NCB - HC
+  const bool active = r0 + 64 * q + p < nm;
+  // run 4 q + p of the table block; row block h adds two runs
+  const float* arow = static_cast<const float*>(g.table) + g.tab_off[L.m_base + m] +
+                      (long long)t.rb * Kp * 128 + (4 * q + p) * 16 * KB + lane * 4;
 
-  f32x4 acc[2][HC];
+  f32x4 acc[2][NCB];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int h = 0; h < 2; ++h)
 #pragma unroll
-    for (int c = 0; c < HC; ++c) acc[a][c] = f32x4{0, 0, 0, 0};
+    for (int c = 0; c < NCB; ++c) acc[h][c] = f32x4{0, 0, 0, 0};
 
-  u32x4 ra[NA];
-  V rb[NB];
-  auto gload = [&](int k0) {
+  // table: two K blocks ahead in two register sets (loop unrolled by two);
+  // [h][v]: vector v holds slots 4 v .. 4 v + 3
+  f4 an[2][2][2];
+  // workspace: one K block ahead; task u = ((par * BN/4) + cq) * 4 + gg holds
+  // latitudes 4 e + gg (e < 8) of columns 4 cq .. 4 cq + 3 of parity par
+  f4 bq[S::TR][8];
+  auto gload_a = [&](int kb, f4 (&av)[2][2]) {
 #pragma unroll
-    for (int i = 0; i < NA; ++i) {
-      const int q = tid + i * 256;
-      const int pc = q / 256, rem = q % 256;
-      const int row = rem / 4, cv = rem % 4;
-      ra[i] = *reinterpret_cast<const u32x4*>(tab + pc * g.table_plane + (long long)row * Kp + k0 + cv * 8);
-    }
+    for (int h = 0; h < 2; ++h)
 #pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      const int q = tid + i * 256;
-      const int par = q / (KB * BN / 4);
-      const int rem = q - par * (KB * BN / 4);
-      const int row = rem / (BN / 4), cv = rem % (BN / 4);
-      rb[i] = *reinterpret_cast<const V*>(wsm + par * plane + (long long)(k0 + row) * Cp + cv * 4);
+      for (int v = 0; v < 2; ++v)
+        av[h][v] = *reinterpret_cast<const f4*>(arow + (long long)kb * 128 * KB + h * 32 * KB + v * 256);
+  };
+  auto gload_b = [&](int kb) {
+#pragma unroll
+    for (int i = 0; i < S::TR; ++i) {
+      int u = tid + i * 256;
+      if (S::TR * 256 != S::TASKS && u >= S::TASKS) u = S::TASKS - 1;  // clamped, not stored
+      const int gg = u & 3, cq = (u >> 2) % (BN / 4), par = (u >> 2) / (BN / 4);
+      const float* src = wsm + par * plane + (long long)(kb * KB + gg) * Cp + 4 * cq;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) bq[i][e] = *reinterpret_cast<const f4*>(src + 4LL * e * Cp);
     }
   };
   auto lstore = [&]() {
 #pragma unroll
-    for (int i = 0; i < NA; ++i) {
-      const int q = tid + i * 256;
-      const int pc = q / 256, rem = q % 256;
-      const int row = rem / 4, cv = rem % 4;
-      *reinterpret_cast<u32x4*>(As + ((pc * 2 + (row & 1)) * 32 + (row >> 1)) * AS + cv * 8) = ra[i];
-    }
+    for (int i = 0; i < S::TR; ++i) {
+      const int u = tid + i * 256;
+      if (S::TR * 256 == S::TASKS || u < S::TASKS) {
+        const int gg = u & 3, cq = (u >> 2) % (BN / 4), par = (u >> 2) / (BN / 4);
 #pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      const int q = tid + i * 256;
-      const int par = q / (KB * BN / 4);
-      const int rem = q - par * (KB * BN / 4);
-      const int row = rem / (BN / 4), cv = rem % (BN / 4);
-      lds_store8<float>(Bs + (par * KB + row) * BS + cv * 4, rb[i]);
-    }
-  };
-
-  const int nkb = Kp / KB;
-  auto kloop = [&](auto nrc, auto ncc) {
-    constexpr int NR = decltype(nrc)::value, NC = decltype(ncc)::value;
-    gload(0);
-    lstore();
-    __syncthreads();
-    for (int kb = 0; kb < nkb; ++kb) {
-      if (kb + 1 < nkb) gload((kb + 1) * KB);
-      if constexpr (NR > 0 && NC > 0) {
-        bf16x8 av[NR][3];
+        for (int cc = 0; cc < 4; ++cc) {
+          const f32x8 x = {bq[i][0][cc], bq[i][1][cc], bq[i][2][cc], bq[i][3][cc],
+                           bq[i][4][cc], bq[i][5][cc], bq[i][6][cc], bq[i][7][cc]};
+          bf16x8 pc[3];
+          split3(x, pc);
 #pragma unroll
-        for (int rb2 = 0; rb2 < NR; ++rb2)
-#pragma unroll
-          for (int pc = 0; pc < 3; ++pc)
-            av[rb2][pc] = __builtin_bit_cast(
-                bf16x8, *reinterpret_cast<const u32x4*>(As + ((pc * 2 + p) * 32 + 16 * rb2 + li) * AS + 8 * lg));
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-          const int cb = ch * HC + c;
-          float bv[8];
-#pragma unroll
-          for (int e = 0; e < 8; ++e) bv[e] = Bs[(p * KB + 8 * lg + e) * BS + cb * 16 + li];
-          bf16x8 b0, b1, b2;
-          split3x8(bv, b0, b1, b2);
-#pragma unroll
-          for (int r = 0; r < NR; ++r) acc[r][c] = mfma6(av[r], b0, b1, b2, acc[r][c]);
+          for (int k = 0; k < 3; ++k)
+            *reinterpret_cast<bf16x8*>(Bs + k * S::PLANE + (par * BN + 4 * cq + cc) * P + 8 * gg) = pc[k];
         }
       }
-      __syncthreads();
-      if (kb + 1 < nkb) {
-        lstore();
-        __syncthreads();
-      }
     }
   };
-  using I0 = std::integral_constant<int, 0>;
-  using I1 = std::integral_constant<int, 1>;
-  using I2 = std::integral_constant<int, 2>;
-  using CH = std::integral_constant<int, HC>;
-  using CL = std::integral_constant<int, NCB - HC>;
-  if (nrb == 0) {
-    kloop(I0{}, CH{});
-  } else if (full_cols || 2 * HC == NCB) {
-    if (nrb == 2)
-      kloop(I2{}, CH{});
-    else
-      kloop(I1{}, CH{});
-  } else {
-    if (nrb == 2)
-      kloop(I2{}, CL{});
-    else
-      kloop(I1{}, CL{});
+  auto compute = [&](const f4 (&av)[2][2]) {
+    bf16x8 a[2][3];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const f32x8 x = {av[h][0][0], av[h][0][1], av[h][0][2], av[h][0][3],
+                       av[h][1][0], av[h][1][1], av[h][1][2], av[h][1][3]};
+      split3(x, a[h]);
+    }
+    const __bf16* Bp = Bs + (p * BN + li) * P + 8 * lg;
+#pragma unroll
+    for (int c = 0; c < NCB; ++c) {
+      bf16x8 b[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) b[k] = *reinterpret_cast<const bf16x8*>(Bp + k * S::PLANE + c * 16 * P);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) acc[h][c] = mfma6(a[h], b, acc[h][c]);
+    }
+  };
+  const int nkb = Kp / KB;
+  // one K block; H = kb & 1 selects the table registers of block kb (and of
+  // kb + 2).  Loads past the end are clamped to the last block (never used),
+  // which keeps memory operations out of branches.
+  auto step = [&](auto hc, int kb) {
+    constexpr int H = decltype(hc)::value;
+    lds_barrier();  // every wave is done reading the previous block
+    lstore();
+    gload_b(kb + 1 < nkb ? kb + 1 : nkb - 1);
+    lds_barrier();
+    f4 ac[2][2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int v = 0; v < 2; ++v) ac[h][v] = an[H][h][v];
+    gload_a(kb + 2 < nkb ? kb + 2 : nkb - 1, an[H]);
+    if (active) compute(ac);
+  };
+
+  gload_a(0, an[0]);
+  gload_b(0);
+  gload_a(nkb > 1 ? 1 : 0, an[1]);
+  for (int kb = 0; kb < nkb; kb += 2) {
+    step(std::integral_constant<int, 0>{}, kb);
+    if (kb + 1 < nkb) step(std::integral_constant<int, 1>{}, kb + 1);
   }
 
-  constexpr int CS = BN + 1;
+  // stage 64 rows at a time in LDS, then write spec rows contiguously
   float* Cs = reinterpret_cast<float*>(smem_raw);  // [64][CS]
-#pragma unroll
-  for (int rb2 = 0; rb2 < 2; ++rb2)
-#pragma unroll
-    for (int c = 0; c < HC; ++c) {
-      const int cb = ch * HC + c;
-      if (cb < NCB) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int rl = 2 * (16 * rb2 + 4 * lg + i) + p;
-          Cs[rl * CS + cb * 16 + li] = acc[rb2][c][i];
-        }
-      }
-    }
-  __syncthreads();
   float* spec = static_cast<float*>(g.spec_out) + L.spec_off;
   const long long nc = (long long)(N + 1) * (N + 2) / 2;
-  const long long base = spec_idx(N, m, m) + r0;
-  for (int q = tid; q < 64 * (BN / 2); q += 256) {
-    const int fl = q >> 6, rl = q & 63;
-    const int f = (c0 >> 1) + fl;
-    if (r0 + rl < nm && f < L.F) {
-      float* d = spec + ((long long)f * nc + base + rl) * 2;
-      d[0] = Cs[rl * CS + 2 * fl];
-      d[1] = Cs[rl * CS + 2 * fl + 1];
+  const long long base = spec_idx(N, m, m);
+#pragma unroll
+  for (int hh = 0; hh < 2; ++hh) {
+    __syncthreads();
+    if (q == hh) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int c = 0; c < NCB; ++c)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) Cs[(32 * h + 2 * (4 * lg + i) + p) * S::CS + c * 16 + li] = acc[h][c][i];
+    }
+    __syncthreads();
+    for (int qq = tid; qq < 64 * (BN / 2); qq += 256) {
+      const int fl = qq >> 6, rl = qq & 63;
+      const int f = (c0 >> 1) + fl;
+      const int r = r0 + 64 * hh + rl;
+      if (r < nm && f < L.F) {
+        float* d = spec + ((long long)f * nc + base + r) * 2;
+        d[0] = Cs[rl * S::CS + 2 * fl];
+        d[1] = Cs[rl * S::CS + 2 * fl + 1];
+      }
     }
   }
 }
 
-// Synthesis in the split form: tile 64 j x 16*NCB columns, contraction over
-// natural rows in blocks of 64 (32 per parity, one 16x16x32 step).  The
-// table comes from its split synthesis copy, blocked per (m, 64-row j block,
-// 64-row r block) as [piece plane][parity][64 j][32 r'].
+// ---------------------------------------------------------------------------
+// synthesis: S_p[j][c] = sum_{r of parity p} P[r][j] * a[r][c]
+// tile = 128 latitudes x BN = 16*NCB columns, both parities, 8 waves.  Wave
+// w: parity p = w & 1, latitude quarter q = w >> 1; it owns the 32
+// latitudes j = 32 q + 16 jb + i (jb < 2) and all NCB column blocks.  The
+// contraction runs over r' (r = 2 r' + p) in blocks of 32 per parity (64
+// natural rows, two blocks of the FP32 synthesis table copy); lane (i, g)
+// holds in slot 8 g + 4 s + u (s < 2, u < 4) r' = 16 s + 4 g + u of the
+// block, which is what its run of table block 2 kb + s holds.
+// The spectra of a block (64 rows x BN/2 fields) are fetched into
+// registers two blocks ahead, split and stored into the other of two LDS
+// stages; one barrier per block.
+// ---------------------------------------------------------------------------
 template <int NCB>
-__global__ __launch_bounds__(256) void k_legendre_synthesis_bf16(const GemmArgs g) {
-  constexpr int BN = 16 * NCB;
-  constexpr int HC = (NCB + 1) / 2;
-  constexpr int KH = 32;                  // table rows per parity and block
-  constexpr int AS = 40;                  // bf16 per LDS row (5 x 16 bytes)
-  constexpr int BS = BN + 2;
-  constexpr int NA = 3 * 2 * 64 * KH / 8 / 256;
-  constexpr int NB = (BN / 2) * KH / 256 > 0 ? (BN / 2) * KH / 256 : 1;
+struct X6Synthesis {
+  static constexpr int BN = 16 * NCB;
+  static constexpr int PLANE = 2 * BN * kX6Pitch;   // bfloat16 per piece
+  static constexpr int STAGE = 3 * PLANE;
+  static constexpr int TASKS = 4 * BN;              // (field, g, s): 8 natural rows
+  static constexpr int TR = (TASKS + 511) / 512;
+  static constexpr int CHUNK = 128 * 32;            // FP32 table block (32 natural rows)
+  static constexpr size_t lds_bytes() { return (size_t)2 * STAGE * 2; }
+};
+
+template <int NCB>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k_legendre_synthesis_bf16(const GemmArgs g) {
+  using S = X6Synthesis<NCB>;
+  constexpr int BN = S::BN, P = kX6Pitch;
+  typedef float f4 __attribute__((ext_vector_type(4)));
 
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  unsigned short* At = reinterpret_cast<unsigned short*>(smem_raw);    // [3][2][64][AS]
-  float* Bs = reinterpret_cast<float*>(smem_raw + 3 * 2 * 64 * AS * 2);  // [2][KH][BS]
+  __bf16* Bs = reinterpret_cast<__bf16*>(smem_raw);  // [2 stage][3 piece][2 parity][BN][P]
 
   const Tile t = g.tiles[blockIdx.x];
   if (t.level < 0) return;
   const LevelDesc& L = g.lev[t.level];
   const int N = L.N, m = t.m;
   const int nm = N - m + 1;
-  const int nkb = (nm + 63) / 64;
-  const int jb = t.rb;
+  const int nkb = (nm + 63) / 64;       // blocks of 64 natural rows
+  const int nkb32 = (nm + 31) / 32;     // blocks of the FP32 table copy
+  const int jt = t.rb;
   const int c0 = t.cb * BN;
   const long long Cp = L.Cp;
-  const unsigned short* tab = static_cast<const unsigned short*>(g.table) + g.tab_off[L.m_base + m] +
-                              (long long)jb * nkb * 4096;
   const float* spec = static_cast<const float*>(g.spec_in) + L.spec_off;
   const long long nc = (long long)(N + 1) * (N + 2) / 2;
   const long long sbase = spec_idx(N, m, m);
 
   const int tid = threadIdx.x;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
-  const int p = w & 1, ch = w >> 1;
+  const int p = w & 1, q = w >> 1;
   const int li = lane & 15, lg = lane >> 4;
-  const bool full_cols = ch == 0;  // HC column blocks, else NCB - HC
+  const bool active = jt * 128 + 32 * q < L.Jh;
+  const float* arun = static_cast<const float*>(g.table) + g.tab_off[L.m_base + m] +
+                      (long long)jt * nkb32 * S::CHUNK + w * (S::CHUNK / 8) + lane * 4;
 
-  f32x4 acc[4][HC];
+  f32x4 acc[2][NCB];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int jb = 0; jb < 2; ++jb)
 #pragma unroll
-    for (int c = 0; c < HC; ++c) acc[a][c] = f32x4{0, 0, 0, 0};
+    for (int c = 0; c < NCB; ++c) acc[jb][c] = f32x4{0, 0, 0, 0};
 
-  u32x4 ra[NA];
-  float rs[NB][4];
-  auto gload = [&](int kb) {
-    const unsigned short* blk = tab + (long long)kb * 4096;
+  // The tile's spectra as a buffer starting at its first field and wave
+  // number: reads past the end of the level's spectra return zero (fields
+  // beyond F), rows beyond n = N are masked; offsets stay below 4 GiB.
+  const long long sfirst = ((long long)(c0 >> 1) * nc + sbase) * 2;
+  const long long sbytes = ((long long)L.F * nc * 2 - sfirst) * 4LL;
+  const __amdgpu_buffer_rsrc_t srs = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<float*>(spec + sfirst), (short)0, (int)(unsigned)(sbytes > 0xFFFFFFFFLL ? 0xFFFFFFFFLL : sbytes),
+      0x00020000);
+
+  // operands two blocks ahead in two register sets (loop unrolled by two):
+  // an[s][jb] = table block 2 kb + s, latitude block jb; task u = (fl, gg, s)
+  // with s fastest holds natural rows 32 s + 8 gg .. + 7 (re, im) of field fl
+  f4 an[2][2][2], ac[2][2];
+  f4 rq[2][S::TR][4];
+  auto gload = [&](int kb, f4 (&av)[2][2], f4 (&bq)[S::TR][4]) {
 #pragma unroll
-    for (int i = 0; i < NA; ++i) {
-      const int q = tid + i * 256;
-      const int pc = q / 512, rem = q % 512;
-      ra[i] = *reinterpret_cast<const u32x4*>(blk + pc * g.table_plane + rem * 8);
+    for (int s = 0; s < 2; ++s) {
+      const int k32 = 2 * kb + s < nkb32 ? 2 * kb + s : nkb32 - 1;  // clamped: those rows are masked
+#pragma unroll
+      for (int jb = 0; jb < 2; ++jb)
+        av[s][jb] = *reinterpret_cast<const f4*>(arun + (long long)k32 * S::CHUNK + jb * 256);
     }
-    const int rb0 = kb * 64;
 #pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      const int q = tid + i * 256;
-      const int fl = q / KH, rp = q % KH;
-      const int f = (c0 >> 1) + fl;
-      const int r = rb0 + 2 * rp;
-      rs[i][0] = rs[i][1] = rs[i][2] = rs[i][3] = 0.f;
-      if (fl < BN / 2 && f < L.F) {
-        const float* sp = spec + ((long long)f * nc + sbase + r) * 2;
-        if (r < nm) {
-          rs[i][0] = sp[0];
-          rs[i][1] = sp[1];
-        }
-        if (r + 1 < nm) {
-          rs[i][2] = sp[2];
-          rs[i][3] = sp[3];
-        }
+    for (int i = 0; i < S::TR; ++i) {
+      const int u = tid + i * 512;  // tasks past the end read zeros, beyond the buffer
+      const int s = u & 1, gg = (u >> 1) & 3, fl = u >> 3;
+      const int r = kb * 64 + 32 * s + 8 * gg;
+      const unsigned off = ((unsigned)fl * (unsigned)nc + (unsigned)r) * 8u;
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        bq[i][v] = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(srs, (int)(off + 16u * v), 0, 0));
+    }
+  };
+  auto lstore = [&](int stage, const f4 (&bq)[S::TR][4], int kb) {
+    __bf16* dst = Bs + stage * S::STAGE;
+#pragma unroll
+    for (int i = 0; i < S::TR; ++i) {
+      const int u = tid + i * 512;
+      if (S::TR * 512 == S::TASKS || u < S::TASKS) {
+        const int s = u & 1, gg = (u >> 1) & 3, fl = u >> 3;
+        const int r = kb * 64 + 32 * s + 8 * gg;
+        float x[16];  // natural rows r + k (k < 8), re and im
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) x[4 * v + e] = r + (4 * v + e) / 2 < nm ? bq[i][v][e] : 0.f;
+#pragma unroll
+        for (int par = 0; par < 2; ++par)
+#pragma unroll
+          for (int ri = 0; ri < 2; ++ri) {
+            // rows r + 2 u' + par, u' < 4: r' = 16 s + 4 gg + u'
+            const f4 y = {x[2 * par + ri], x[4 + 2 * par + ri], x[8 + 2 * par + ri], x[12 + 2 * par + ri]};
+            bf16x4 pc[3];
+            split3(y, pc);
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+              *reinterpret_cast<bf16x4*>(dst + k * S::PLANE + (par * BN + 2 * fl + ri) * P + 8 * gg + 4 * s) = pc[k];
+          }
       }
     }
   };
-  auto lstore = [&]() {
+  auto compute = [&](int stage) {
+    bf16x8 a[2][3];
 #pragma unroll
-    for (int i = 0; i < NA; ++i) {
-      const int q = tid + i * 256;
-      const int pc = q / 512, rem = q % 512;
-      const int e0 = rem * 8;
-      const int pj = e0 / KH, kv = e0 % KH;   // (parity*64 + j), r'
-      *reinterpret_cast<u32x4*>(At + (pc * 128 + pj) * AS + kv) = ra[i];
+    for (int jb = 0; jb < 2; ++jb) {
+      const f32x8 x = {ac[0][jb][0], ac[0][jb][1], ac[0][jb][2], ac[0][jb][3],
+                       ac[1][jb][0], ac[1][jb][1], ac[1][jb][2], ac[1][jb][3]};
+      split3(x, a[jb]);
     }
+    const __bf16* Bp = Bs + stage * S::STAGE + (p * BN + li) * P + 8 * lg;
 #pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      const int q = tid + i * 256;
-      const int fl = q / KH, rp = q % KH;
-      if (fl < BN / 2) {
-        float* d0 = Bs + rp * BS + 2 * fl;
-        float* d1 = Bs + (KH + rp) * BS + 2 * fl;
-        d0[0] = rs[i][0];
-        d0[1] = rs[i][1];
-        d1[0] = rs[i][2];
-        d1[1] = rs[i][3];
-      }
+    for (int c = 0; c < NCB; ++c) {
+      bf16x8 b[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) b[k] = *reinterpret_cast<const bf16x8*>(Bp + k * S::PLANE + c * 16 * P);
+#pragma unroll
+      for (int jb = 0; jb < 2; ++jb) acc[jb][c] = mfma6(a[jb], b, acc[jb][c]);
     }
   };
-
-  auto kloop = [&](auto ncc) {
-    constexpr int NC = decltype(ncc)::value;
-    gload(0);
-    lstore();
-    __syncthreads();
-    for (int kb = 0; kb < nkb; ++kb) {
-      if (kb + 1 < nkb) gload(kb + 1);
+  // one K block; H = kb & 1 selects the register set of block kb (and of
+  // kb + 2), 1 - H that of block kb + 1
+  auto step = [&](auto hc, int kb) {
+    constexpr int H = decltype(hc)::value;
+    gload(kb + 2 < nkb ? kb + 2 : nkb - 1, an[H], rq[H]);
+    if (active) compute(H);
+    // after the last block this fills the idle stage with a clamped block
+    // (nothing reads it)
+    lstore(1 - H, rq[1 - H], kb + 1 < nkb ? kb + 1 : nkb - 1);
 #pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        const int cb = ch * HC + c;
-        float bv[8];
+    for (int s = 0; s < 2; ++s)
 #pragma unroll
-        for (int e = 0; e < 8; ++e) bv[e] = Bs[(p * KH + 8 * lg + e) * BS + cb * 16 + li];
-        bf16x8 b0, b1, b2;
-        split3x8(bv, b0, b1, b2);
-#pragma unroll
-        for (int jr = 0; jr < 4; ++jr) {
-          bf16x8 av[3];
-#pragma unroll
-          for (int pc = 0; pc < 3; ++pc)
-            av[pc] = __builtin_bit_cast(
-                bf16x8, *reinterpret_cast<const u32x4*>(At + (pc * 128 + p * 64 + 16 * jr + li) * AS + 8 * lg));
-          acc[jr][c] = mfma6(av, b0, b1, b2, acc[jr][c]);
-        }
-      }
-      __syncthreads();
-      if (kb + 1 < nkb) {
-        lstore();
-        __syncthreads();
-      }
-    }
+      for (int jb = 0; jb < 2; ++jb) ac[s][jb] = an[1 - H][s][jb];
+    lds_barrier();
   };
-  if (full_cols || 2 * HC == NCB)
-    kloop(std::integral_constant<int, HC>{});
-  else
-    kloop(std::integral_constant<int, NCB - HC>{});
 
+  gload(0, an[0], rq[0]);
+  gload(nkb > 1 ? 1 : 0, an[1], rq[1]);
+  lstore(0, rq[0], 0);
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int jb = 0; jb < 2; ++jb) ac[s][jb] = an[0][s][jb];
+  __syncthreads();
+  for (int kb = 0; kb < nkb; kb += 2) {
+    step(std::integral_constant<int, 0>{}, kb);
+    if (kb + 1 < nkb) step(std::integral_constant<int, 1>{}, kb + 1);
+  }
+
+  if (!active) return;
   const long long plane = (long long)L.Kp * Cp;
   float* ws = static_cast<float*>(g.ws) + L.ws_off + (2LL * m + p) * plane;
 #pragma unroll
-  for (int jr = 0; jr < 4; ++jr)
+  for (int jb = 0; jb < 2; ++jb)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int j = jb * 64 + 16 * jr + 4 * lg + i;
+      const int j = jt * 128 + 32 * q + 16 * jb + 4 * lg + i;
       if (j < L.Jh) {
 #pragma unroll
-        for (int c = 0; c < HC; ++c) {
-          const int cb = ch * HC + c;
-          if (cb < NCB) ws[(long long)j * Cp + c0 + cb * 16 + li] = acc[jr][c][i];
-        }
+        for (int c = 0; c < NCB; ++c) ws[(long long)j * Cp + c0 + c * 16 + li] = acc[jb][c][i];
       }
     }
 }
 
 // ---------------------------------------------------------------------------
-// launchers
+// launcher
 // ---------------------------------------------------------------------------
-static size_t lds_analysis_bf16(int ncb) {
-  const int BN = 16 * ncb;
-  size_t stage = (size_t)3 * 64 * 40 * 2 + (size_t)2 * 32 * (BN + 2) * 4;
-  size_t cst = (size_t)64 * (BN + 1) * 4;
-  return stage > cst ? stage : cst;
-}
-
-static size_t lds_synthesis_bf16(int ncb) {
-  const int BN = 16 * ncb;
-  return (size_t)3 * 2 * 64 * 40 * 2 + (size_t)2 * 32 * (BN + 2) * 4;
+template <int NCB>
+static hipError_t launch_bf16_ncb(bool analysis, const GemmArgs& g, hipStream_t st) {
+  const dim3 grid(g.ntiles);
+  if (analysis) {
+    const size_t lds = X6Analysis<NCB>::lds_bytes();
+    lds_optin<k_legendre_analysis_bf16<NCB>>(lds);
+    hipLaunchKernelGGL((k_legendre_analysis_bf16<NCB>), grid, dim3(256), lds, st, g);
+  } else {
+    const size_t lds = X6Synthesis<NCB>::lds_bytes();
+    lds_optin<k_legendre_synthesis_bf16<NCB>>(lds);
+    hipLaunchKernelGGL((k_legendre_synthesis_bf16<NCB>), grid, dim3(512), lds, st, g);
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_legendre_bf16(bool analysis, const GemmArgs& g, int ncb, hipStream_t st) {
-  const dim3 grid(g.ntiles), block(256);
-#define SHT_BLAUNCH(NCB_)                                                        \
-  case NCB_:                                                                    \
-    if (analysis) {                                                             \
-      lds_optin<k_legendre_analysis_bf16<NCB_>>(lds_analysis_bf16(NCB_));      \
-      hipLaunchKernelGGL((k_legendre_analysis_bf16<NCB_>), grid, block,        \
-                         lds_analysis_bf16(NCB_), st, g);                       \
-    } else {                                                                    \
-      lds_optin<k_legendre_synthesis_bf16<NCB_>>(lds_synthesis_bf16(NCB_));    \
-      hipLaunchKernelGGL((k_legendre_synthesis_bf16<NCB_>), grid, block,       \
-                         lds_synthesis_bf16(NCB_), st, g);                      \
-    }                                                                           \
-    break;
   switch (ncb) {
-    SHT_BLAUNCH(1)
-    SHT_BLAUNCH(2)
-    SHT_BLAUNCH(4)
-    SHT_BLAUNCH(5)
-    SHT_BLAUNCH(8)
-    SHT_BLAUNCH(10)
-    default:
-      return hipErrorInvalidValue;
+    case 1: return launch_bf16_ncb<1>(analysis, g, st);
+    case 2: return launch_bf16_ncb<2>(analysis, g, st);
+    case 4: return launch_bf16_ncb<4>(analysis, g, st);
+    case 5: return launch_bf16_ncb<5>(analysis, g, st);
+    case 8: return launch_bf16_ncb<8>(analysis, g, st);
+    case 10: return launch_bf16_ncb<10>(analysis, g, st);
+    default: return hipErrorInvalidValue;
   }
-#undef SHT_BLAUNCH
-  return hipGetLastError();
 }
 
 }  // namespace sht
