@@ -223,7 +223,9 @@ std::vector<Tile> build_tiles(const sht_plan_s* P, bool analysis, int ncb, int s
       const int nm = L.N - m + 1;
       for (int cb = 0; cb < ncol; ++cb) {
         if (analysis) {
-          for (int rb = 0; rb < (nm + 127) / 128; ++rb) {
+          // 128-row tiles; 256 in the split form
+          const int rows = P->form == SHT_FORM_BF16X6 ? 256 : 128;
+          for (int rb = 0; rb < (nm + rows - 1) / rows; ++rb) {
             t.push_back(Tile{l, m, rb, cb});
             c.push_back((double)L.Kp * BN);
           }
@@ -435,17 +437,20 @@ int build_plan(int nlev, const int* Nv, const int* Jv, const int* Iv, const int*
   }
 
   // ---- tile schedules (default; the autotuner may replace them) ----
-  P->ncb_fwd = P->ncb_inv = P->ncb;
-  if (P->ncb > max_synthesis_ncb(o.form)) {
-    // the synthesis kernel keeps its whole output tile in registers: take the
-    // widest blocking it supports that divides every level's row length
+  // the kernels keep their whole output tile in registers: where the
+  // plan's blocking is wider than a kernel takes, use the widest blocking it
+  // supports that divides every level's row length
+  for (int dir = 0; dir < 2; ++dir) {
+    int& ncb = dir == 0 ? P->ncb_fwd : P->ncb_inv;
+    ncb = P->ncb;
+    if (ncb <= max_ncb(o.form, dir == 0)) continue;
     for (int c : {8, 5, 4, 2, 1}) {
-      if (c > max_synthesis_ncb(o.form)) continue;
+      if (c > max_ncb(o.form, dir == 0)) continue;
       bool ok = true;
       for (int l = 0; l < nlev; ++l)
         if (P->lev[l].Cp % (16 * c)) ok = false;
       if (ok) {
-        P->ncb_inv = c;
+        ncb = c;
         break;
       }
     }
@@ -741,7 +746,7 @@ int autotune(sht_plan_s* P) {
       int bc = analysis ? P->ncb_fwd : P->ncb_inv, bs = 0;
       for (int c : cands)
         for (int sched = 0; sched < 2 && !rc; ++sched) {
-          if (!analysis && c > max_synthesis_ncb(P->form)) continue;
+          if (c > max_ncb(P->form, analysis)) continue;
           std::vector<Tile> t = build_tiles(P, analysis, c, sched);
           Tile* dt = nullptr;
           if ((rc = hip_check(hipMalloc(reinterpret_cast<void**>(&dt), t.size() * sizeof(Tile)), "tune alloc"))) break;

@@ -86,8 +86,8 @@ struct GemmArgs {
 int zonal_fields_per_block(int form);
 int launch_zonal(int form, bool analysis, const FftArgs& a, int maxN, void* stream);
 int launch_legendre(int form, bool analysis, const GemmArgs& g, int ncb, void* stream);
-// Widest column blocking (16-column units) the synthesis kernel of a form takes.
-int max_synthesis_ncb(int form);
+// Widest column blocking (16-column units) a Legendre kernel of a form takes.
+int max_ncb(int form, bool analysis);
 
 }  // namespace sht
 

@@ -518,7 +518,11 @@ static hipError_t launch_legendre_t(bool analysis, const GemmArgs& g, int ncb,
   }
 }
 
-int max_synthesis_ncb(int form) { return form == SHT_FORM_BF16X6 ? 10 : kMaxSynthesisNcb; }
+int max_ncb(int form, bool analysis) {
+  if (form == SHT_FORM_BF16X6) return 8;  // wider split-form tiles do not fit the register file
+  if (form == SHT_FORM_FP64) return 8;
+  return analysis ? 10 : kMaxSynthesisNcb;
+}
 
 int launch_legendre(int form, bool analysis, const GemmArgs& g, int ncb,
                     void* stream) {

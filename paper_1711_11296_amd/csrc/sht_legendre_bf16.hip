@@ -40,19 +40,50 @@ namespace sht {
 // ---------------------------------------------------------------------------
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
-typedef float f32x8 __attribute__((ext_vector_type(8)));
 
 __device__ __forceinline__ f32x4 mfma_bf16(bf16x8 a, bf16x8 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
-// three bfloat16 pieces of n floats (n = 4 or 8), rounded to nearest
-template <typename F, typename B>
-__device__ __forceinline__ void split3(F x, B (&pc)[3]) {
-  pc[0] = __builtin_convertvector(x, B);
-  const F r = x - __builtin_convertvector(pc[0], F);
-  pc[1] = __builtin_convertvector(r, B);
-  pc[2] = __builtin_convertvector(r - __builtin_convertvector(pc[1], F), B);
+// Three bfloat16 pieces of a pair of floats, rounded to nearest, packed two
+// per 32-bit word (low half = first value).  The remainders x - x0 are
+// formed by the bfloat16 dot-product instruction as x + (-1) x0 + (-0) x0':
+// its products are exact and the sum is representable, so it is exact.
+// (The weight pairs are written with -0 rather than +0 so that they stay
+// 32-bit literals: (-1, +0) would be encoded as the inline constant -1.0,
+// which the instruction does not read as the bfloat16 pair (-1, 0).)
+__device__ __forceinline__ unsigned cvt_pk_bf16(float a, float b) {
+  typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+  typedef float f32x2 __attribute__((ext_vector_type(2)));
+  return __builtin_bit_cast(unsigned, __builtin_convertvector(f32x2{a, b}, bf16x2));
+}
+__device__ __forceinline__ void split_pair(float x0, float x1, unsigned (&pc)[3]) {
+  typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+  const bf16x2 neg_lo = __builtin_bit_cast(bf16x2, 0x8000BF80u);  // (-1, -0)
+  const bf16x2 neg_hi = __builtin_bit_cast(bf16x2, 0xBF808000u);  // (-0, -1)
+  pc[0] = cvt_pk_bf16(x0, x1);
+  const bf16x2 h = __builtin_bit_cast(bf16x2, pc[0]);
+  const float r0 = __builtin_amdgcn_fdot2_f32_bf16(h, neg_lo, x0, false);
+  const float r1 = __builtin_amdgcn_fdot2_f32_bf16(h, neg_hi, x1, false);
+  pc[1] = cvt_pk_bf16(r0, r1);
+  const bf16x2 mm = __builtin_bit_cast(bf16x2, pc[1]);
+  pc[2] = cvt_pk_bf16(__builtin_amdgcn_fdot2_f32_bf16(mm, neg_lo, r0, false),
+                      __builtin_amdgcn_fdot2_f32_bf16(mm, neg_hi, r1, false));
+}
+// pieces of n = 4 or 8 floats as bfloat16 vectors (B = bf16x4 or bf16x8)
+template <int n, typename B>
+__device__ __forceinline__ void split3(const float (&x)[n], B (&pc)[3]) {
+  typedef unsigned U __attribute__((ext_vector_type(n / 2)));
+  U w[3];
+#pragma unroll
+  for (int i = 0; i < n / 2; ++i) {
+    unsigned t[3];
+    split_pair(x[2 * i], x[2 * i + 1], t);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) w[k][i] = t[k];
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) pc[k] = __builtin_bit_cast(B, w[k]);
 }
 
 // acc += a * b from the pieces of both operands
@@ -72,51 +103,68 @@ __device__ __forceinline__ f32x4 mfma6(const bf16x8 (&a)[3], const bf16x8 (&b)[3
 // cycle) fall on 8 distinct groups of 4 banks.
 constexpr int kX6Pitch = 40;
 
+// Both kernels step through K blocks with two LDS stages and one barrier
+// per block: the matrix cores multiply block kb (table pieces in registers,
+// right-hand pieces in LDS stage kb & 1); then the wave splits block kb + 1,
+// fetched one block earlier (table values into its registers, right-hand
+// values into the other LDS stage); block kb + 2 is in flight meanwhile.
+// The split work is a list of units: unit u < 8 splits one pair of table
+// values, the others one pair of right-hand values and, after the second
+// pair of a column, store its three 8-byte pieces.  Threads without a
+// right-hand task (when the block has fewer tasks than threads) store into
+// the padding slots 32..39 of a column, which no matrix step reads.  Waves
+// without rows (latitudes) in the tile run the same steps without the
+// products: the choice is made once, outside the loop, so that the loop
+// body has no branches (the accumulators then stay in their registers).
 // ---------------------------------------------------------------------------
 // analysis: C[n][c] = P[n][j] * B_par(n)[j][c]
-// tile = 128 rows r = n - m (both parities) x BN = 16*NCB columns, 4 waves.
-// Wave w: parity p = w & 1, row half q = w >> 1; it owns the 32 rows
-// r = 64 q + 32 h + 2 i + p (h < 2, two MFMA row blocks) and all NCB column
-// blocks; each B read feeds both row blocks.  The contraction runs over
-// latitudes in blocks of 32; lane (i, g) holds, in slot 8 g + e (e < 8),
-// latitude 4 e + g of the block: exactly the values its run of the FP32
-// analysis table copy holds (that copy is blocked for 16-row runs; row
-// block h of wave (q, p) is run 4 q + 2 h + p).
-// The workspace block (both parities, 32 x BN) is fetched into registers one
-// block ahead, split and stored into LDS; one LDS stage per workgroup and
-// two workgroups per CU, one in its split/store phase while the other runs
-// its matrix steps.
+// tile = 256 rows r = n - m (two 128-row blocks of the table copy, both
+// parities) x BN = 16*NCB columns, 8 waves.  Wave w: row block th = w >> 2,
+// quarter q = (w >> 1) & 1, parity p = w & 1; it owns the 32 rows
+// r = 128 th + 64 q + 32 h + 2 i + p (h < 2, two MFMA row blocks) and all
+// NCB column blocks, so that each B read feeds both row blocks.  The
+// contraction runs over latitudes in blocks of 32; lane (i, g) holds, in
+// slot 8 g + e (e < 8), latitude 4 e + g of the block: exactly the values
+// its run of the FP32 analysis table copy holds (that copy is blocked for
+// 16-row runs; row block h of wave (q, p) is run 4 q + 2 h + p).  A second
+// 128-row block past the end of the rows is not read: its waves fetch the
+// first block's runs again (no extra memory traffic) and skip the
+// products.  Right-hand task u (eh fastest, then gg, cq, par) holds
+// latitudes 4 e + gg (e = 4 eh .. 4 eh + 3) of columns 4 cq .. 4 cq + 3 of
+// parity par; its pieces go to slots 8 gg + 4 eh .. + 3.
 // ---------------------------------------------------------------------------
 template <int NCB>
 struct X6Analysis {
+  static constexpr int NT = 512;                     // threads (8 waves)
   static constexpr int BN = 16 * NCB;
   static constexpr int KB = 32;                      // latitudes per block
   static constexpr int PLANE = 2 * BN * kX6Pitch;    // bfloat16 per piece
-  static constexpr int TASKS = 2 * BN;               // (parity, column quad, g)
-  static constexpr int TR = (TASKS + 255) / 256;     // task rounds per thread
+  static constexpr int STAGE = 3 * PLANE;
+  static constexpr int TASKS = 4 * BN;               // (parity, column quad, g, half)
+  static constexpr int TR = (TASKS + 511) / 512;     // task rounds per thread
   static constexpr int CS = BN + 1;                  // output staging pitch
   static constexpr size_t lds_bytes() {
-    const size_t main = (size_t)3 * PLANE * 2;
+    const size_t main = (size_t)2 * STAGE * 2;
     const size_t cst = (size_t)64 * CS * 4;
     return main > cst ? main : cst;
   }
 };
 
 template <int NCB>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_legendre_analysis_bf16(const GemmArgs g) {
+__global__ __launch_bounds__(X6Analysis<NCB>::NT) __attribute__((amdgpu_waves_per_eu(2))) void k_legendre_analysis_bf16(const GemmArgs g) {
   using S = X6Analysis<NCB>;
-  constexpr int BN = S::BN, KB = S::KB, P = kX6Pitch;
+  constexpr int BN = S::BN, KB = S::KB, P = kX6Pitch, TR = S::TR;
   typedef float f4 __attribute__((ext_vector_type(4)));
 
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  __bf16* Bs = reinterpret_cast<__bf16*>(smem_raw);
+  __bf16* Bs = reinterpret_cast<__bf16*>(smem_raw);  // [2 stage][3 piece][2 parity][BN][P]
 
   const Tile t = g.tiles[blockIdx.x];
   if (t.level < 0) return;
   const LevelDesc& L = g.lev[t.level];
   const int N = L.N, m = t.m;
   const int nm = N - m + 1;
-  const int r0 = t.rb * 128;
+  const int r0 = t.rb * 256;
   const int c0 = t.cb * BN;
   const int Kp = L.Kp;
   const long long Cp = L.Cp;
@@ -125,12 +173,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 
   const int tid = threadIdx.x;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
-  const int p = w & 1, q = w >> 1;
+  const int th = w >> 2, q = (w >> 1) & 1, p = w & 1;
   const int li = lane & 15, lg = lane >> 4;
-  const bool active = r0 + 64 * q + p < nm;
+  const bool active = r0 + 128 * th + 64 * q + p < nm;
+  const int nrb = (nm + 127) / 128;
+  const int rbt = 2 * t.rb + th < nrb ? 2 * t.rb + th : nrb - 1;
   // run 4 q + p of the table block; row block h adds two runs
   const float* arow = static_cast<const float*>(g.table) + g.tab_off[L.m_base + m] +
-                      (long long)t.rb * Kp * 128 + (4 * q + p) * 16 * KB + lane * 4;
+                      (long long)rbt * Kp * 128 + (4 * q + p) * 16 * KB + lane * 4;
+
+  // right-hand tasks: source offset (latitude 0 of the block) and LDS offset
+  const float* bsrc[TR];
+  int boff[TR];
+#pragma unroll
+  for (int i = 0; i < TR; ++i) {
+    const int u = tid + i * 512;
+    const bool valid = TR * 512 == S::TASKS || u < S::TASKS;
+    const int uc = valid ? u : S::TASKS - 1;  // loads clamped to a real task
+    const int eh = uc & 1, gg = (uc >> 1) & 3, cq = (uc >> 3) % (BN / 4), par = (uc >> 3) / (BN / 4);
+    bsrc[i] = wsm + par * plane + (long long)(16 * eh + gg) * Cp + 4 * cq;
+    boff[i] = valid ? (par * BN + 4 * cq) * P + 8 * gg + 4 * eh : 32;
+  }
 
   f32x4 acc[2][NCB];
 #pragma unroll
@@ -138,93 +201,96 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
     for (int c = 0; c < NCB; ++c) acc[h][c] = f32x4{0, 0, 0, 0};
 
-  // table: two K blocks ahead in two register sets (loop unrolled by two);
-  // [h][v]: vector v holds slots 4 v .. 4 v + 3
-  f4 an[2][2][2];
-  // workspace: one K block ahead; task u = ((par * BN/4) + cq) * 4 + gg holds
-  // latitudes 4 e + gg (e < 8) of columns 4 cq .. 4 cq + 3 of parity par
-  f4 bq[S::TR][8];
-  auto gload_a = [&](int kb, f4 (&av)[2][2]) {
+  f4 araw[2][2][2];    // [set][h][v]: vector v holds slots 4 v .. 4 v + 3
+  f4 braw[2][TR][4];   // [set][round][e]
+  bf16x8 acur[2][3];   // pieces of the table block being multiplied
+
+  auto gload = [&](int kb, int set) __attribute__((always_inline)) {
 #pragma unroll
     for (int h = 0; h < 2; ++h)
 #pragma unroll
       for (int v = 0; v < 2; ++v)
-        av[h][v] = *reinterpret_cast<const f4*>(arow + (long long)kb * 128 * KB + h * 32 * KB + v * 256);
+        araw[set][h][v] = *reinterpret_cast<const f4*>(arow + (long long)kb * 128 * KB + h * 32 * KB + v * 256);
+#pragma unroll
+    for (int i = 0; i < TR; ++i)
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        braw[set][i][e] = *reinterpret_cast<const f4*>(bsrc[i] + (long long)(kb * KB + 4 * e) * Cp);
   };
-  auto gload_b = [&](int kb) {
+  auto split_a = [&](int set) __attribute__((always_inline)) {
 #pragma unroll
-    for (int i = 0; i < S::TR; ++i) {
-      int u = tid + i * 256;
-      if (S::TR * 256 != S::TASKS && u >= S::TASKS) u = S::TASKS - 1;  // clamped, not stored
-      const int gg = u & 3, cq = (u >> 2) % (BN / 4), par = (u >> 2) / (BN / 4);
-      const float* src = wsm + par * plane + (long long)(kb * KB + gg) * Cp + 4 * cq;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) bq[i][e] = *reinterpret_cast<const f4*>(src + 4LL * e * Cp);
+    for (int h = 0; h < 2; ++h) {
+      const float x[8] = {araw[set][h][0][0], araw[set][h][0][1], araw[set][h][0][2], araw[set][h][0][3],
+                          araw[set][h][1][0], araw[set][h][1][1], araw[set][h][1][2], araw[set][h][1][3]};
+      split3(x, acur[h]);
     }
   };
-  auto lstore = [&]() {
+  auto split_b = [&](int set, int stage) __attribute__((always_inline)) {
 #pragma unroll
-    for (int i = 0; i < S::TR; ++i) {
-      const int u = tid + i * 256;
-      if (S::TR * 256 == S::TASKS || u < S::TASKS) {
-        const int gg = u & 3, cq = (u >> 2) % (BN / 4), par = (u >> 2) / (BN / 4);
+    for (int i = 0; i < TR; ++i)
 #pragma unroll
-        for (int cc = 0; cc < 4; ++cc) {
-          const f32x8 x = {bq[i][0][cc], bq[i][1][cc], bq[i][2][cc], bq[i][3][cc],
-                           bq[i][4][cc], bq[i][5][cc], bq[i][6][cc], bq[i][7][cc]};
-          bf16x8 pc[3];
-          split3(x, pc);
+      for (int cc = 0; cc < 4; ++cc) {
+        const float x[4] = {braw[set][i][0][cc], braw[set][i][1][cc], braw[set][i][2][cc], braw[set][i][3][cc]};
+        bf16x4 pc[3];
+        split3(x, pc);
 #pragma unroll
-          for (int k = 0; k < 3; ++k)
-            *reinterpret_cast<bf16x8*>(Bs + k * S::PLANE + (par * BN + 4 * cq + cc) * P + 8 * gg) = pc[k];
-        }
+        for (int k = 0; k < 3; ++k)
+          *reinterpret_cast<bf16x4*>(Bs + stage * S::STAGE + k * S::PLANE + boff[i] + cc * P) = pc[k];
+      }
+  };
+  auto compute = [&](int stage) __attribute__((always_inline)) {
+    const __bf16* Bp = Bs + stage * S::STAGE + (p * BN + li) * P + 8 * lg;
+#pragma unroll
+    for (int c = 0; c < NCB; ++c) {
+      bf16x8 bb[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) bb[k] = *reinterpret_cast<const bf16x8*>(Bp + k * S::PLANE + c * 16 * P);
+      // six piece products, smallest first, the two row blocks alternating
+#pragma unroll
+      for (int pr = 0; pr < 6; ++pr) {
+        constexpr int ia[6] = {2, 1, 0, 1, 0, 0}, ib[6] = {0, 1, 2, 0, 1, 0};
+#pragma unroll
+        for (int h = 0; h < 2; ++h) acc[h][c] = mfma_bf16(acur[h][ia[pr]], bb[ib[pr]], acc[h][c]);
       }
     }
   };
-  auto compute = [&](const f4 (&av)[2][2]) {
-    bf16x8 a[2][3];
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const f32x8 x = {av[h][0][0], av[h][0][1], av[h][0][2], av[h][0][3],
-                       av[h][1][0], av[h][1][1], av[h][1][2], av[h][1][3]};
-      split3(x, a[h]);
-    }
-    const __bf16* Bp = Bs + (p * BN + li) * P + 8 * lg;
-#pragma unroll
-    for (int c = 0; c < NCB; ++c) {
-      bf16x8 b[3];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) b[k] = *reinterpret_cast<const bf16x8*>(Bp + k * S::PLANE + c * 16 * P);
-#pragma unroll
-      for (int h = 0; h < 2; ++h) acc[h][c] = mfma6(a[h], b, acc[h][c]);
-    }
-  };
   const int nkb = Kp / KB;
-  // one K block; H = kb & 1 selects the table registers of block kb (and of
-  // kb + 2).  Loads past the end are clamped to the last block (never used),
-  // which keeps memory operations out of branches.
-  auto step = [&](auto hc, int kb) {
+  // one K block: raw set 1 - H holds block kb + 1, block kb + 2 goes to set
+  // H (clamped past the end: never used, keeps memory operations out of
+  // branches)
+  auto step = [&](auto act, auto hc, int kb) __attribute__((always_inline)) {
+    constexpr bool ACT = decltype(act)::value;
     constexpr int H = decltype(hc)::value;
-    lds_barrier();  // every wave is done reading the previous block
-    lstore();
-    gload_b(kb + 1 < nkb ? kb + 1 : nkb - 1);
+    gload(kb + 2 < nkb ? kb + 2 : nkb - 1, H);
+    // keep the loads ahead of the block's work (the scheduler would sink
+    // them towards their distant uses)
+    __builtin_amdgcn_sched_barrier(0);
+    if constexpr (ACT) {
+      compute(H);
+      split_a(1 - H);
+    }
+    split_b(1 - H, 1 - H);
     lds_barrier();
-    f4 ac[2][2];
-#pragma unroll
-    for (int h = 0; h < 2; ++h)
-#pragma unroll
-      for (int v = 0; v < 2; ++v) ac[h][v] = an[H][h][v];
-    gload_a(kb + 2 < nkb ? kb + 2 : nkb - 1, an[H]);
-    if (active) compute(ac);
+  };
+  // pairs of blocks with a branch-free body, then an odd last block
+  auto run = [&](auto act) __attribute__((always_inline)) {
+    int kb = 0;
+    for (; kb + 1 < nkb; kb += 2) {
+      step(act, std::integral_constant<int, 0>{}, kb);
+      step(act, std::integral_constant<int, 1>{}, kb + 1);
+    }
+    if (kb < nkb) step(act, std::integral_constant<int, 0>{}, kb);
   };
 
-  gload_a(0, an[0]);
-  gload_b(0);
-  gload_a(nkb > 1 ? 1 : 0, an[1]);
-  for (int kb = 0; kb < nkb; kb += 2) {
-    step(std::integral_constant<int, 0>{}, kb);
-    if (kb + 1 < nkb) step(std::integral_constant<int, 1>{}, kb + 1);
-  }
+  gload(0, 0);
+  gload(nkb > 1 ? 1 : 0, 1);
+  split_a(0);
+  split_b(0, 0);
+  __syncthreads();
+  if (active)
+    run(std::true_type{});
+  else
+    run(std::false_type{});
 
   // stage 64 rows at a time in LDS, then write spec rows contiguously
   float* Cs = reinterpret_cast<float*>(smem_raw);  // [64][CS]
@@ -232,9 +298,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   const long long nc = (long long)(N + 1) * (N + 2) / 2;
   const long long base = spec_idx(N, m, m);
 #pragma unroll
-  for (int hh = 0; hh < 2; ++hh) {
+  for (int hh = 0; hh < 4; ++hh) {
+    if (r0 + 64 * hh >= nm) break;  // uniform across the workgroup
     __syncthreads();
-    if (q == hh) {
+    if ((w >> 1) == hh) {
 #pragma unroll
       for (int h = 0; h < 2; ++h)
 #pragma unroll
@@ -243,7 +310,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
           for (int i = 0; i < 4; ++i) Cs[(32 * h + 2 * (4 * lg + i) + p) * S::CS + c * 16 + li] = acc[h][c][i];
     }
     __syncthreads();
-    for (int qq = tid; qq < 64 * (BN / 2); qq += 256) {
+    for (int qq = tid; qq < 64 * (BN / 2); qq += 512) {
       const int fl = qq >> 6, rl = qq & 63;
       const int f = (c0 >> 1) + fl;
       const int r = r0 + 64 * hh + rl;
@@ -265,12 +332,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 // natural rows, two blocks of the FP32 synthesis table copy); lane (i, g)
 // holds in slot 8 g + 4 s + u (s < 2, u < 4) r' = 16 s + 4 g + u of the
 // block, which is what its run of table block 2 kb + s holds.
-// The spectra of a block (64 rows x BN/2 fields) are fetched into
-// registers two blocks ahead, split and stored into the other of two LDS
-// stages; one barrier per block.
+// Right-hand task u = (fl, gg, s) holds natural rows 32 s + 8 gg .. + 7
+// (re, im) of field fl of the block.  Lane order s, gg, fl bit 1, fl bit 0,
+// ...: the 16 lanes of one LDS write cycle cover fields fl and fl + 2,
+// whose columns are 80 words apart, so their 8-byte pieces fill all 32
+// banks once.
 // ---------------------------------------------------------------------------
 template <int NCB>
 struct X6Synthesis {
+  static constexpr int NT = 512;                    // threads (8 waves)
   static constexpr int BN = 16 * NCB;
   static constexpr int PLANE = 2 * BN * kX6Pitch;   // bfloat16 per piece
   static constexpr int STAGE = 3 * PLANE;
@@ -281,9 +351,9 @@ struct X6Synthesis {
 };
 
 template <int NCB>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k_legendre_synthesis_bf16(const GemmArgs g) {
+__global__ __launch_bounds__(X6Synthesis<NCB>::NT) __attribute__((amdgpu_waves_per_eu(2))) void k_legendre_synthesis_bf16(const GemmArgs g) {
   using S = X6Synthesis<NCB>;
-  constexpr int BN = S::BN, P = kX6Pitch;
+  constexpr int BN = S::BN, P = kX6Pitch, TR = S::TR;
   typedef float f4 __attribute__((ext_vector_type(4)));
 
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -311,12 +381,6 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
   const float* arun = static_cast<const float*>(g.table) + g.tab_off[L.m_base + m] +
                       (long long)jt * nkb32 * S::CHUNK + w * (S::CHUNK / 8) + lane * 4;
 
-  f32x4 acc[2][NCB];
-#pragma unroll
-  for (int jb = 0; jb < 2; ++jb)
-#pragma unroll
-    for (int c = 0; c < NCB; ++c) acc[jb][c] = f32x4{0, 0, 0, 0};
-
   // The tile's spectra as a buffer starting at its first field and wave
   // number: reads past the end of the level's spectra return zero (fields
   // beyond F), rows beyond n = N are masked; offsets stay below 4 GiB.
@@ -326,104 +390,125 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
       const_cast<float*>(spec + sfirst), (short)0, (int)(unsigned)(sbytes > 0xFFFFFFFFLL ? 0xFFFFFFFFLL : sbytes),
       0x00020000);
 
-  // operands two blocks ahead in two register sets (loop unrolled by two):
-  // an[s][jb] = table block 2 kb + s, latitude block jb; task u = (fl, gg, s)
-  // with s fastest holds natural rows 32 s + 8 gg .. + 7 (re, im) of field fl
-  f4 an[2][2][2], ac[2][2];
-  f4 rq[2][S::TR][4];
-  auto gload = [&](int kb, f4 (&av)[2][2], f4 (&bq)[S::TR][4]) {
+  // right-hand tasks: first natural row within a block, byte offset of
+  // field fl's row 0, LDS offset
+  int brow[TR], boff[TR];
+  unsigned bsrc[TR];
+#pragma unroll
+  for (int i = 0; i < TR; ++i) {
+    const int u = tid + i * 512;
+    const bool valid = TR * 512 == S::TASKS || u < S::TASKS;
+    const int s = u & 1, gg = (u >> 1) & 3;
+    const int fl = (((u >> 3) & 1) << 1) | ((u >> 4) & 1) | ((u >> 5) << 2);
+    brow[i] = 32 * s + 8 * gg;
+    bsrc[i] = (unsigned)fl * (unsigned)nc * 8u;  // tasks past the end read zeros or other fields; not stored
+    boff[i] = valid ? 2 * fl * P + 8 * gg + 4 * s : 32;
+  }
+
+  f32x4 acc[2][NCB];
+#pragma unroll
+  for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+    for (int c = 0; c < NCB; ++c) acc[jb][c] = f32x4{0, 0, 0, 0};
+
+  f4 araw[2][2][2];    // [set][s][jb]: table block 2 kb + s, latitude block jb
+  f4 braw[2][TR][4];   // [set][round][v]: rows r + 2 v, r + 2 v + 1 (re, im)
+  bf16x8 acur[2][3];
+
+  auto gload = [&](int kb, int set) __attribute__((always_inline)) {
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
       const int k32 = 2 * kb + s < nkb32 ? 2 * kb + s : nkb32 - 1;  // clamped: those rows are masked
 #pragma unroll
       for (int jb = 0; jb < 2; ++jb)
-        av[s][jb] = *reinterpret_cast<const f4*>(arun + (long long)k32 * S::CHUNK + jb * 256);
+        araw[set][s][jb] = *reinterpret_cast<const f4*>(arun + (long long)k32 * S::CHUNK + jb * 256);
     }
 #pragma unroll
-    for (int i = 0; i < S::TR; ++i) {
-      const int u = tid + i * 512;  // tasks past the end read zeros, beyond the buffer
-      const int s = u & 1, gg = (u >> 1) & 3, fl = u >> 3;
-      const int r = kb * 64 + 32 * s + 8 * gg;
-      const unsigned off = ((unsigned)fl * (unsigned)nc + (unsigned)r) * 8u;
+    for (int i = 0; i < TR; ++i) {
+      const unsigned off = bsrc[i] + (unsigned)(kb * 64 + brow[i]) * 8u;
 #pragma unroll
       for (int v = 0; v < 4; ++v)
-        bq[i][v] = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(srs, (int)(off + 16u * v), 0, 0));
+        braw[set][i][v] = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(srs, (int)(off + 16u * v), 0, 0));
     }
   };
-  auto lstore = [&](int stage, const f4 (&bq)[S::TR][4], int kb) {
-    __bf16* dst = Bs + stage * S::STAGE;
-#pragma unroll
-    for (int i = 0; i < S::TR; ++i) {
-      const int u = tid + i * 512;
-      if (S::TR * 512 == S::TASKS || u < S::TASKS) {
-        const int s = u & 1, gg = (u >> 1) & 3, fl = u >> 3;
-        const int r = kb * 64 + 32 * s + 8 * gg;
-        float x[16];  // natural rows r + k (k < 8), re and im
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-#pragma unroll
-          for (int e = 0; e < 4; ++e) x[4 * v + e] = r + (4 * v + e) / 2 < nm ? bq[i][v][e] : 0.f;
-#pragma unroll
-        for (int par = 0; par < 2; ++par)
-#pragma unroll
-          for (int ri = 0; ri < 2; ++ri) {
-            // rows r + 2 u' + par, u' < 4: r' = 16 s + 4 gg + u'
-            const f4 y = {x[2 * par + ri], x[4 + 2 * par + ri], x[8 + 2 * par + ri], x[12 + 2 * par + ri]};
-            bf16x4 pc[3];
-            split3(y, pc);
-#pragma unroll
-            for (int k = 0; k < 3; ++k)
-              *reinterpret_cast<bf16x4*>(dst + k * S::PLANE + (par * BN + 2 * fl + ri) * P + 8 * gg + 4 * s) = pc[k];
-          }
-      }
-    }
-  };
-  auto compute = [&](int stage) {
-    bf16x8 a[2][3];
+  auto split_a = [&](int set) __attribute__((always_inline)) {
 #pragma unroll
     for (int jb = 0; jb < 2; ++jb) {
-      const f32x8 x = {ac[0][jb][0], ac[0][jb][1], ac[0][jb][2], ac[0][jb][3],
-                       ac[1][jb][0], ac[1][jb][1], ac[1][jb][2], ac[1][jb][3]};
-      split3(x, a[jb]);
+      const float x[8] = {araw[set][0][jb][0], araw[set][0][jb][1], araw[set][0][jb][2], araw[set][0][jb][3],
+                          araw[set][1][jb][0], araw[set][1][jb][1], araw[set][1][jb][2], araw[set][1][jb][3]};
+      split3(x, acur[jb]);
     }
+  };
+  // block kb of raw set `set` into LDS stage `stage`
+  auto split_b = [&](int set, int stage, int kb) __attribute__((always_inline)) {
+#pragma unroll
+    for (int i = 0; i < TR; ++i) {
+      const int r = kb * 64 + brow[i];
+#pragma unroll
+      for (int par = 0; par < 2; ++par)
+#pragma unroll
+        for (int ri = 0; ri < 2; ++ri) {
+          // rows r + 2 u + par, u < 4: r' = 16 s + 4 gg + u
+          float y[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) y[u] = r + 2 * u + par < nm ? braw[set][i][u][2 * par + ri] : 0.f;
+          bf16x4 pc[3];
+          split3(y, pc);
+#pragma unroll
+          for (int k = 0; k < 3; ++k)
+            *reinterpret_cast<bf16x4*>(Bs + stage * S::STAGE + k * S::PLANE + boff[i] + (par * BN + ri) * P) = pc[k];
+        }
+    }
+  };
+  auto compute = [&](int stage) __attribute__((always_inline)) {
     const __bf16* Bp = Bs + stage * S::STAGE + (p * BN + li) * P + 8 * lg;
 #pragma unroll
     for (int c = 0; c < NCB; ++c) {
-      bf16x8 b[3];
+      bf16x8 bb[3];
 #pragma unroll
-      for (int k = 0; k < 3; ++k) b[k] = *reinterpret_cast<const bf16x8*>(Bp + k * S::PLANE + c * 16 * P);
+      for (int k = 0; k < 3; ++k) bb[k] = *reinterpret_cast<const bf16x8*>(Bp + k * S::PLANE + c * 16 * P);
 #pragma unroll
-      for (int jb = 0; jb < 2; ++jb) acc[jb][c] = mfma6(a[jb], b, acc[jb][c]);
+      for (int pr = 0; pr < 6; ++pr) {
+        constexpr int ia[6] = {2, 1, 0, 1, 0, 0}, ib[6] = {0, 1, 2, 0, 1, 0};
+#pragma unroll
+        for (int jb = 0; jb < 2; ++jb) acc[jb][c] = mfma_bf16(acur[jb][ia[pr]], bb[ib[pr]], acc[jb][c]);
+      }
     }
   };
-  // one K block; H = kb & 1 selects the register set of block kb (and of
-  // kb + 2), 1 - H that of block kb + 1
-  auto step = [&](auto hc, int kb) {
+  auto step = [&](auto act, auto hc, int kb) __attribute__((always_inline)) {
+    constexpr bool ACT = decltype(act)::value;
     constexpr int H = decltype(hc)::value;
-    gload(kb + 2 < nkb ? kb + 2 : nkb - 1, an[H], rq[H]);
-    if (active) compute(H);
-    // after the last block this fills the idle stage with a clamped block
-    // (nothing reads it)
-    lstore(1 - H, rq[1 - H], kb + 1 < nkb ? kb + 1 : nkb - 1);
-#pragma unroll
-    for (int s = 0; s < 2; ++s)
-#pragma unroll
-      for (int jb = 0; jb < 2; ++jb) ac[s][jb] = an[1 - H][s][jb];
+    const int kn = kb + 1 < nkb ? kb + 1 : nkb - 1;
+    gload(kb + 2 < nkb ? kb + 2 : nkb - 1, H);
+    // keep the loads ahead of the block's work (the scheduler would sink
+    // them towards their distant uses)
+    __builtin_amdgcn_sched_barrier(0);
+    if constexpr (ACT) {
+      compute(H);
+      split_a(1 - H);
+    }
+    split_b(1 - H, 1 - H, kn);
     lds_barrier();
   };
+  // pairs of blocks with a branch-free body, then an odd last block
+  auto run = [&](auto act) __attribute__((always_inline)) {
+    int kb = 0;
+    for (; kb + 1 < nkb; kb += 2) {
+      step(act, std::integral_constant<int, 0>{}, kb);
+      step(act, std::integral_constant<int, 1>{}, kb + 1);
+    }
+    if (kb < nkb) step(act, std::integral_constant<int, 0>{}, kb);
+  };
 
-  gload(0, an[0], rq[0]);
-  gload(nkb > 1 ? 1 : 0, an[1], rq[1]);
-  lstore(0, rq[0], 0);
-#pragma unroll
-  for (int s = 0; s < 2; ++s)
-#pragma unroll
-    for (int jb = 0; jb < 2; ++jb) ac[s][jb] = an[0][s][jb];
+  gload(0, 0);
+  gload(nkb > 1 ? 1 : 0, 1);
+  split_a(0);
+  split_b(0, 0, 0);
   __syncthreads();
-  for (int kb = 0; kb < nkb; kb += 2) {
-    step(std::integral_constant<int, 0>{}, kb);
-    if (kb + 1 < nkb) step(std::integral_constant<int, 1>{}, kb + 1);
-  }
+  if (active)
+    run(std::true_type{});
+  else
+    run(std::false_type{});
 
   if (!active) return;
   const long long plane = (long long)L.Kp * Cp;
@@ -449,11 +534,11 @@ static hipError_t launch_bf16_ncb(bool analysis, const GemmArgs& g, hipStream_t 
   if (analysis) {
     const size_t lds = X6Analysis<NCB>::lds_bytes();
     lds_optin<k_legendre_analysis_bf16<NCB>>(lds);
-    hipLaunchKernelGGL((k_legendre_analysis_bf16<NCB>), grid, dim3(256), lds, st, g);
+    hipLaunchKernelGGL((k_legendre_analysis_bf16<NCB>), grid, dim3(X6Analysis<NCB>::NT), lds, st, g);
   } else {
     const size_t lds = X6Synthesis<NCB>::lds_bytes();
     lds_optin<k_legendre_synthesis_bf16<NCB>>(lds);
-    hipLaunchKernelGGL((k_legendre_synthesis_bf16<NCB>), grid, dim3(512), lds, st, g);
+    hipLaunchKernelGGL((k_legendre_synthesis_bf16<NCB>), grid, dim3(X6Synthesis<NCB>::NT), lds, st, g);
   }
   return hipGetLastError();
 }
@@ -465,7 +550,6 @@ hipError_t launch_legendre_bf16(bool analysis, const GemmArgs& g, int ncb, hipSt
     case 4: return launch_bf16_ncb<4>(analysis, g, st);
     case 5: return launch_bf16_ncb<5>(analysis, g, st);
     case 8: return launch_bf16_ncb<8>(analysis, g, st);
-    case 10: return launch_bf16_ncb<10>(analysis, g, st);
     default: return hipErrorInvalidValue;
   }
 }
