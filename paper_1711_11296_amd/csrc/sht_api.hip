@@ -52,6 +52,7 @@ struct sht_plan_s {
   int nlev = 0;
   int ncb = 1;                 // column blocking that fixes the workspace layout
   int ncb_fwd = 1, ncb_inv = 1;   // column blocking used by each Legendre kernel
+  int fb = 8;                  // fields per zonal work item
   int sched_fwd = 0, sched_inv = 0;
   int maxN = 0;
   int nitems = 0;
@@ -218,7 +219,9 @@ std::vector<Tile> build_tiles(const sht_plan_s* P, bool analysis, int ncb, int s
   std::vector<double> c;
   for (int l = 0; l < P->nlev; ++l) {
     const LevelDesc& L = P->lev[l];
-    const int ncol = L.Cp / BN;
+    // column tiles that hold at least one field (the row length may be
+    // padded past the last field by more than a tile)
+    const int ncol = std::min(L.Cp / BN, (2 * L.F + BN - 1) / BN);
     for (int m = 0; m <= L.N; ++m) {
       const int nm = L.N - m + 1;
       for (int cb = 0; cb < ncol; ++cb) {
@@ -335,7 +338,15 @@ int build_plan(int nlev, const int* Nv, const int* Jv, const int* Iv, const int*
   }
   P->ncb = choose_ncb(o.form, nlev, Nv, Jv, Fv);
   const int BN = 16 * P->ncb;
-  const int FB = zonal_fields_per_block(o.form);
+  int FB = zonal_fields_per_block(o.form, nlev, Nv[0], Jv[0], Iv[0], Fv[0]);
+  if (FB > 8) {
+    // the wide blocking runs only in the fixed-length kernel, whose
+    // workspace offsets are 32-bit
+    const long long Cp = roundup(2LL * Fv[0], std::max(BN, 2 * FB));
+    const long long Kp = roundup((Jv[0] + 1) / 2, SHT_K_PAD);
+    if ((double)(Nv[0] + 1) * 2.0 * Kp * Cp * P->elem >= 4294967296.0) FB = 8;
+  }
+  P->fb = FB;
 
   // ---- level descriptors and sizes ----
   long long goff = 0, soff = 0, woff = 0, moff = 0, item = 0;
@@ -540,6 +551,7 @@ FftArgs fft_args(const sht_plan_s* P, const void* src, void* dst, int use_w, int
   a.use_w = use_w;
   a.use_inv_I = use_inv_I;
   a.mscale = mscale;
+  a.fb = P->fb;
   return a;
 }
 

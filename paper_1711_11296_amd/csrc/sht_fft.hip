@@ -426,26 +426,31 @@ __device__ __forceinline__ void quad_transpose(int (&x)[4][4]) {
 // (j = lane in quad) at dst(m') = base + (2 m') * plane; runs with m' > N
 // are skipped.  All lanes of the quad must call it.  base is uniform and the
 // level's workspace is below 4 GiB: the per-lane part of each address is a
-// 32-bit byte offset.
+// 32-bit byte offset.  A run of 2 FB values is 64 or 128 bytes; a 128-byte
+// run goes as two 64-byte halves.
 template <typename T, int FB>
 __device__ __forceinline__ void store_runs_quad(T* base, long long plane, int m, int N,
                                                 const cx<T> (&v)[FB]) {
-  static_assert(2 * FB * sizeof(T) == 64, "64-byte runs");
-  int x[4][4];
-  __builtin_memcpy(x, v, 64);
-  quad_transpose(x);
+  constexpr int HALVES = 2 * FB * (int)sizeof(T) / 64;
+  static_assert(HALVES * 64 == 2 * FB * (int)sizeof(T) && HALVES <= 2, "64- or 128-byte runs");
   const int j = threadIdx.x & 3;
   char* b = reinterpret_cast<char*>(base);
   const unsigned step = (unsigned)(2 * plane * (long long)sizeof(T));
-  unsigned off = (unsigned)(m - j) * step + 16u * (unsigned)j;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int mr = m - j + r;
-    if (mr <= N) {
-      typedef int i32x4 __attribute__((ext_vector_type(4)));
-      *reinterpret_cast<i32x4*>(b + off) = i32x4{x[r][0], x[r][1], x[r][2], x[r][3]};
+  for (int hf = 0; hf < HALVES; ++hf) {
+    int x[4][4];
+    __builtin_memcpy(x, reinterpret_cast<const char*>(v) + 64 * hf, 64);
+    quad_transpose(x);
+    unsigned off = (unsigned)(m - j) * step + 16u * (unsigned)j + 64u * (unsigned)hf;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int mr = m - j + r;
+      if (mr <= N) {
+        typedef int i32x4 __attribute__((ext_vector_type(4)));
+        *reinterpret_cast<i32x4*>(b + off) = i32x4{x[r][0], x[r][1], x[r][2], x[r][3]};
+      }
+      off += step;
     }
-    off += step;
   }
 }
 
@@ -1189,8 +1194,11 @@ static bool launch_fixed(bool analysis, const FftArgs& a, int maxN, hipStream_t 
   constexpr bool dbl = sizeof(T) == 8;
   switch (a.lev[0].I) {
     case 2880:
-      *err = launch_p3<T, Plan3<2880, 12, 15>, 512, FB, dbl ? 2 : 4>(analysis, a, maxN, st);
-      return true;
+      if constexpr (FB > 8) return false;  // several wavenumbers per thread: 8 fields at most
+      else {
+        *err = launch_p3<T, Plan3<2880, 12, 15>, 512, FB, dbl ? 2 : 4>(analysis, a, maxN, st);
+        return true;
+      }
     case 1440:
       *err = launch_p3<T, Plan3<1440, 9, 10>, 512, FB, dbl ? 2 : 4>(analysis, a, maxN, st);
       return true;
@@ -1202,8 +1210,8 @@ static bool launch_fixed(bool analysis, const FftArgs& a, int maxN, hipStream_t 
   }
 }
 
-template <typename T, int FB, int FC>
-static hipError_t launch_zonal_t(bool analysis, const FftArgs& a, int maxN, hipStream_t st) {
+// compute units of the current device (persistent grids are sized by it)
+static void ensure_num_cu() {
   if (g_num_cu == 0) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
@@ -1211,6 +1219,11 @@ static hipError_t launch_zonal_t(bool analysis, const FftArgs& a, int maxN, hipS
         g_num_cu <= 0)
       g_num_cu = 256;
   }
+}
+
+template <typename T, int FB, int FC>
+static hipError_t launch_zonal_t(bool analysis, const FftArgs& a, int maxN, hipStream_t st) {
+  ensure_num_cu();
   hipError_t err = hipSuccess;
   if (launch_fixed<T, FB>(analysis, a, maxN, st, &err)) return err;
   int maxI = 0;
@@ -1231,11 +1244,23 @@ static hipError_t launch_zonal_t(bool analysis, const FftArgs& a, int maxN, hipS
   return launch_cfg<T, 512, FB, FC, 4, 4096>(analysis, a, maxI, st);
 }
 
-int zonal_fields_per_block(int form) { return form == SHT_FORM_FP64 ? 4 : 8; }
+int zonal_fields_per_block(int form, int nlev, int N, int J, int I, int F) {
+  if (form == SHT_FORM_FP64) return 4;
+  // wide items halve the item count: only where plenty remain for 256 CUs
+  const long long items16 = (long long)((J + 1) / 2) * ((F + 15) / 16);
+  if (nlev == 1 && items16 >= 4096 && ((I == 1440 && N + 1 <= 512) || (I == 480 && N + 1 <= 256))) return 16;
+  return 8;
+}
 
 int launch_zonal(int form, bool analysis, const FftArgs& a, int maxN, void* stream) {
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (form == SHT_FORM_FP64) return (int)launch_zonal_t<double, 4, 1>(analysis, a, maxN, st);
+  if (a.fb == 16) {
+    ensure_num_cu();
+    hipError_t err = hipErrorInvalidValue;
+    if (!launch_fixed<float, 16>(analysis, a, maxN, st, &err)) return (int)hipErrorInvalidValue;
+    return (int)err;
+  }
   return (int)launch_zonal_t<float, 8, 4>(analysis, a, maxN, st);
 }
 

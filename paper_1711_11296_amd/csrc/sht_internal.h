@@ -62,6 +62,7 @@ struct FftArgs {
   int use_inv_I;
   double mscale;
   int tw_lds;        // element offset of the LDS twiddle table (set at launch)
+  int fb;            // fields per work item (zonal_fields_per_block)
 };
 
 // One work tile of a Legendre kernel; level < 0 marks an idle slot.
@@ -83,7 +84,12 @@ struct GemmArgs {
 
 // ---- kernel launchers (sht_fft.hip, sht_legendre.hip) ----
 // The stream argument is a hipStream_t.
-int zonal_fields_per_block(int form);
+// Fields per zonal work item: 4 (FP64) or 8, and 16 for large single-level
+// FP32-data plans whose fixed-length kernel holds one wavenumber per thread
+// (I = 1440 or 480), so that every workspace run is a whole 128-byte line.
+// The level's workspace size with that blocking must be below 4 GiB (the
+// planner checks and falls back to 8).
+int zonal_fields_per_block(int form, int nlev, int N, int J, int I, int F);
 int launch_zonal(int form, bool analysis, const FftArgs& a, int maxN, void* stream);
 int launch_legendre(int form, bool analysis, const GemmArgs& g, int ncb, void* stream);
 // Widest column blocking (16-column units) a Legendre kernel of a form takes.

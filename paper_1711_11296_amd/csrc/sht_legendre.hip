@@ -342,7 +342,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
   // beyond F), rows beyond n = N are masked; offsets stay below 4 GiB (at
   // most 16 NCB fields of at most (N+1)(N+2)/2 rows).
   const long long sfirst = ((long long)(c0 >> 1) * nc + sbase) * 2;
-  const long long sbytes = ((long long)L.F * nc * 2 - sfirst) * (long long)sizeof(T);
+  long long sbytes = ((long long)L.F * nc * 2 - sfirst) * (long long)sizeof(T);
+  if (sbytes < 0) sbytes = 0;  // a tile past the last field (all its reads are zeros)
   const __amdgpu_buffer_rsrc_t srs = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<T*>(spec + sfirst), (short)0, (int)(unsigned)(sbytes > 0xFFFFFFFFLL ? 0xFFFFFFFFLL : sbytes),
       0x00020000);

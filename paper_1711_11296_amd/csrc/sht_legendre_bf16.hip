@@ -385,7 +385,8 @@ __global__ __launch_bounds__(X6Synthesis<NCB>::NT) __attribute__((amdgpu_waves_p
   // number: reads past the end of the level's spectra return zero (fields
   // beyond F), rows beyond n = N are masked; offsets stay below 4 GiB.
   const long long sfirst = ((long long)(c0 >> 1) * nc + sbase) * 2;
-  const long long sbytes = ((long long)L.F * nc * 2 - sfirst) * 4LL;
+  long long sbytes = ((long long)L.F * nc * 2 - sfirst) * 4LL;
+  if (sbytes < 0) sbytes = 0;  // a tile past the last field (all its reads are zeros)
   const __amdgpu_buffer_rsrc_t srs = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<float*>(spec + sfirst), (short)0, (int)(unsigned)(sbytes > 0xFFFFFFFFLL ? 0xFFFFFFFFLL : sbytes),
       0x00020000);

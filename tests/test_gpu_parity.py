@@ -236,3 +236,31 @@ def test_c5_batch_field0(form):
     print("C5 %s: inverse rel-L2 %.3e, forward rel-L2 %.3e" % (form, e_inv, e_fwd))
     assert e_inv < TOL[form] and e_fwd < TOL[form]
     p.close()
+
+
+@pytest.mark.parametrize("form", ["fp32", "bf16x6"])
+def test_wide_items_first_launch_in_fresh_process(form):
+    """A large single-level FP32-data plan with I = 480 and N + 1 <= 256
+    runs the zonal stage with 16-field work items; its launch sizing must not
+    depend on an earlier launch of another zonal kernel in the process, so
+    the plan's first transform runs in a fresh interpreter (round trip,
+    J >= 2N+1, spectra against their input; 201 latitude pairs x 25 field
+    blocks of 16)."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "import torch\n"
+        "from paper_1711_11296_amd import Plan, inputs\n"
+        "N, J, I, F = 200, 401, 480, 400\n"
+        "p = Plan(N, J, I, F, grid='cc_poles', form=%r)\n"
+        "a = torch.from_numpy(inputs.random_spectra(N, F, seed=3, profile='k3')).to('cuda:0', torch.float32)\n"
+        "s = p.forward(p.inverse(a))\n"
+        "torch.cuda.synchronize()\n"
+        "print('ERR', float((s - a).norm() / a.norm()))\n" % (root, form))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    err = float([ln for ln in r.stdout.splitlines() if ln.startswith("ERR")][-1].split()[1])
+    assert err < 10 * TOL[form], err
