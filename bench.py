@@ -68,14 +68,19 @@ KERNEL_PREFIX = {("legendre_analysis", "fp32"): "sht::k_legendre_analysis<float,
 
 
 def source_digest(form):
-    """SHA-256 prefix of the sources the form's Legendre kernels are built
-    from (kernel file, then the shared device header)."""
+    """SHA-256 prefix of the code the form's Legendre kernels are built from
+    (kernel file, then the shared device header), with // comments and blank
+    lines removed, so that a change of wording does not void a measurement."""
     import hashlib
+    import re
     csrc = os.path.join(ROOT, "paper_1711_11296_amd", "csrc")
     files = ["sht_legendre_bf16.hip" if form == "bf16x6" else "sht_legendre.hip", "sht_device.h"]
     h = hashlib.sha256()
     for f in files:
-        h.update(open(os.path.join(csrc, f), "rb").read())
+        for line in open(os.path.join(csrc, f), encoding="utf-8"):
+            code = re.sub(r"//.*", "", line).rstrip()
+            if code:
+                h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

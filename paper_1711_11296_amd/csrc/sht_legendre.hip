@@ -13,9 +13,11 @@
 //     S^m_j = sum_{n-m even} P~_n^m(mu_j) a_n^m,  A^m_j = sum_{n-m odd} ...
 // i.e. the same table read transposed.
 //
-// Table layout: per (level, m) a block of R_m = roundup(N-m+1, 64) rows
-// (row r = n - m, zero padding) by Kp columns (j, zero padding), row-major.
-// Workspace layout: ws[m][parity][j][c] (see the zonal stage).
+// Table layout: two copies per (level, m), each blocked in the order its
+// kernel streams it (analysis: rows r = n - m padded to 128 by Kp columns j;
+// synthesis: 128-latitude tiles by blocks of 32 natural rows; zero padding;
+// see the kernels below).  The split-bfloat16 kernels read the same FP32
+// copies.  Workspace layout: ws[m][parity][j][c] (see the zonal stage).
 //
 // Work decomposition: a host-built list gives one tile per workgroup; it is
 // ordered so that the tiles of one m, which share the same right-hand
