@@ -19,7 +19,11 @@
  *   Grids (sht_grid_t): SHT_GRID_FEJER2 is the paper's pole-free grid,
  *   theta_j = j*pi/(J+1), j = 1..J (Sec. 3.1, eq. cc-points);
  *   SHT_GRID_CC_POLES is the classical Clenshaw-Curtis grid with the poles,
- *   theta_j = j*pi/(J-1), j = 0..J-1.  Row 0 is nearest the north pole.
+ *   theta_j = j*pi/(J-1), j = 0..J-1; SHT_GRID_FEJER1 is the shifted grid
+ *   of Sec. 3.3, theta_j = (j-1/2)*pi/J, j = 1..J (eq. fejer1-points), with
+ *   Fejer's first-rule weights (eq. fejer1-wgt read with a factor 2 before
+ *   its sum, without which the rule is not interpolatory); it does not
+ *   nest.  Row 0 is nearest the north pole.
  *   lambda_i = 2*pi*i/I.  P~_n^m has unit L2 norm over mu in [-1, 1]
  *   (eq. pnm-ortho) and no Condon-Shortley phase.
  *
@@ -62,7 +66,8 @@ typedef struct sht_plan_s* sht_plan_t;
 
 typedef enum {
   SHT_GRID_CC_POLES = 0,
-  SHT_GRID_FEJER2 = 1
+  SHT_GRID_FEJER2 = 1,
+  SHT_GRID_FEJER1 = 2
 } sht_grid_t;
 
 typedef enum {
@@ -110,7 +115,7 @@ enum {
  * sht_plan: plan for one level with the defaults (SHT_GRID_CC_POLES,
  * SHT_FORM_FP64) on the current HIP device.  Returns NULL on failure.
  *   N >= 0 truncation wavenumber; J latitudes (>= 2 on CC_POLES, >= 1 on
- *   FEJER2); I >= 2N+1 longitudes (radix 2, 3, 5 only, I <= 4096);
+ *   FEJER2 and FEJER1); I >= 2N+1 longitudes (radix 2, 3, 5 only, I <= 4096);
  *   nfields >= 1 independent fields.  J < 2N+1 is accepted (the quadrature
  *   then aliases, Sec. 3.1; SHT_Q_EXACT reports 0).
  * Plan time builds the nodes and weights (Sec. 3.1, eq. cc-points,

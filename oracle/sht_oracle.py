@@ -16,8 +16,9 @@ plain three-term recurrence.  Each function names the passage it follows.
 Conventions (the readings of the paper used throughout):
   * grid kinds: "fejer2" is the paper's pole-free grid, theta_j = j*pi/(J+1),
     j = 1..J (Sec. 3.1, eq. cc-points); "cc_poles" is the classical
-    Clenshaw-Curtis grid with the poles, theta_j = j*pi/(J-1), j = 0..J-1.
-    Row 0 is the one nearest the north pole in both cases.
+    Clenshaw-Curtis grid with the poles, theta_j = j*pi/(J-1), j = 0..J-1;
+    "fejer1" is the shifted grid of Sec. 3.3, theta_j = (j - 1/2)*pi/J,
+    j = 1..J (eq. fejer1-points).  Row 0 is the one nearest the north pole.
   * P~_n^m is normalised so that its square integrates to 1 over mu in
     [-1, 1] (Sec. 2, eq. pnm-ortho), with no Condon-Shortley phase.
   * spectra are stored for m >= 0 only, as float pairs (re, im), m-major
@@ -31,7 +32,7 @@ import math
 
 import numpy as np
 
-GRID_KINDS = ("cc_poles", "fejer2")
+GRID_KINDS = ("cc_poles", "fejer2", "fejer1")
 
 
 # --------------------------------------------------------------------------
@@ -73,14 +74,18 @@ def _node_fraction(J, kind, j):
         if J < 1:
             raise ValueError("fejer2 needs J >= 1")
         return j + 1, J + 1          # Sec. 3.1, eq. cc-points
+    if kind == "fejer1":
+        if J < 1:
+            raise ValueError("fejer1 needs J >= 1")
+        return 2 * j + 1, 2 * J      # Sec. 3.3, eq. fejer1-points
     raise ValueError("unknown grid kind %r" % (kind,))
 
 
 def nodes(J, kind):
     """Colatitudes theta_j, mu_j = cos(theta_j) = sin(phi_j) and sin(theta_j).
 
-    Sec. 3.1 (eq. cc-points) for "fejer2"; the classical grid with the poles
-    for "cc_poles".  mu is evaluated as sin(pi*(q-2p)/(2q)) with the fraction
+    Sec. 3.1 (eq. cc-points) for "fejer2"; Sec. 3.3 (eq. fejer1-points) for
+    "fejer1"; the classical grid with the poles for "cc_poles".  mu is evaluated as sin(pi*(q-2p)/(2q)) with the fraction
     reduced by its gcd, so that the equator gets mu = 0 exactly, the mirror
     node gets exactly -mu and nested grids share their common nodes bit for
     bit.
@@ -103,6 +108,12 @@ def weights(J, kind):
     App. A): w_j = 4 sin(theta_j)/(J+1) * sum over odd p <= J of
     sin(p theta_j)/p.
 
+    "fejer1": Fejer's first rule, the interpolatory rule on the shifted nodes
+    (Sec. 3.3, eq. fejer1-wgt): w_j = (2/J) [1 - 2 sum_{p=1}^{floor(J/2)}
+    cos(2 p theta_j)/(4p^2-1)].  The printed form has no factor 2 before the
+    sum; without it the rule is not exact even for mu^2 (J = 3), so the
+    factor is taken as lost in print.
+
     "cc_poles": the classical Clenshaw-Curtis rule on n+1 = J points,
     w_k = (c_k/n) [1 - sum_{l=1}^{floor(n/2)} b_l cos(2 l theta_k)/(4l^2-1)]
     with c_0 = c_n = 1, c_k = 2 otherwise and b_l = 1 for l = n/2, 2 otherwise
@@ -116,6 +127,15 @@ def weights(J, kind):
             for p in range(1, J + 1, 2):
                 s += _sinpi_frac((p * p0) % (2 * q), q) / p
             w[j] = 4.0 * _sinpi_frac(p0, q) / (J + 1) * s
+        return w
+    if kind == "fejer1":
+        for j in range(J):
+            s = 0.0
+            for p in range(1, J // 2 + 1):
+                # 2 p theta_j = pi * p (2j+1) / J, reduced mod 2 pi
+                r = (p * (2 * j + 1)) % (2 * J)
+                s += math.cos(math.pi * r / J) / (4.0 * p * p - 1.0)
+            w[j] = 2.0 / J * (1.0 - 2.0 * s)
         return w
     if kind == "cc_poles":
         n = J - 1

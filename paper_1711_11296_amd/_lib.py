@@ -11,7 +11,7 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsht.so")
 
-GRID = {"cc_poles": 0, "fejer2": 1}
+GRID = {"cc_poles": 0, "fejer2": 1, "fejer1": 2}
 FORM = {"fp64": 0, "fp32": 1, "bf16x6": 2}
 
 SHT_OK, SHT_EINVAL, SHT_ENOMEM, SHT_EHIP, SHT_ESTATE = 0, -1, -2, -3, -4

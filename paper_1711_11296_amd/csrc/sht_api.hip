@@ -144,7 +144,7 @@ int check_level_args(int N, int J, int I, int F, int grid) {
   if (F < 1) return fail(SHT_EINVAL, "nfields must be >= 1");
   if (!grid_args_ok(J, grid))
     return fail(SHT_EINVAL, grid == SHT_GRID_CC_POLES ? "J must be >= 2 on the CC grid with poles"
-                                                     : (grid == SHT_GRID_FEJER2 ? "J must be >= 1"
+                                                     : (grid == SHT_GRID_FEJER2 || grid == SHT_GRID_FEJER1 ? "J must be >= 1"
                                                                                 : "unknown grid kind"));
   if (I < 2 * N + 1) return fail(SHT_EINVAL, "I must be >= 2N+1 (no retained wavenumber may alias)");
   if (I > SHT_MAX_I) return fail(SHT_EINVAL, "I exceeds the supported maximum 4096");

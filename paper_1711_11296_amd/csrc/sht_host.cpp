@@ -43,11 +43,15 @@ long double sinpi_frac_l(long a, long b) {
               (long double)(b / g));
 }
 
+// theta_j = pi p / q
 void node_pq(int J, int kind, int j, long* p, long* q) {
   if (kind == SHT_GRID_CC_POLES) {
     *p = j;
     *q = J - 1;
-  } else {
+  } else if (kind == SHT_GRID_FEJER1) {  // Sec. 3.3, eq. fejer1-points
+    *p = 2 * j + 1;
+    *q = 2 * J;
+  } else {  // Sec. 3.1, eq. cc-points
     *p = j + 1;
     *q = J + 1;
   }
@@ -57,7 +61,7 @@ void node_pq(int J, int kind, int j, long* p, long* q) {
 
 bool grid_args_ok(int J, int kind) {
   if (kind == SHT_GRID_CC_POLES) return J >= 2;
-  if (kind == SHT_GRID_FEJER2) return J >= 1;
+  if (kind == SHT_GRID_FEJER2 || kind == SHT_GRID_FEJER1) return J >= 1;
   return false;
 }
 
@@ -82,6 +86,21 @@ void grid_weights(int J, int kind, double* w) {
       long double s = 0.0L;
       for (long p = 1; p <= J; p += 2) s += sinpi_frac_l(p * p0, q) / (long double)p;
       w[j] = (double)(4.0L * sinpi_frac_l(p0, q) / (long double)(J + 1) * s);
+    }
+    return;
+  }
+  if (kind == SHT_GRID_FEJER1) {
+    // Fejer's first rule (Sec. 3.3, eq. fejer1-wgt, with the factor 2 before
+    // the sum that makes the rule interpolatory):
+    // w_j = (2/J) [1 - 2 sum_{p=1}^{J/2} cos(2 p theta_j) / (4 p^2 - 1)],
+    // 2 p theta_j = pi p (2j+1) / J
+    for (long j = 0; j < J; ++j) {
+      long double s = 0.0L;
+      for (long p = 1; p <= J / 2; ++p) {
+        const long r = (p * (2 * j + 1)) % (2L * J);
+        s += cosl(PI * (long double)r / (long double)J) / (4.0L * (long double)p * (long double)p - 1.0L);
+      }
+      w[j] = (double)(2.0L / (long double)J * (1.0L - 2.0L * s));
     }
     return;
   }

@@ -30,7 +30,7 @@ class Plan:
     """A transform plan on the current GPU.
 
     levels: one (N, J, I, nfields) tuple, or a list of them for a batched
-    hierarchy run in one launch per stage.  grid: "cc_poles" or "fejer2";
+    hierarchy run in one launch per stage.  grid: "cc_poles", "fejer2" or "fejer1";
     form: "fp64", "fp32" or "bf16x6".
     """
 

@@ -84,6 +84,8 @@ def test_tiny_sweep(form, kind, N):
     ("fejer2", 130, 250, 300, 9),       # even J (no equator row), F not a multiple of 8
     ("cc_poles", 64, 129, 200, 17),     # 5^2 radix, three field blocks
     ("fejer2", 33, 80, 81, 2),          # J > 2N+1, pure radix 3
+    ("fejer1", 90, 183, 192, 6),        # shifted grid (Sec. 3.3), odd J
+    ("fejer1", 71, 144, 150, 3),        # shifted grid, even J (no equator row)
 ])
 def test_multi_tile_parity(form, kind, N, J, I, F):
     _roundtrip_case(N, J, I, F, kind, form, profile="k3", seed=N)

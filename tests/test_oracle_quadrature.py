@@ -21,6 +21,8 @@ def test_nodes_closed_form(kind, J):
     theta, mu, sint = O.nodes(J, kind)
     if kind == "cc_poles":
         ref = np.arange(J) * math.pi / (J - 1)
+    elif kind == "fejer1":
+        ref = (np.arange(1, J + 1) - 0.5) * math.pi / J   # Sec. 3.3, eq. fejer1-points
     else:
         ref = np.arange(1, J + 1) * math.pi / (J + 1)
     assert np.allclose(theta, ref, rtol=0, atol=1e-15)
@@ -73,6 +75,28 @@ def test_weights_hand_values():
                        np.array([1, 8, 12, 8, 1]) / 15, rtol=1e-15)
     # J = 2 on the classical grid is the trapezoid rule
     assert np.allclose(O.weights(2, "cc_poles"), [1.0, 1.0], rtol=1e-15)
+    # Fejer's first rule: the midpoint rule in theta for J = 1; J = 2 has
+    # nodes mu = +-1/sqrt(2) and weights 1, 1; J = 3 (theta = pi/6, pi/2,
+    # 5pi/6) is exact for 1 and mu^2 only with weights 4/9, 10/9, 4/9
+    assert np.allclose(O.weights(1, "fejer1"), [2.0], rtol=1e-15)
+    assert np.allclose(O.weights(2, "fejer1"), [1.0, 1.0], rtol=1e-15)
+    assert np.allclose(O.weights(3, "fejer1"), [4 / 9, 10 / 9, 4 / 9], rtol=1e-15)
+
+
+def test_fejer1_printed_weights_lack_a_factor_two():
+    """Sec. 3.3 prints eq. fejer1-wgt as (2/J)(1 - sum cos(2p theta)/(4p^2-1));
+    that form sums to 2 but does not integrate mu^2 exactly, while the form
+    with 2 * sum (Fejer's first rule, the oracle's) does: the reading taken."""
+    J = 7
+    theta, mu, _ = O.nodes(J, "fejer1")
+    p = np.arange(1, J // 2 + 1)
+    s = (np.cos(2 * np.outer(theta, p)) / (4 * p * p - 1)).sum(axis=1)
+    printed = 2.0 / J * (1.0 - s)
+    assert abs(printed.sum() - 2.0) < 1e-14
+    assert abs(np.sum(printed * mu ** 2) - 2 / 3) > 1e-2
+    w = O.weights(J, "fejer1")
+    assert np.allclose(w, 2.0 / J * (1.0 - 2.0 * s), rtol=1e-14)
+    assert abs(np.sum(w * mu ** 2) - 2 / 3) < 1e-15
 
 
 @pytest.mark.parametrize("kind", O.GRID_KINDS)
@@ -109,6 +133,8 @@ def test_weights_moment_system_mpmath(kind, J):
     mpmath.mp.dps = 40
     if kind == "cc_poles":
         th = [mpmath.pi * j / (J - 1) for j in range(J)]
+    elif kind == "fejer1":
+        th = [mpmath.pi * (2 * j + 1) / (2 * J) for j in range(J)]
     else:
         th = [mpmath.pi * (j + 1) / (J + 1) for j in range(J)]
     A = mpmath.matrix(J, J)
