@@ -41,6 +41,9 @@ def parse():
     ap.add_argument("--grid", default=None)
     ap.add_argument("--form", default=None)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-form comparison")
+    ap.add_argument("--reduced", action="store_true",
+                    help="reduced transform (Sec. 4.1): leave out the polar latitudes where every "
+                         "|P~_n^m| < 1e-16; reported in config, never the default")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy a 1 GiB buffer 3 times (calibrates HBM byte counters)")
@@ -144,7 +147,7 @@ def main():
 
     # ---- workload: grids synthesised from k^-3 band-limited spectra ----
     spec0 = inputs.random_spectra(N, F, seed=0, profile="k3")
-    plan = Plan(N, J, I, F, grid=args.grid, form=args.form)
+    plan = Plan(N, J, I, F, grid=args.grid, form=args.form, reduced=args.reduced)
     a = torch.from_numpy(spec0).to("cuda:0", dt)
     g = plan.inverse(a)
     torch.cuda.synchronize()
@@ -197,7 +200,7 @@ def main():
     fp64 = None
     if not args.no_fp64 and args.form != "fp64":
         del s_out, g_out
-        p64 = Plan(N, J, I, F, grid=args.grid, form="fp64")
+        p64 = Plan(N, J, I, F, grid=args.grid, form="fp64", reduced=args.reduced)
         g64 = g.double()
         st = max(2, args.steps // 4)
         secs64, stages64, _, _ = time_pairs(p64, g64, st, 1, torch)
@@ -223,9 +226,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if args.form == "fp32" else ("f64" if args.form == "fp64" else "bf16x6/f32"),
         "data": "synthetic: grids synthesised from k^-3 random spectra (seed 0)",
-        "config": {"workload": "T%d batch: N=%d J=%d I=%d, %d fields, %s grid, %s form, forward+inverse"
-                               % (N, N, J, I, F, args.grid, args.form),
-                   "N": N, "J": J, "I": I, "fields": F, "grid": args.grid, "form": args.form},
+        "config": {"workload": "T%d batch: N=%d J=%d I=%d, %d fields, %s grid, %s form, forward+inverse%s"
+                               % (N, N, J, I, F, args.grid, args.form,
+                                  ", reduced transform" if args.reduced else ""),
+                   "N": N, "J": J, "I": I, "fields": F, "grid": args.grid, "form": args.form,
+                   "reduced": bool(args.reduced)},
         "legendre_tflops": leg_tflops,
         "legendre_mfma_frac": leg_tflops / peak,
         "end_to_end_mfma_frac": 2 * flops_dir / (ms_step * 1e-3) / 1e12 / peak,

@@ -83,6 +83,12 @@ typedef struct {
   int form;       /* sht_form_t */
   int autotune;   /* nonzero: time candidate tile shapes at plan time */
   int use_graph;  /* nonzero: replay each transform from a captured hipGraph */
+  int reduced;    /* nonzero: reduced transform (Sec. 4.1): for each m the
+                     polar latitudes at which every |P~_n^m| (n = m..N) is
+                     below 1e-16 are left out of both Legendre sums, in
+                     whole blocks of the kernels (32 latitudes; 16 in the
+                     FP64 analysis; 128 in the synthesis).  The terms left
+                     out are below 1e-16 relative. */
 } sht_options;
 
 enum {
@@ -107,6 +113,13 @@ enum {
   SHT_Q_LEGENDRE_FLOPS = 9, /* double: parity-folded Legendre flops of one
                                direction, 2*ceil(J/2)*(N+1)(N+2)*F summed
                                over levels */
+  SHT_Q_LEGENDRE_FLOPS_KEPT = 10, /* double: the part of SHT_Q_LEGENDRE_FLOPS
+                               the analysis kernel multiplies when the plan
+                               uses the reduced transform: for each m,
+                               4 (N-m+1) F (ceil(J/2) - b_m), b_m = the latitudes
+                               left out, a whole number of the kernel's
+                               blocks (32; 16 in the FP64 form); equal to
+                               SHT_Q_LEGENDRE_FLOPS otherwise */
   SHT_Q_GRID_OFFSET = 100,  /* size_t: element offset of level (key-100) */
   SHT_Q_SPEC_OFFSET = 200   /* size_t: element offset of level (key-200) */
 };

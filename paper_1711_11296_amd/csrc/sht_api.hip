@@ -48,6 +48,9 @@ struct sht_plan_s {
   int grid = SHT_GRID_CC_POLES;
   int autotune = 0;
   int use_graph = 0;
+  int reduced = 0;             // reduced transform (Sec. 4.1)
+  std::vector<int> jst;        // per (level, m): first latitude kept (0 if not reduced)
+  int* d_jst = nullptr;
   int device = 0;
   int nlev = 0;
   int ncb = 1;                 // column blocking that fixes the workspace layout
@@ -62,6 +65,7 @@ struct sht_plan_s {
   size_t grid_elems = 0, spec_elems = 0;
   size_t ws_elems = 0, table_elems = 0, table_bytes = 0, ws_bytes = 0;
   double flops = 0.0;
+  double flops_kept = 0.0;     // flops the analysis kernel multiplies (reduced transform)
   bool exact = true;
   void* d_table = nullptr;      // analysis copy of the table
   void* d_table_syn = nullptr;  // synthesis copy (blocked, parity split)
@@ -224,19 +228,23 @@ std::vector<Tile> build_tiles(const sht_plan_s* P, bool analysis, int ncb, int s
     const int ncol = std::min(L.Cp / BN, (2 * L.F + BN - 1) / BN);
     for (int m = 0; m <= L.N; ++m) {
       const int nm = L.N - m + 1;
+      const int j0 = P->jst[L.m_base + m];  // reduced transform: latitudes below are left out
       for (int cb = 0; cb < ncol; ++cb) {
         if (analysis) {
-          // 128-row tiles; 256 in the split form
+          // 128-row tiles; 256 in the split form; K blocks of 32 latitudes
+          // (16 in the FP64 form)
           const int rows = P->form == SHT_FORM_BF16X6 ? 256 : 128;
+          const int kb = P->form == SHT_FORM_FP64 ? 16 : 32;
           for (int rb = 0; rb < (nm + rows - 1) / rows; ++rb) {
             t.push_back(Tile{l, m, rb, cb});
-            c.push_back((double)L.Kp * BN);
+            c.push_back((double)(L.Kp - j0 / kb * kb) * BN);
           }
         } else {
           // 128-latitude tiles; K blocks of 32 natural rows (64 in the
-          // split form)
+          // split form); tiles wholly below j0 are left out (the zonal
+          // synthesis reads those workspace rows as zero)
           const int kr2 = P->form == SHT_FORM_BF16X6 ? 64 : 32;
-          for (int jt = 0; jt < (L.Jh + 127) / 128; ++jt) {
+          for (int jt = j0 / 128; jt < (L.Jh + 127) / 128; ++jt) {
             t.push_back(Tile{l, m, jt, cb});
             c.push_back(((double)roundup(nm, kr2) + kr2) * 2 * BN);
           }
@@ -250,7 +258,7 @@ std::vector<Tile> build_tiles(const sht_plan_s* P, bool analysis, int ncb, int s
 
 template <typename T>
 void fill_table_level(const LevelDesc& L, const double* mu, const double* sint,
-                      T* dst, const long long* off_a, T* dsyn, const long long* off_s) {
+                      T* dst, const long long* off_a, T* dsyn, const long long* off_s, int* j0) {
   const int N = L.N, Jh = L.Jh, Kp = L.Kp;
   int nth = (int)std::thread::hardware_concurrency();
   nth = std::max(1, std::min(nth, 64));
@@ -263,6 +271,18 @@ void fill_table_level(const LevelDesc& L, const double* mu, const double* sint,
         const int nm = N - m + 1;
         col.assign((size_t)nm * Jh, 0.0);
         alf_column(N, m, Jh, mu, sint, col.data(), Jh);
+        if (j0) {
+          // reduced transform (Sec. 4.1): first latitude (from the pole) at
+          // which some |P~_n^m| reaches 1e-16
+          int first = Jh;
+          for (int r = 0; r < nm; ++r)
+            for (int j = 0; j < first; ++j)
+              if (std::fabs(col[(size_t)r * Jh + j]) >= 1e-16) {
+                first = j;
+                break;
+              }
+          j0[m] = first;
+        }
         T* blk = dst + off_a[m];
         const int R = (int)roundup(nm, 128);
         constexpr int KB = sizeof(T) == 4 ? 32 : 16, E = 16 / (int)sizeof(T);
@@ -315,7 +335,7 @@ int build_plan(int nlev, const int* Nv, const int* Jv, const int* Iv, const int*
   *out = nullptr;
   if (nlev < 1 || nlev > SHT_MAX_LEVELS) return fail(SHT_EINVAL, "nlevels must be 1..8");
   if (!Nv || !Jv || !Iv || !Fv) return fail(SHT_EINVAL, "level arrays must not be NULL");
-  sht_options o{SHT_GRID_CC_POLES, SHT_FORM_FP64, 0, 0};
+  sht_options o{SHT_GRID_CC_POLES, SHT_FORM_FP64, 0, 0, 0};
   if (opts) o = *opts;
   if (o.form < SHT_FORM_FP64 || o.form > SHT_FORM_BF16X6) return fail(SHT_EINVAL, "unknown form");
   for (int l = 0; l < nlev; ++l) {
@@ -329,6 +349,7 @@ int build_plan(int nlev, const int* Nv, const int* Jv, const int* Iv, const int*
   P->grid = o.grid;
   P->autotune = o.autotune;
   P->use_graph = o.use_graph;
+  P->reduced = o.reduced != 0;
   P->nlev = nlev;
   P->elem = o.form == SHT_FORM_FP64 ? 8 : 4;
   int rc = hip_check(hipGetDevice(&P->device), "hipGetDevice");
@@ -408,6 +429,7 @@ int build_plan(int nlev, const int* Nv, const int* Jv, const int* Iv, const int*
 
   // ---- host tables ----
   std::vector<unsigned char> htab(P->table_elems * tel), htabs(P->table_syn_elems * tel);
+  P->jst.assign((size_t)moff, 0);
   std::vector<double> hw;
   std::vector<std::vector<unsigned char>> htw(nlev);
   size_t tw_total = 0;
@@ -425,10 +447,10 @@ int build_plan(int nlev, const int* Nv, const int* Jv, const int* Iv, const int*
     const long long* ts = taboff_syn.data() + L.m_base;
     if (o.form == SHT_FORM_FP64)
       fill_table_level<double>(L, mu.data(), sint.data(), reinterpret_cast<double*>(htab.data()), to,
-                               reinterpret_cast<double*>(htabs.data()), ts);
+                               reinterpret_cast<double*>(htabs.data()), ts, P->reduced ? P->jst.data() + L.m_base : nullptr);
     else
       fill_table_level<float>(L, mu.data(), sint.data(), reinterpret_cast<float*>(htab.data()), to,
-                              reinterpret_cast<float*>(htabs.data()), ts);
+                              reinterpret_cast<float*>(htabs.data()), ts, P->reduced ? P->jst.data() + L.m_base : nullptr);
     // twiddles exp(-2 pi i k / I)
     const size_t cs = 2 * P->elem;
     htw[l].resize((size_t)L.I * cs);
@@ -466,12 +488,21 @@ int build_plan(int nlev, const int* Nv, const int* Jv, const int* Iv, const int*
       }
     }
   }
+  // flops kept by the reduced transform (whole analysis blocks left out)
+  P->flops_kept = 0.0;
+  for (int l = 0; l < nlev; ++l) {
+    const LevelDesc& L = P->lev[l];
+    const int kb = o.form == SHT_FORM_FP64 ? 16 : 32;
+    for (int m = 0; m <= L.N; ++m)
+      P->flops_kept += 4.0 * (L.N - m + 1) * L.F * (double)(L.Jh - P->jst[L.m_base + m] / kb * kb);
+  }
   std::vector<Tile> sf = build_tiles(P, true, P->ncb_fwd, 0), si = build_tiles(P, false, P->ncb_inv, 0);
   P->ntiles_fwd = (int)sf.size();
   P->ntiles_inv = (int)si.size();
 
   // ---- device buffers ----
-  void *dtw = nullptr, *dw = nullptr, *dto = nullptr, *dtf = nullptr, *dti = nullptr, *dtos = nullptr;
+  void *dtw = nullptr, *dw = nullptr, *dto = nullptr, *dtf = nullptr, *dti = nullptr, *dtos = nullptr,
+       *djs = nullptr;
   if ((rc = dev_alloc(P, &P->d_table, htab.size())) ||
       (rc = dev_alloc(P, &P->d_table_syn, htabs.size())) ||
       (rc = dev_alloc(P, &dtos, taboff_syn.size() * sizeof(long long))) ||
@@ -480,7 +511,8 @@ int build_plan(int nlev, const int* Nv, const int* Jv, const int* Iv, const int*
       (rc = dev_alloc(P, &dw, w_total * sizeof(double))) ||
       (rc = dev_alloc(P, &dto, taboff.size() * sizeof(long long))) ||
       (rc = dev_alloc(P, &dtf, sf.size() * sizeof(Tile))) ||
-      (rc = dev_alloc(P, &dti, si.size() * sizeof(Tile)))) {
+      (rc = dev_alloc(P, &dti, si.size() * sizeof(Tile))) ||
+      (rc = dev_alloc(P, &djs, P->jst.size() * sizeof(int)))) {
     free_plan(P);
     delete P;
     return rc;
@@ -491,6 +523,7 @@ int build_plan(int nlev, const int* Nv, const int* Jv, const int* Iv, const int*
   P->d_taboff_syn = static_cast<long long*>(dtos);
   P->d_tiles_fwd = static_cast<Tile*>(dtf);
   P->d_tiles_inv = static_cast<Tile*>(dti);
+  P->d_jst = static_cast<int*>(djs);
   for (int l = 0; l < nlev; ++l) {
     P->lev[l].tw = static_cast<unsigned char*>(dtw) + tw_off[l];
     P->lev[l].wrow = P->d_w + w_off[l];
@@ -512,6 +545,9 @@ int build_plan(int nlev, const int* Nv, const int* Jv, const int* Iv, const int*
                    "upload table offsets");
   if (!rc) rc = hip_check(hipMemcpy(dtf, sf.data(), sf.size() * sizeof(Tile), hipMemcpyHostToDevice), "upload tiles");
   if (!rc) rc = hip_check(hipMemcpy(dti, si.data(), si.size() * sizeof(Tile), hipMemcpyHostToDevice), "upload tiles");
+  if (!rc)
+    rc = hip_check(hipMemcpy(djs, P->jst.data(), P->jst.size() * sizeof(int), hipMemcpyHostToDevice),
+                   "upload latitude starts");
   if (!rc) rc = hip_check(hipDeviceSynchronize(), "plan synchronize");
   if (!rc && o.autotune) rc = autotune(P);
   if (rc) {
@@ -552,6 +588,7 @@ FftArgs fft_args(const sht_plan_s* P, const void* src, void* dst, int use_w, int
   a.use_inv_I = use_inv_I;
   a.mscale = mscale;
   a.fb = P->fb;
+  a.jstart = P->d_jst;
   return a;
 }
 
@@ -564,6 +601,7 @@ GemmArgs gemm_args(const sht_plan_s* P, bool analysis, const void* spec_in, void
   g.tiles = analysis ? P->d_tiles_fwd : P->d_tiles_inv;
   g.tab_off = analysis ? P->d_taboff : P->d_taboff_syn;
   g.table = analysis ? P->d_table : P->d_table_syn;
+  g.jstart = P->d_jst;
   g.spec_in = spec_in;
   g.spec_out = spec_out;
   g.ws = P->d_ws;
@@ -867,6 +905,7 @@ int sht_plan_query(sht_plan_t plan, int key, void* out) {
     case SHT_Q_FORM: *(int*)out = P->form; return SHT_OK;
     case SHT_Q_GRID_KIND: *(int*)out = P->grid; return SHT_OK;
     case SHT_Q_LEGENDRE_FLOPS: *(double*)out = P->flops; return SHT_OK;
+    case SHT_Q_LEGENDRE_FLOPS_KEPT: *(double*)out = P->flops_kept; return SHT_OK;
     default: break;
   }
   if (key >= SHT_Q_GRID_OFFSET && key < SHT_Q_GRID_OFFSET + P->nlev) {

@@ -642,7 +642,9 @@ __global__ __launch_bounds__(NT) void k_zonal_synthesis(const FftArgs a) {
 #pragma unroll
     for (int s = 0; s < MS; ++s) {
       const int m = threadIdx.x + s * NT;
-      if (m <= L.N) {
+      // rows below the first 128-latitude tile the Legendre synthesis
+      // computes for this m (reduced transform) are zero
+      if (m <= L.N && it.jp >= (a.jstart[L.m_base + m] & ~127)) {
         const T* sS = ws + (2LL * m) * plane + (long long)it.jp * Cp + 2 * it.fb * FB;
         load_run<T, FB>(sS, stS[s]);
         load_run<T, FB>(sS + plane, stA[s]);
@@ -1011,7 +1013,9 @@ __global__ __launch_bounds__(NT) void k_zonal_synthesis_p3(const FftArgs a) {
 #pragma unroll
     for (int s = 0; s < MS; ++s) {
       const int m = threadIdx.x + s * NT;
-      if (m <= N) {
+      // rows below the first 128-latitude tile the Legendre synthesis
+      // computes for this m (reduced transform) are zero
+      if (m <= N && jp >= (a.jstart[L.m_base + m] & ~127)) {
         const T* sS = ws + (2LL * m) * plane + (long long)jp * Cp + 2 * fb * FB;
         load_run<T, FB>(sS, stS[s]);
         load_run<T, FB>(sS + plane, stA[s]);

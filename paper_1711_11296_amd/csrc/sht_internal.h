@@ -63,6 +63,10 @@ struct FftArgs {
   double mscale;
   int tw_lds;        // element offset of the LDS twiddle table (set at launch)
   int fb;            // fields per work item (zonal_fields_per_block)
+  // per (level, m): first latitude of the Legendre sums (reduced transform;
+  // else 0); the synthesis leaves whole 128-latitude tiles below it out of
+  // the workspace, and the zonal synthesis reads them as zero
+  const int* jstart;
 };
 
 // One work tile of a Legendre kernel; level < 0 marks an idle slot.
@@ -77,6 +81,7 @@ struct GemmArgs {
   const Tile* tiles;           // one per workgroup
   const long long* tab_off;    // per (level, m): element offset of the table block
   const void* table;           // P~ table copy (FP64 in the FP64 form, else FP32)
+  const int* jstart;           // per (level, m): first latitude of the sums (reduced transform; else 0)
   const void* spec_in;         // synthesis: spectra
   void* spec_out;              // analysis: spectra
   void* ws;                    // workspace

@@ -219,17 +219,20 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     lds_barrier();
   };
 
-  dma(0, 0);
-  gload_b(0);
+  // reduced transform: the blocks before kb0 hold only latitudes where
+  // every |P~_n^m| < 1e-16 (kb0 = 0 otherwise)
+  const int kb0 = min(g.jstart[L.m_base + m] / KB, nkb - 1);
+  dma(kb0, 0);
+  gload_b(kb0);
   asm volatile("" ::: "memory");
-  gload_a(0, an[0]);
-  gload_a(nkb > 1 ? 1 : 0, an[1]);
+  gload_a(kb0, an[0]);
+  gload_a(kb0 + 1 < nkb ? kb0 + 1 : nkb - 1, an[1]);
   lstore(0);
   wait_fills();
 #pragma unroll
   for (int v = 0; v < KQ / E; ++v) ac[v] = an[0][v];
   __syncthreads();
-  for (int kb = 0; kb < nkb; kb += 2) {
+  for (int kb = kb0; kb < nkb; kb += 2) {
     step(std::integral_constant<int, 0>{}, kb);
     if (kb + 1 < nkb) step(std::integral_constant<int, 1>{}, kb + 1);
   }
@@ -434,15 +437,19 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
     lds_barrier();
   };
 
-  gload(0, an[0], rq[0]);
-  gload(nkb > 1 ? 1 : 0, an[1], rq[1]);
-  lstore(0, rq[0], 0);
+  // reduced transform: a tile whose latitudes all lie below the first one
+  // kept for this m writes zeros (uniform across the workgroup)
+  if (jt * 128 + 128 > g.jstart[L.m_base + m]) {
+    gload(0, an[0], rq[0]);
+    gload(nkb > 1 ? 1 : 0, an[1], rq[1]);
+    lstore(0, rq[0], 0);
 #pragma unroll
-  for (int v = 0; v < S::NV; ++v) ac[v] = an[0][v];
-  __syncthreads();
-  for (int kb = 0; kb < nkb; kb += 2) {
-    step(std::integral_constant<int, 0>{}, kb);
-    if (kb + 1 < nkb) step(std::integral_constant<int, 1>{}, kb + 1);
+    for (int v = 0; v < S::NV; ++v) ac[v] = an[0][v];
+    __syncthreads();
+    for (int kb = 0; kb < nkb; kb += 2) {
+      step(std::integral_constant<int, 0>{}, kb);
+      if (kb + 1 < nkb) step(std::integral_constant<int, 1>{}, kb + 1);
+    }
   }
 
   if (!active) return;

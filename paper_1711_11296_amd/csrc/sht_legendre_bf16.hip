@@ -273,8 +273,11 @@ __global__ __launch_bounds__(X6Analysis<NCB>::NT) __attribute__((amdgpu_waves_pe
     lds_barrier();
   };
   // pairs of blocks with a branch-free body, then an odd last block
+  // reduced transform: the blocks before kb0 hold only latitudes where
+  // every |P~_n^m| < 1e-16 (kb0 = 0 otherwise)
+  const int kb0 = min(g.jstart[L.m_base + m] / KB, nkb - 1);
   auto run = [&](auto act) __attribute__((always_inline)) {
-    int kb = 0;
+    int kb = kb0;
     for (; kb + 1 < nkb; kb += 2) {
       step(act, std::integral_constant<int, 0>{}, kb);
       step(act, std::integral_constant<int, 1>{}, kb + 1);
@@ -282,8 +285,8 @@ __global__ __launch_bounds__(X6Analysis<NCB>::NT) __attribute__((amdgpu_waves_pe
     if (kb < nkb) step(act, std::integral_constant<int, 0>{}, kb);
   };
 
-  gload(0, 0);
-  gload(nkb > 1 ? 1 : 0, 1);
+  gload(kb0, 0);
+  gload(kb0 + 1 < nkb ? kb0 + 1 : nkb - 1, 1);
   split_a(0);
   split_b(0, 0);
   __syncthreads();
@@ -501,15 +504,19 @@ __global__ __launch_bounds__(X6Synthesis<NCB>::NT) __attribute__((amdgpu_waves_p
     if (kb < nkb) step(act, std::integral_constant<int, 0>{}, kb);
   };
 
-  gload(0, 0);
-  gload(nkb > 1 ? 1 : 0, 1);
-  split_a(0);
-  split_b(0, 0, 0);
-  __syncthreads();
-  if (active)
-    run(std::true_type{});
-  else
-    run(std::false_type{});
+  // reduced transform: a tile whose latitudes all lie below the first one
+  // kept for this m writes zeros (uniform across the workgroup)
+  if (jt * 128 + 128 > g.jstart[L.m_base + m]) {
+    gload(0, 0);
+    gload(nkb > 1 ? 1 : 0, 1);
+    split_a(0);
+    split_b(0, 0, 0);
+    __syncthreads();
+    if (active)
+      run(std::true_type{});
+    else
+      run(std::false_type{});
+  }
 
   if (!active) return;
   const long long plane = (long long)L.Kp * Cp;

@@ -31,11 +31,13 @@ class Plan:
 
     levels: one (N, J, I, nfields) tuple, or a list of them for a batched
     hierarchy run in one launch per stage.  grid: "cc_poles", "fejer2" or "fejer1";
-    form: "fp64", "fp32" or "bf16x6".
+    form: "fp64", "fp32" or "bf16x6".  reduced: leave out, per m, the polar
+    latitudes where every |P~_n^m| < 1e-16 (the reduced transform of
+    Sec. 4.1; see sht_options.reduced).
     """
 
     def __init__(self, N=None, J=None, I=None, nfields=None, *, levels=None, grid="cc_poles",
-                 form="fp64", autotune=False, use_graph=False):
+                 form="fp64", autotune=False, use_graph=False, reduced=False):
         import torch
         lib = _lib.load()
         if levels is None:
@@ -44,7 +46,7 @@ class Plan:
         self.grid_kind = grid
         self.form = form
         self.dtype = torch.float64 if form == "fp64" else torch.float32
-        opts = _lib.Options(_lib.GRID[grid], _lib.FORM[form], int(autotune), int(use_graph))
+        opts = _lib.Options(_lib.GRID[grid], _lib.FORM[form], int(autotune), int(use_graph), int(reduced))
         h = ctypes.c_void_p()
         n = len(self.levels)
         arr = lambda k: (ctypes.c_int * n)(*[lv[k] for lv in self.levels])  # noqa: E731
@@ -55,6 +57,7 @@ class Plan:
         self.grid_elems = self._query(_lib.Q_GRID_ELEMS, ctypes.c_size_t)
         self.spec_elems = self._query(_lib.Q_SPEC_ELEMS, ctypes.c_size_t)
         self.legendre_flops = self._query(_lib.Q_LEGENDRE_FLOPS, ctypes.c_double)
+        self.legendre_flops_kept = self._query(_lib.Q_LEGENDRE_FLOPS_KEPT, ctypes.c_double)
         self.exact = bool(self._query(_lib.Q_EXACT, ctypes.c_int))
         self.workspace_bytes = self._query(_lib.Q_WORKSPACE_BYTES, ctypes.c_size_t)
         self.table_bytes = self._query(_lib.Q_TABLE_BYTES, ctypes.c_size_t)

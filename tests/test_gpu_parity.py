@@ -266,3 +266,42 @@ def test_wide_items_first_launch_in_fresh_process(form):
     assert r.returncode == 0, r.stderr[-2000:]
     err = float([ln for ln in r.stdout.splitlines() if ln.startswith("ERR")][-1].split()[1])
     assert err < 10 * TOL[form], err
+
+
+def _kept_flops_from_oracle(N, J, F, kind, kb):
+    """Legendre flops left after dropping, per m, the whole kb-latitude
+    blocks at the pole where every |P~_n^m| < 1e-16 (scan of the oracle's P~)."""
+    _, mu, s = O.nodes(J, kind)
+    Jh = (J + 1) // 2
+    kept = 0.0
+    for m in range(N + 1):
+        big = (np.abs(O.alf_m(N, m, mu[:Jh], s[:Jh])) >= 1e-16).any(axis=0)
+        j0 = int(np.argmax(big)) if big.any() else Jh
+        kept += 4.0 * (N - m + 1) * F * (Jh - j0 // kb * kb)
+    return kept
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_reduced_transform(form):
+    """Reduced transform (Sec. 4.1): for each m the polar latitudes where
+    every |P~_n^m| < 1e-16 are left out of both sums.  The work left out
+    matches a scan of the oracle's P~, and both directions still match the
+    full transform of the oracle to the form's tolerance."""
+    from paper_1711_11296_amd import Plan
+    N, J, I, F, kind = 479, 959, 1440, 6, "fejer2"
+    p = Plan(N, J, I, F, grid=kind, form=form, reduced=True)
+    kept = _kept_flops_from_oracle(N, J, F, kind, 16 if form == "fp64" else 32)
+    assert abs(p.legendre_flops_kept - kept) <= 1e-3 * kept
+    assert p.legendre_flops_kept < 0.9 * p.legendre_flops
+    a = inputs.random_spectra(N, F, seed=5, profile="k3")
+    a_d = _to_dev(a, form)
+    a_in = _host(a_d)
+    g_d = p.inverse(a_d)
+    g_in = _host(g_d)
+    assert rel(g_in, O.inverse(a_in, N, J, I, kind)) < TOL[form], "inverse"
+    s_d = p.forward(g_d)
+    assert rel(_host(s_d), O.forward(g_in, N, kind)) < TOL[form], "forward"
+    p.close()
+    full = Plan(N, J, I, F, grid=kind, form=form)
+    assert full.legendre_flops_kept == full.legendre_flops
+    full.close()
