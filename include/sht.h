@@ -207,6 +207,30 @@ int sht_plan_destroy(sht_plan_t plan);
 const char* sht_last_error(void);
 
 /*
+ * Transfers for multigrid cycles (App. C: restriction and prolongation
+ * between a finer and a coarser level), enqueued on `stream`; no plan
+ * needed.  dbl nonzero: double elements, else float.  Buffers are device
+ * memory, 16-byte aligned, caller-owned, and must not overlap.
+ *
+ * sht_spec_retruncate: spectral restriction (N_out < N_in) or prolongation
+ *   (N_out > N_in) of nfields spectra in the layout of sht_forward:
+ *   out(m, n) = in(m, n) for n <= min(N_in, N_out), 0 for n > N_in.
+ * sht_grid_inject: grid restriction by injection (Sec. 3.2, App. C): the
+ *   coarse grid's rows and columns are a subset of the fine grid's.
+ *   SHT_GRID_CC_POLES: (J_fine-1) = s (J_coarse-1), coarse row j = fine row
+ *   s j; SHT_GRID_FEJER2: (J_fine+1) = s (J_coarse+1), coarse row j = fine
+ *   row s (j+1) - 1; columns: I_fine = t I_coarse, coarse column i = fine
+ *   column t i.  SHT_GRID_FEJER1 does not nest (SHT_EINVAL).
+ * Both return SHT_EINVAL on bad sizes or pointers, SHT_EHIP on a launch
+ * failure.
+ */
+int sht_spec_retruncate(int N_in, int N_out, int nfields, int dbl,
+                        const void* spec_in, void* spec_out, void* stream);
+int sht_grid_inject(int J_fine, int I_fine, int J_coarse, int I_coarse,
+                    int nfields, int grid, int dbl, const void* fine,
+                    void* coarse, void* stream);
+
+/*
  * Host-only planning (no GPU needed): nodes and weights of a grid, and the
  * FP64 table of P~_n^m for the northern rows, as sht_plan_tables.  Returns
  * SHT_EINVAL on bad arguments.

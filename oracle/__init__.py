@@ -7,4 +7,4 @@ from .sht_oracle import *  # noqa: F401,F403
 from .sht_oracle import (GRID_KINDS, ncoef, spec_index, nodes, weights, alf_m,
                          zonal_analysis, zonal_synthesis, forward, inverse,
                          forward_adjoint, inverse_adjoint, forward_sample,
-                         inverse_sample_row, orthonormality_errors)
+                         inverse_sample_row, orthonormality_errors, retruncate, inject)

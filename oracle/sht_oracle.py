@@ -399,3 +399,46 @@ def orthonormality_errors(N, J, kind):
         off = np.abs(G - np.diag(np.diag(G)))
         eo[m, m:] = off.max(axis=1) if G.shape[0] > 1 else 0.0
     return en, eo
+
+
+# --------------------------------------------------------------------------
+# transfers between levels (App. C building blocks)
+# --------------------------------------------------------------------------
+
+def retruncate(spec, N_in, N_out):
+    """Spectral restriction / prolongation between truncations: coefficient
+    (m, n) of the output is that of the input for n <= min(N_in, N_out) and
+    zero for n > N_in.  spec: [F, ncoef(N_in), 2] -> [F, ncoef(N_out), 2]."""
+    spec = np.asarray(spec, dtype=np.float64)
+    F = spec.shape[0]
+    out = np.zeros((F, ncoef(N_out), 2))
+    for m in range(min(N_in, N_out) + 1):
+        for n in range(m, min(N_in, N_out) + 1):
+            out[:, spec_index(N_out, m, n)] = spec[:, spec_index(N_in, m, n)]
+    return out
+
+
+def inject(grid, Jc, Ic, kind):
+    """Grid restriction by injection (Sec. 3.2): the coarse grid's nodes are
+    a subset of the fine grid's.  "cc_poles": rows s*j with
+    s = (Jf-1)/(Jc-1); "fejer2": rows s*(j+1)-1 with s = (Jf+1)/(Jc+1);
+    columns t*i with t = If/Ic."""
+    grid = np.asarray(grid, dtype=np.float64)
+    _, Jf, If = grid.shape
+    if If % Ic:
+        raise ValueError("I_fine must be a multiple of I_coarse")
+    t = If // Ic
+    if kind == "cc_poles":
+        if (Jf - 1) % (Jc - 1):
+            raise ValueError("rows do not nest")
+        s = (Jf - 1) // (Jc - 1)
+        rows = [s * j for j in range(Jc)]
+    elif kind == "fejer2":
+        if (Jf + 1) % (Jc + 1):
+            raise ValueError("rows do not nest")
+        s = (Jf + 1) // (Jc + 1)
+        rows = [s * (j + 1) - 1 for j in range(Jc)]
+    else:
+        raise ValueError("grid kind %r does not nest" % (kind,))
+    return grid[:, rows, :][:, :, ::t].copy()
+

@@ -17,7 +17,7 @@ BUILD = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-HIP_SOURCES = ["sht_fft.hip", "sht_legendre.hip", "sht_legendre_bf16.hip", "sht_api.hip"]
+HIP_SOURCES = ["sht_fft.hip", "sht_legendre.hip", "sht_legendre_bf16.hip", "sht_transfer.hip", "sht_api.hip"]
 CXX_SOURCES = ["sht_host.cpp"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-I" + CSRC, "-I" + os.path.join(os.path.dirname(HERE), "include")]

@@ -23,7 +23,7 @@ Q_GRID_OFFSET, Q_SPEC_OFFSET = 100, 200
 EXPORTS = ["sht_plan", "sht_plan_ex", "sht_plan_multi", "sht_forward", "sht_inverse",
            "sht_forward_adjoint", "sht_inverse_adjoint", "sht_plan_query",
            "sht_plan_tables", "sht_plan_destroy", "sht_last_error", "sht_host_tables",
-           "sht_plan_profile", "sht_plan_profile_read"]
+           "sht_plan_profile", "sht_plan_profile_read", "sht_spec_retruncate", "sht_grid_inject"]
 
 
 class SHTError(RuntimeError):
@@ -77,6 +77,10 @@ def load(require_torch=True):
     lib.sht_plan_profile.argtypes = [vp, c_int]
     lib.sht_plan_profile_read.restype = c_int
     lib.sht_plan_profile_read.argtypes = [vp, dp, ip]
+    lib.sht_spec_retruncate.restype = c_int
+    lib.sht_spec_retruncate.argtypes = [c_int, c_int, c_int, c_int, vp, vp, vp]
+    lib.sht_grid_inject.restype = c_int
+    lib.sht_grid_inject.argtypes = [c_int, c_int, c_int, c_int, c_int, c_int, c_int, vp, vp, vp]
     lib.sht_host_tables.restype = c_int
     lib.sht_host_tables.argtypes = [c_int, c_int, c_int, dp, dp, dp]
     _lib = lib

@@ -848,6 +848,46 @@ extern "C" {
 
 const char* sht_last_error(void) { return g_err.c_str(); }
 
+int sht_spec_retruncate(int N_in, int N_out, int nfields, int dbl, const void* spec_in, void* spec_out,
+                        void* stream) {
+  if (N_in < 0 || N_out < 0 || nfields < 1) return fail(SHT_EINVAL, "need N_in, N_out >= 0 and nfields >= 1");
+  if (N_out > 65534 || nfields > 65535) return fail(SHT_EINVAL, "N_out or nfields too large");
+  int rc = check_ptr(spec_in, "spec_in");
+  if (!rc) rc = check_ptr(spec_out, "spec_out");
+  if (rc) return rc;
+  if (spec_in == spec_out) return fail(SHT_EINVAL, "spec_in and spec_out must not overlap");
+  return hip_check((hipError_t)launch_retruncate(N_in, N_out, nfields, dbl != 0, spec_in, spec_out, stream),
+                   "retruncate launch");
+}
+
+int sht_grid_inject(int J_fine, int I_fine, int J_coarse, int I_coarse, int nfields, int grid, int dbl,
+                    const void* fine, void* coarse, void* stream) {
+  if (nfields < 1 || nfields > 65535 || I_coarse < 1 || I_fine < I_coarse || I_fine % I_coarse)
+    return fail(SHT_EINVAL, "need nfields >= 1 and I_fine a multiple of I_coarse");
+  int rs = 0, r0 = 0;
+  if (grid == SHT_GRID_CC_POLES) {
+    if (J_coarse < 2 || J_fine < J_coarse || (J_fine - 1) % (J_coarse - 1))
+      return fail(SHT_EINVAL, "CC grid with poles: need J_fine - 1 a multiple of J_coarse - 1 (J_coarse >= 2)");
+    rs = (J_fine - 1) / (J_coarse - 1);
+    r0 = 0;
+  } else if (grid == SHT_GRID_FEJER2) {
+    if (J_coarse < 1 || J_fine < J_coarse || (J_fine + 1) % (J_coarse + 1))
+      return fail(SHT_EINVAL, "paper's grid: need J_fine + 1 a multiple of J_coarse + 1");
+    rs = (J_fine + 1) / (J_coarse + 1);
+    r0 = rs - 1;
+  } else {
+    return fail(SHT_EINVAL, "grid kind does not nest");
+  }
+  if (J_coarse > 65535) return fail(SHT_EINVAL, "J_coarse too large");
+  int rc = check_ptr(fine, "fine");
+  if (!rc) rc = check_ptr(coarse, "coarse");
+  if (rc) return rc;
+  if (fine == coarse) return fail(SHT_EINVAL, "fine and coarse must not overlap");
+  return hip_check((hipError_t)launch_inject(J_fine, I_fine, J_coarse, I_coarse, nfields, rs, r0, I_fine / I_coarse,
+                                             dbl != 0, fine, coarse, stream),
+                   "inject launch");
+}
+
 sht_plan_t sht_plan(int N, int J, int I, int nfields) {
   sht_plan_t p = nullptr;
   if (build_plan(1, &N, &J, &I, &nfields, nullptr, &p) != SHT_OK) return nullptr;

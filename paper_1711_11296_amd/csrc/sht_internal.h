@@ -97,6 +97,10 @@ struct GemmArgs {
 int zonal_fields_per_block(int form, int nlev, int N, int J, int I, int F);
 int launch_zonal(int form, bool analysis, const FftArgs& a, int maxN, void* stream);
 int launch_legendre(int form, bool analysis, const GemmArgs& g, int ncb, void* stream);
+// Transfers between truncations and nested grids (sht_transfer.hip).
+int launch_retruncate(int Nin, int Nout, int F, bool dbl, const void* in, void* out, void* stream);
+int launch_inject(int Jf, int If, int Jc, int Ic, int F, int rs, int r0, int cs, bool dbl, const void* fine,
+                  void* coarse, void* stream);
 // Widest column blocking (16-column units) a Legendre kernel of a form takes.
 int max_ncb(int form, bool analysis);
 

@@ -123,3 +123,27 @@ def test_host_table_no_underflow_at_high_order():
     j = (J - 1) // 2
     assert mu[j] == 0.0
     assert np.all(alf[O.spec_index(N, m, m):O.spec_index(N, m, N) + 1, j][1::2] == 0.0)
+
+
+def test_transfer_arguments_are_rejected_without_a_gpu():
+    """Re-truncation and injection check their arguments before any GPU
+    call: bad sizes, grids that do not nest, NULL or misaligned pointers.
+    (Every call here must fail validation: none may reach a launch, since
+    the buffers are host memory.)"""
+    lib = _lib.load(require_torch=False)
+    buf = ctypes.create_string_buffer(4096 + 16)
+    p = ctypes.c_void_p((ctypes.addressof(buf) + 15) // 16 * 16)
+    q = ctypes.c_void_p(p.value + 2048)
+    E = _lib.SHT_EINVAL
+    assert lib.sht_spec_retruncate(-1, 3, 1, 0, p, q, None) == E
+    assert lib.sht_spec_retruncate(3, 3, 0, 0, p, q, None) == E
+    assert lib.sht_spec_retruncate(3, 3, 1, 0, None, q, None) == E
+    assert lib.sht_spec_retruncate(3, 3, 1, 0, ctypes.c_void_p(p.value + 4), q, None) == E
+    assert lib.sht_spec_retruncate(3, 3, 1, 0, p, p, None) == E
+    assert lib.sht_grid_inject(33, 48, 16, 24, 1, 0, 0, p, q, None) == E    # 32 % 15
+    assert lib.sht_grid_inject(34, 48, 17, 24, 1, 1, 0, p, q, None) == E    # 35 % 18
+    assert lib.sht_grid_inject(33, 48, 17, 25, 1, 0, 0, p, q, None) == E    # 48 % 25
+    assert lib.sht_grid_inject(33, 48, 17, 24, 1, 2, 0, p, q, None) == E    # shifted grid
+    assert lib.sht_grid_inject(33, 48, 17, 24, 0, 0, 0, p, q, None) == E    # no fields
+    assert lib.sht_grid_inject(33, 48, 17, 24, 1, 0, 0, None, q, None) == E
+

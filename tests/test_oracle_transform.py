@@ -338,3 +338,46 @@ def test_sampled_forms_match_full(kind):
     x = O.inverse(s, N, J, I, kind)
     for j in (0, 7, 21, 42):
         assert np.abs(O.inverse_sample_row(s[1], N, J, I, kind, j) - x[1, j]).max() < 1e-14
+
+
+# --------------------------------------------------------------------------
+# transfers between levels (App. C): re-truncation and injection
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("kind,Jc,Jf,Ic,If", [("cc_poles", 17, 33, 24, 48), ("fejer2", 17, 35, 24, 72),
+                                              ("fejer2", 17, 53, 25, 50)])
+def test_two_grid_transfers(kind, Jc, Jf, Ic, If):
+    """Injection then coarse analysis, and fine analysis then restriction,
+    both return the coarse spectrum of a field band-limited at the coarse
+    truncation (Sec. 3.2, App. C); prolongation then restriction is the
+    identity and prolongation pads with zeros."""
+    Nc = 8
+    Nf = (Jf - 1) // 2
+    a = inputs.random_spectra(Nc, 2, seed=21, profile="k3")
+    g_f = O.inverse(a, Nc, Jf, If, kind)
+    g_c = O.inject(g_f, Jc, Ic, kind)
+    assert g_c.shape == (2, Jc, Ic)
+    assert np.abs(O.forward(g_c, Nc, kind) - a).max() < 1e-13 * np.abs(a).max()
+    b = O.retruncate(O.forward(g_f, Nf, kind), Nf, Nc)
+    assert np.abs(b - a).max() < 1e-13 * np.abs(a).max()
+    up = O.retruncate(a, Nc, Nf)
+    assert np.array_equal(O.retruncate(up, Nf, Nc), a)
+    assert np.array_equal(O.retruncate(a, Nc, Nc), a)
+    ordf = inputs.orders(Nf)
+    deg_f = inputs.degrees(Nf)
+    assert np.all(up[:, deg_f > Nc] == 0)
+    assert ordf.size == up.shape[1]
+
+
+@pytest.mark.parametrize("kind,Jc,Jf", [("cc_poles", 9, 33), ("fejer2", 15, 31), ("fejer2", 9, 29)])
+def test_injection_rows_are_the_nested_nodes(kind, Jc, Jf):
+    """Injected rows carry exactly the coarse grid's nodes: a grid holding
+    mu_j of the fine grid injects to mu_j of the coarse one, bit for bit."""
+    _, muf, _ = O.nodes(Jf, kind)
+    _, muc, _ = O.nodes(Jc, kind)
+    g = np.repeat(muf[None, :, None], 6, axis=2)
+    assert np.array_equal(O.inject(g, Jc, 3, kind)[0, :, 0], muc)
+    with pytest.raises(ValueError):
+        O.inject(g, Jc + 1, 3, kind)
+    with pytest.raises(ValueError):
+        O.inject(g, Jc, 3, "fejer1")
