@@ -67,7 +67,10 @@ typedef struct sht_plan_s* sht_plan_t;
 typedef enum {
   SHT_GRID_CC_POLES = 0,
   SHT_GRID_FEJER2 = 1,
-  SHT_GRID_FEJER1 = 2
+  SHT_GRID_FEJER1 = 2,
+  SHT_GRID_GAUSS = 3   /* Gaussian grid (Sec. 2): the paper's comparison
+                          grid, for reference transforms (exact when
+                          J >= N+1) */
 } sht_grid_t;
 
 typedef enum {
@@ -128,7 +131,7 @@ enum {
  * sht_plan: plan for one level with the defaults (SHT_GRID_CC_POLES,
  * SHT_FORM_FP64) on the current HIP device.  Returns NULL on failure.
  *   N >= 0 truncation wavenumber; J latitudes (>= 2 on CC_POLES, >= 1 on
- *   FEJER2 and FEJER1); I >= 2N+1 longitudes (radix 2, 3, 5 only, I <= 4096);
+ *   FEJER2, FEJER1 and GAUSS); I >= 2N+1 longitudes (radix 2, 3, 5 only, I <= 4096);
  *   nfields >= 1 independent fields.  J < 2N+1 is accepted (the quadrature
  *   then aliases, Sec. 3.1; SHT_Q_EXACT reports 0).
  * Plan time builds the nodes and weights (Sec. 3.1, eq. cc-points,
@@ -229,6 +232,14 @@ int sht_spec_retruncate(int N_in, int N_out, int nfields, int dbl,
 int sht_grid_inject(int J_fine, int I_fine, int J_coarse, int I_coarse,
                     int nfields, int grid, int dbl, const void* fine,
                     void* coarse, void* stream);
+
+/*
+ * Pointwise product of n grid values, out[i] = a[i] * b[i] (the quadratic
+ * and cubic terms whose aliasing Sec. 4.2 measures); out may be a or b.
+ * Same conventions as the transfers above.
+ */
+int sht_grid_product(long long n, int dbl, const void* a, const void* b,
+                     void* out, void* stream);
 
 /*
  * Host-only planning (no GPU needed): nodes and weights of a grid, and the

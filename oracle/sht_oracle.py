@@ -18,7 +18,9 @@ Conventions (the readings of the paper used throughout):
     j = 1..J (Sec. 3.1, eq. cc-points); "cc_poles" is the classical
     Clenshaw-Curtis grid with the poles, theta_j = j*pi/(J-1), j = 0..J-1;
     "fejer1" is the shifted grid of Sec. 3.3, theta_j = (j - 1/2)*pi/J,
-    j = 1..J (eq. fejer1-points).  Row 0 is the one nearest the north pole.
+    j = 1..J (eq. fejer1-points); "gauss" is the Gaussian grid of Sec. 2
+    (not in GRID_KINDS: a reference for the aliasing workload of Sec. 4.2).
+    Row 0 is the one nearest the north pole.
   * P~_n^m is normalised so that its square integrates to 1 over mu in
     [-1, 1] (Sec. 2, eq. pnm-ortho), with no Condon-Shortley phase.
   * spectra are stored for m >= 0 only, as float pairs (re, im), m-major
@@ -81,6 +83,53 @@ def _node_fraction(J, kind, j):
     raise ValueError("unknown grid kind %r" % (kind,))
 
 
+_GAUSS_CACHE = {}
+
+
+def _gauss_rule(J):
+    """Gauss-Legendre nodes (descending) and weights of the J-point rule.
+
+    The roots of P_J start from numpy's Gauss-Legendre routine and are
+    refined by Newton's method on the three-term recurrence
+    k P_k = (2k-1) x P_{k-1} - (k-1) P_{k-2} in 40-digit decimal arithmetic;
+    the weight is w = 2 (1 - x^2) / (J P_{J-1}(x))^2.  numpy's own weights
+    lose about J * 1e-15 relative accuracy near the poles, too much for a
+    1e-12 reference.  Nodes are mirrored so that mu_{J-1-j} = -mu_j.
+    """
+    if J in _GAUSS_CACHE:
+        return _GAUSS_CACHE[J]
+    import decimal
+    ctx = decimal.Context(prec=40)
+    D = decimal.Decimal
+    x0, _ = np.polynomial.legendre.leggauss(J)
+    mu = np.empty(J)
+    w = np.empty(J)
+    for j in range((J + 1) // 2):
+        x = D(float(-x0[j]))                 # north-first: mu_j = -x_j > 0
+        for _ in range(4):
+            p0, p1 = D(1), x
+            for k in range(2, J + 1):
+                p0, p1 = p1, ctx.divide(ctx.subtract(ctx.multiply(ctx.multiply(D(2 * k - 1), x), p1),
+                                                     ctx.multiply(D(k - 1), p0)), D(k))
+            dp = ctx.divide(ctx.multiply(D(J), ctx.subtract(p0, ctx.multiply(x, p1))),
+                            ctx.subtract(D(1), ctx.multiply(x, x)))
+            x = ctx.subtract(x, ctx.divide(p1, dp))
+        p0, p1 = D(1), x
+        for k in range(2, J + 1):
+            p0, p1 = p1, ctx.divide(ctx.subtract(ctx.multiply(ctx.multiply(D(2 * k - 1), x), p1),
+                                                 ctx.multiply(D(k - 1), p0)), D(k))
+        if J == 1:
+            p0 = D(1)
+        wj = ctx.divide(ctx.multiply(D(2), ctx.subtract(D(1), ctx.multiply(x, x))),
+                        ctx.multiply(ctx.multiply(D(J), p0), ctx.multiply(D(J), p0)))
+        if 2 * j + 1 == J:
+            x = D(0)
+        mu[j], mu[J - 1 - j] = float(x), -float(x)
+        w[j] = w[J - 1 - j] = float(wj)
+    _GAUSS_CACHE[J] = (mu, w)
+    return mu, w
+
+
 def nodes(J, kind):
     """Colatitudes theta_j, mu_j = cos(theta_j) = sin(phi_j) and sin(theta_j).
 
@@ -90,6 +139,11 @@ def nodes(J, kind):
     node gets exactly -mu and nested grids share their common nodes bit for
     bit.
     """
+    if kind == "gauss":
+        # Gaussian grid (Sec. 2, the comparison grid): the roots of P_J,
+        # north first
+        mu, _ = _gauss_rule(J)
+        return np.arccos(mu), mu, np.sqrt((1.0 - mu) * (1.0 + mu))
     theta = np.empty(J)
     mu = np.empty(J)
     sint = np.empty(J)
@@ -119,6 +173,8 @@ def weights(J, kind):
     with c_0 = c_n = 1, c_k = 2 otherwise and b_l = 1 for l = n/2, 2 otherwise
     (the rule the paper cites from Trefethen 2008 and Waldvogel 2006).
     """
+    if kind == "gauss":
+        return _gauss_rule(J)[1].copy()
     w = np.empty(J)
     if kind == "fejer2":
         for j in range(J):

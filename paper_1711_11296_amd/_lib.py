@@ -11,7 +11,7 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsht.so")
 
-GRID = {"cc_poles": 0, "fejer2": 1, "fejer1": 2}
+GRID = {"cc_poles": 0, "fejer2": 1, "fejer1": 2, "gauss": 3}
 FORM = {"fp64": 0, "fp32": 1, "bf16x6": 2}
 
 SHT_OK, SHT_EINVAL, SHT_ENOMEM, SHT_EHIP, SHT_ESTATE = 0, -1, -2, -3, -4
@@ -23,7 +23,8 @@ Q_GRID_OFFSET, Q_SPEC_OFFSET = 100, 200
 EXPORTS = ["sht_plan", "sht_plan_ex", "sht_plan_multi", "sht_forward", "sht_inverse",
            "sht_forward_adjoint", "sht_inverse_adjoint", "sht_plan_query",
            "sht_plan_tables", "sht_plan_destroy", "sht_last_error", "sht_host_tables",
-           "sht_plan_profile", "sht_plan_profile_read", "sht_spec_retruncate", "sht_grid_inject"]
+           "sht_plan_profile", "sht_plan_profile_read", "sht_spec_retruncate", "sht_grid_inject",
+           "sht_grid_product"]
 
 
 class SHTError(RuntimeError):
@@ -79,6 +80,8 @@ def load(require_torch=True):
     lib.sht_plan_profile_read.argtypes = [vp, dp, ip]
     lib.sht_spec_retruncate.restype = c_int
     lib.sht_spec_retruncate.argtypes = [c_int, c_int, c_int, c_int, vp, vp, vp]
+    lib.sht_grid_product.restype = c_int
+    lib.sht_grid_product.argtypes = [ctypes.c_longlong, c_int, vp, vp, vp, vp]
     lib.sht_grid_inject.restype = c_int
     lib.sht_grid_inject.argtypes = [c_int, c_int, c_int, c_int, c_int, c_int, c_int, vp, vp, vp]
     lib.sht_host_tables.restype = c_int

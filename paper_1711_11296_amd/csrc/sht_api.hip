@@ -148,7 +148,9 @@ int check_level_args(int N, int J, int I, int F, int grid) {
   if (F < 1) return fail(SHT_EINVAL, "nfields must be >= 1");
   if (!grid_args_ok(J, grid))
     return fail(SHT_EINVAL, grid == SHT_GRID_CC_POLES ? "J must be >= 2 on the CC grid with poles"
-                                                     : (grid == SHT_GRID_FEJER2 || grid == SHT_GRID_FEJER1 ? "J must be >= 1"
+                                                     : (grid == SHT_GRID_FEJER2 || grid == SHT_GRID_FEJER1 ||
+                                                                grid == SHT_GRID_GAUSS
+                                                            ? "J must be >= 1"
                                                                                 : "unknown grid kind"));
   if (I < 2 * N + 1) return fail(SHT_EINVAL, "I must be >= 2N+1 (no retained wavenumber may alias)");
   if (I > SHT_MAX_I) return fail(SHT_EINVAL, "I exceeds the supported maximum 4096");
@@ -410,7 +412,8 @@ int build_plan(int nlev, const int* Nv, const int* Jv, const int* Iv, const int*
     }
     P->maxN = std::max(P->maxN, L.N);
     P->flops += 2.0 * L.Jh * (double)(L.N + 1) * (L.N + 2) * L.F;
-    if (L.J < 2 * L.N + 1) P->exact = false;
+    // Gauss-Legendre on J nodes is exact to degree 2J-1, the CC rules to J-1
+    if (o.grid == SHT_GRID_GAUSS ? L.J < L.N + 1 : L.J < 2 * L.N + 1) P->exact = false;
   }
   if (item > 0x7fffffff) {
     delete P;
@@ -858,6 +861,15 @@ int sht_spec_retruncate(int N_in, int N_out, int nfields, int dbl, const void* s
   if (spec_in == spec_out) return fail(SHT_EINVAL, "spec_in and spec_out must not overlap");
   return hip_check((hipError_t)launch_retruncate(N_in, N_out, nfields, dbl != 0, spec_in, spec_out, stream),
                    "retruncate launch");
+}
+
+int sht_grid_product(long long n, int dbl, const void* a, const void* b, void* out, void* stream) {
+  if (n < 1) return fail(SHT_EINVAL, "n must be >= 1");
+  int rc = check_ptr(a, "a");
+  if (!rc) rc = check_ptr(b, "b");
+  if (!rc) rc = check_ptr(out, "out");
+  if (rc) return rc;
+  return hip_check((hipError_t)launch_product(n, dbl != 0, a, b, out, stream), "product launch");
 }
 
 int sht_grid_inject(int J_fine, int I_fine, int J_coarse, int I_coarse, int nfields, int grid, int dbl,

@@ -61,11 +61,53 @@ void node_pq(int J, int kind, int j, long* p, long* q) {
 
 bool grid_args_ok(int J, int kind) {
   if (kind == SHT_GRID_CC_POLES) return J >= 2;
-  if (kind == SHT_GRID_FEJER2 || kind == SHT_GRID_FEJER1) return J >= 1;
+  if (kind == SHT_GRID_FEJER2 || kind == SHT_GRID_FEJER1 || kind == SHT_GRID_GAUSS) return J >= 1;
   return false;
 }
 
+namespace {
+// Gauss-Legendre nodes (roots of P_J, descending: north first) and weights
+// 2 / ((1 - x^2) P_J'(x)^2), by Newton's method on the three-term
+// recurrence of P_J in extended precision from Tricomi's estimate
+// cos(pi (j + 3/4) / (J + 1/2)).  The southern half is the exact mirror and
+// the middle node of odd J is 0.
+void gauss_nodes_weights(int J, long double* x, long double* w) {
+  const long double PI = 3.141592653589793238462643383279502884L;
+  for (int j = 0; j < (J + 1) / 2; ++j) {
+    long double z = cosl(PI * ((long double)j + 0.75L) / ((long double)J + 0.5L));
+    long double dp = 1.0L;
+    for (int it = 0; it < 100; ++it) {
+      long double p0 = 1.0L, p1 = z;  // P_0, P_1
+      for (int n = 2; n <= J; ++n) {
+        const long double p2 = ((2.0L * n - 1.0L) * z * p1 - (n - 1.0L) * p0) / (long double)n;
+        p0 = p1;
+        p1 = p2;
+      }
+      if (J == 1) p0 = 1.0L;  // P_{J-1} = P_0
+      // P_J'(z) = J (z P_J - P_{J-1}) / (z^2 - 1)
+      dp = (long double)J * (z * p1 - p0) / (z * z - 1.0L);
+      const long double dz = p1 / dp;
+      z -= dz;
+      if (fabsl(dz) < 1e-19L) break;
+    }
+    if (2 * j + 1 == J) z = 0.0L;
+    x[j] = z;
+    x[J - 1 - j] = -z;
+    w[j] = w[J - 1 - j] = 2.0L / ((1.0L - z * z) * dp * dp);
+  }
+}
+}  // namespace
+
 void grid_nodes(int J, int kind, double* mu, double* sint) {
+  if (kind == SHT_GRID_GAUSS) {
+    std::vector<long double> x(J), w(J);
+    gauss_nodes_weights(J, x.data(), w.data());
+    for (int j = 0; j < J; ++j) {
+      mu[j] = (double)x[j];
+      sint[j] = (double)sqrtl((1.0L - x[j]) * (1.0L + x[j]));
+    }
+    return;
+  }
   for (int j = 0; j < J; ++j) {
     long p, q;
     node_pq(J, kind, j, &p, &q);
@@ -78,6 +120,12 @@ void grid_nodes(int J, int kind, double* mu, double* sint) {
 
 void grid_weights(int J, int kind, double* w) {
   const long double PI = 3.141592653589793238462643383279502884L;
+  if (kind == SHT_GRID_GAUSS) {
+    std::vector<long double> x(J), wl(J);
+    gauss_nodes_weights(J, x.data(), wl.data());
+    for (int j = 0; j < J; ++j) w[j] = (double)wl[j];
+    return;
+  }
   if (kind == SHT_GRID_FEJER2) {
     // w_j = 4 sin(theta_j)/(J+1) * sum_{p odd <= J} sin(p theta_j)/p
     for (int j = 0; j < J; ++j) {

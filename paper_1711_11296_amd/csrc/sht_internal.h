@@ -101,6 +101,7 @@ int launch_legendre(int form, bool analysis, const GemmArgs& g, int ncb, void* s
 int launch_retruncate(int Nin, int Nout, int F, bool dbl, const void* in, void* out, void* stream);
 int launch_inject(int Jf, int If, int Jc, int Ic, int F, int rs, int r0, int cs, bool dbl, const void* fine,
                   void* coarse, void* stream);
+int launch_product(long long n, bool dbl, const void* a, const void* b, void* out, void* stream);
 // Widest column blocking (16-column units) a Legendre kernel of a form takes.
 int max_ncb(int form, bool analysis);
 

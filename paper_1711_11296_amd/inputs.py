@@ -46,7 +46,7 @@ def random_spectra(N, F, seed=0, profile="k3"):
         n = degrees(N).astype(np.float64)
         lo = (n + 1.0) ** (-1.0 / 3.0)
         u = rng.random((F, ncoef(N), 2))
-        s = (lo + u * lo[:, None])
+        s = lo[None, :, None] * (1.0 + u)
     else:
         s = rng.standard_normal((F, ncoef(N), 2)) * sigma(N, profile)[None, :, None]
     s[:, orders(N) == 0, 1] = 0.0

@@ -1,12 +1,13 @@
 """Transfers between truncations and nested grids for multigrid cycles
-(App. C): spectral re-truncation and grid injection, run by libsht.so on the
+(App. C): spectral re-truncation and grid injection; and the pointwise
+product of grids (the nonlinear terms of Sec. 4.2).  Run by libsht.so on the
 tensors' device and current stream."""
 
 import ctypes
 
 from . import _lib
 
-_GRID = {"cc_poles": 0, "fejer2": 1, "fejer1": 2}
+_GRID = {"cc_poles": 0, "fejer2": 1, "fejer1": 2, "gauss": 3}
 
 
 def _dbl(t):
@@ -49,3 +50,19 @@ def grid_inject(grid, J_coarse, I_coarse, kind="cc_poles"):
                                    ctypes.c_void_p(grid.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                                    ctypes.c_void_p(stream)))
     return out
+
+
+def grid_product(a, b):
+    """Pointwise product a * b of two grids of the same shape and dtype."""
+    import torch
+    lib = _lib.load()
+    if a.shape != b.shape or a.dtype != b.dtype or a.device != b.device:
+        raise ValueError("a and b must match in shape, dtype and device")
+    a = a.contiguous()
+    b = b.contiguous()
+    out = torch.empty_like(a)
+    stream = torch.cuda.current_stream(a.device).cuda_stream
+    _lib.check(lib.sht_grid_product(a.numel(), _dbl(a), ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()),
+                                    ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(stream)))
+    return out
+

@@ -224,3 +224,38 @@ def test_sec43_closed_form_error(p):
     # odd J+p is integrated exactly (error 0 up to rounding)
     err2 = _family_integral("U", deg + 1) - np.sum(w * _family_at_nodes("U", deg + 1, theta, mu))
     assert abs(err2) < 1e-12
+
+
+@pytest.mark.parametrize("J", [1, 2, 3, 4, 7, 16, 33])
+def test_gauss_grid_pins(J):
+    """The Gaussian grid (Sec. 2, the comparison grid used as the aliasing
+    reference): nodes are the roots of P_J (north first, mirror-symmetric),
+    the weights integrate mu^d exactly for d <= 2J-1 and, for small J, not
+    for d = 2J (eq. gauss-condition); J = 2 is the two-point rule
+    +-1/sqrt(3)."""
+    theta, mu, s = O.nodes(J, "gauss")
+    w = O.weights(J, "gauss")
+    assert np.all(np.diff(mu) < 0)
+    assert np.allclose(mu, -mu[::-1], rtol=0, atol=1e-15)
+    assert np.allclose(npleg.legval(mu, [0] * J + [1]), 0, atol=1e-13)
+    assert np.allclose(mu ** 2 + s ** 2, 1, rtol=0, atol=1e-15)
+    for d in range(2 * J):
+        exact = 2.0 / (d + 1) if d % 2 == 0 else 0.0
+        assert abs(np.sum(w * mu ** d) - exact) < 1e-13
+    if J <= 7:  # (the error at degree 2J decays factorially with J)
+        assert abs(np.sum(w * mu ** (2 * J)) - 2.0 / (2 * J + 1)) > 1e-12
+    if J == 2:
+        assert np.allclose(mu, [3 ** -0.5, -(3 ** -0.5)], rtol=1e-15)
+        assert np.allclose(w, [1.0, 1.0], rtol=1e-15)
+
+
+@pytest.mark.parametrize("J", [1, 2, 5, 16, 33, 160])
+def test_gauss_host_nodes_match_oracle(J):
+    """The library's Newton-iteration nodes and weights (host code, no GPU)
+    agree with numpy's Gauss-Legendre routine used by the oracle."""
+    from paper_1711_11296_amd import host_tables
+    mu, w, _ = host_tables(3, J, "gauss")
+    _, mo, _ = O.nodes(J, "gauss")
+    assert np.allclose(mu, mo, rtol=0, atol=2e-16)
+    assert np.array_equal(mu, -mu[::-1])
+    assert np.allclose(w, O.weights(J, "gauss"), rtol=1e-13, atol=0)

@@ -156,6 +156,30 @@ def test_aliasing_visible_below_2N_plus_1(kind):
     assert errs[42] > 1e-7 and errs[41] > 1e-7 and errs[33] > 1e-5
 
 
+@pytest.mark.parametrize("kind", KINDS)
+def test_quadratic_term_alias_free_on_quadratic_grid(kind):
+    """Sec. 3.1 (eq. cc-condition) and Sec. 4.2: the degree-N spectrum of
+    the product of two fields band-limited at N needs integrals of degree
+    3N.  Gauss-Legendre with J >= (3N+1)/2 nodes integrates those exactly
+    (textbook exactness 2J-1), so it fixes the alias-free spectrum; the CC
+    grid with J = 3N+1 must reproduce it to rounding, the linear grid
+    J = 2N+1 must not, and neither may a Gaussian grid one node short."""
+    N, I = 21, 64                                 # I >= 3N+1: no zonal aliasing
+    U = inputs.random_spectra(N, 1, seed=1, profile="uniform13")
+    V = inputs.random_spectra(N, 1, seed=2, profile="uniform13")
+
+    def uv(k, J):
+        return O.forward(O.inverse(U, N, J, I, k) * O.inverse(V, N, J, I, k), N, k)
+
+    def rel(x, y):
+        return np.linalg.norm(x - y) / np.linalg.norm(y)
+
+    ref = uv("gauss", (3 * N + 2) // 2)
+    assert rel(uv(kind, 3 * N + 1), ref) < 1e-13
+    assert rel(uv(kind, 2 * N + 1), ref) > 1e-4
+    assert rel(uv("gauss", (3 * N + 2) // 2 - 1), ref) > 1e-4
+
+
 def _poly_field(coef, mu, lam, sint):
     """Polynomial of total degree <= 3 in (x, y, z) on the sphere
     (z = mu = sin(latitude)), evaluated pointwise."""
