@@ -45,6 +45,8 @@ def parse():
                     help="reduced transform (Sec. 4.1): leave out the polar latitudes where every "
                          "|P~_n^m| < 1e-16; reported in config, never the default")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--aliasing", action="store_true",
+                    help="time the Sec. 4.2 aliasing experiment at N_trunc=479 instead (own JSON line)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy a 1 GiB buffer 3 times (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -125,6 +127,49 @@ def time_pairs(plan, g, steps, warmup, torch):
     return (t1 - t0), stages, s, g2
 
 
+def bench_aliasing(args, torch):
+    """One step = the GPU work of the Sec. 4.2 experiment: UV and UVW of
+    three random fields band-limited at 479 on the Tl1439 Gaussian reference
+    grid, the Tl479 Gaussian linear grid and the Tc479 CC cubic grid (three
+    syntheses, two products and one three-field analysis per grid, FP64).
+    Plans and their tables are built before the timed region."""
+    from paper_1711_11296_amd import aliasing, inputs
+    torch.cuda.set_device(0)
+    Nt = 479
+    U, V, W = [torch.from_numpy(inputs.random_spectra(Nt, 1, seed=k, profile="uniform13")).to("cuda:0")
+               for k in range(3)]
+    terms = {k: aliasing.NonlinearTerms(*v) for k, v in aliasing.grids(Nt).items()}
+    ev = {k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for k in terms}
+    for _ in range(args.warmup):
+        for t in terms.values():
+            t(U, V, W)
+    torch.cuda.synchronize()
+    ms = {}
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        for k, t in terms.items():
+            ev[k][0].record()
+            t(U, V, W)
+            ev[k][1].record()
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    for k in terms:
+        ms[k] = ev[k][0].elapsed_time(ev[k][1])
+    p = terms["reference"].plan
+    out = {"metric": "aliasing-experiment runs/s", "value": args.steps / secs, "unit": "runs/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": secs / args.steps * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic: U, V, W with Re, Im ~ U[(n+1)^-1/3, 2 (n+1)^-1/3], n <= 479",
+           "config": {"workload": "Sec. 4.2 aliasing experiment, N_trunc=479: Tl1439 Gaussian reference, "
+                                  "Tl479 Gaussian linear, Tc479 CC cubic (fejer2), FP64",
+                      "grids": {k: list(v) for k, v in aliasing.grids(Nt).items()}},
+           "last_step_ms_per_grid": ms,
+           "reference_legendre_flops_per_direction": p.legendre_flops}
+    print(json.dumps(out), flush=True)
+    for t in terms.values():
+        t.close()
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -136,6 +181,9 @@ def main():
 
     if args.copy_probe:
         copy_probe(torch)
+        return
+    if args.aliasing:
+        bench_aliasing(args, torch)
         return
     from paper_1711_11296_amd import Plan, inputs
 

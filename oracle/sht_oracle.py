@@ -87,14 +87,18 @@ _GAUSS_CACHE = {}
 
 
 def _gauss_rule(J):
-    """Gauss-Legendre nodes (descending) and weights of the J-point rule.
+    """Gauss-Legendre nodes mu_j (descending), weights and sin(theta_j) of
+    the J-point rule.
 
     The roots of P_J start from numpy's Gauss-Legendre routine and are
     refined by Newton's method on the three-term recurrence
     k P_k = (2k-1) x P_{k-1} - (k-1) P_{k-2} in 40-digit decimal arithmetic;
     the weight is w = 2 (1 - x^2) / (J P_{J-1}(x))^2.  numpy's own weights
     lose about J * 1e-15 relative accuracy near the poles, too much for a
-    1e-12 reference.  Nodes are mirrored so that mu_{J-1-j} = -mu_j.
+    1e-12 reference.  sin(theta_j) = sqrt(1 - x^2) is taken from the refined
+    root too: near the poles, sqrt((1 - mu)(1 + mu)) of the rounded mu would
+    be some 1e-10 off the node's own sine.  Nodes are mirrored so that
+    mu_{J-1-j} = -mu_j.
     """
     if J in _GAUSS_CACHE:
         return _GAUSS_CACHE[J]
@@ -104,6 +108,7 @@ def _gauss_rule(J):
     x0, _ = np.polynomial.legendre.leggauss(J)
     mu = np.empty(J)
     w = np.empty(J)
+    sint = np.empty(J)
     for j in range((J + 1) // 2):
         x = D(float(-x0[j]))                 # north-first: mu_j = -x_j > 0
         for _ in range(4):
@@ -126,8 +131,9 @@ def _gauss_rule(J):
             x = D(0)
         mu[j], mu[J - 1 - j] = float(x), -float(x)
         w[j] = w[J - 1 - j] = float(wj)
-    _GAUSS_CACHE[J] = (mu, w)
-    return mu, w
+        sint[j] = sint[J - 1 - j] = float(ctx.sqrt(ctx.subtract(D(1), ctx.multiply(x, x))))
+    _GAUSS_CACHE[J] = (mu, w, sint)
+    return mu, w, sint
 
 
 def nodes(J, kind):
@@ -142,8 +148,8 @@ def nodes(J, kind):
     if kind == "gauss":
         # Gaussian grid (Sec. 2, the comparison grid): the roots of P_J,
         # north first
-        mu, _ = _gauss_rule(J)
-        return np.arccos(mu), mu, np.sqrt((1.0 - mu) * (1.0 + mu))
+        mu, _, sint = _gauss_rule(J)
+        return np.arctan2(sint, mu), mu, sint
     theta = np.empty(J)
     mu = np.empty(J)
     sint = np.empty(J)

@@ -67,15 +67,20 @@ bool grid_args_ok(int J, int kind) {
 
 namespace {
 // Gauss-Legendre nodes (roots of P_J, descending: north first) and weights
-// 2 / ((1 - x^2) P_J'(x)^2), by Newton's method on the three-term
-// recurrence of P_J in extended precision from Tricomi's estimate
-// cos(pi (j + 3/4) / (J + 1/2)).  The southern half is the exact mirror and
-// the middle node of odd J is 0.
-void gauss_nodes_weights(int J, long double* x, long double* w) {
+// 2 / (sin^2(theta) P_J'(x)^2), by Newton's method in the colatitude theta
+// on the three-term recurrence of P_J in extended precision, from Tricomi's
+// estimate theta = pi (j + 3/4) / (J + 1/2).  Iterating on theta rather than
+// on x = cos(theta) keeps sin(theta) accurate to its own relative precision
+// near the poles, where 1 - x is tiny.  The southern half is the exact
+// mirror and the middle node of odd J is 0.
+void gauss_nodes_weights(int J, long double* x, long double* w, long double* st) {
   const long double PI = 3.141592653589793238462643383279502884L;
   for (int j = 0; j < (J + 1) / 2; ++j) {
-    long double z = cosl(PI * ((long double)j + 0.75L) / ((long double)J + 0.5L));
-    long double dp = 1.0L;
+    long double th = PI * ((long double)j + 0.75L) / ((long double)J + 0.5L);
+    long double z = cosl(th), s = sinl(th);
+    // quadratic convergence: one more step once the step is below 1e-12 th
+    // brings theta to rounding level
+    bool last = false;
     for (int it = 0; it < 100; ++it) {
       long double p0 = 1.0L, p1 = z;  // P_0, P_1
       for (int n = 2; n <= J; ++n) {
@@ -84,27 +89,43 @@ void gauss_nodes_weights(int J, long double* x, long double* w) {
         p1 = p2;
       }
       if (J == 1) p0 = 1.0L;  // P_{J-1} = P_0
-      // P_J'(z) = J (z P_J - P_{J-1}) / (z^2 - 1)
-      dp = (long double)J * (z * p1 - p0) / (z * z - 1.0L);
-      const long double dz = p1 / dp;
-      z -= dz;
-      if (fabsl(dz) < 1e-19L) break;
+      // P_J'(z) = J (P_{J-1} - z P_J) / sin^2(theta); dP_J/dtheta = -sin(theta) P_J'(z)
+      const long double dp = (long double)J * (p0 - z * p1) / (s * s);
+      const long double dth = p1 / (s * dp);
+      th += dth;
+      z = cosl(th);
+      s = sinl(th);
+      if (last) break;
+      last = fabsl(dth) < 1e-12L * th;
     }
-    if (2 * j + 1 == J) z = 0.0L;
+    if (2 * j + 1 == J) {
+      z = 0.0L;
+      s = 1.0L;
+    }
+    // the weight from P_J' at the final theta
+    long double q0 = 1.0L, q1 = z;
+    for (int n = 2; n <= J; ++n) {
+      const long double q2 = ((2.0L * n - 1.0L) * z * q1 - (n - 1.0L) * q0) / (long double)n;
+      q0 = q1;
+      q1 = q2;
+    }
+    if (J == 1) q0 = 1.0L;
     x[j] = z;
     x[J - 1 - j] = -z;
-    w[j] = w[J - 1 - j] = 2.0L / ((1.0L - z * z) * dp * dp);
+    if (st) st[j] = st[J - 1 - j] = s;
+    const long double dq = (long double)J * (q0 - z * q1) / (s * s);
+    w[j] = w[J - 1 - j] = 2.0L / (s * s * dq * dq);
   }
 }
 }  // namespace
 
 void grid_nodes(int J, int kind, double* mu, double* sint) {
   if (kind == SHT_GRID_GAUSS) {
-    std::vector<long double> x(J), w(J);
-    gauss_nodes_weights(J, x.data(), w.data());
+    std::vector<long double> x(J), w(J), st(J);
+    gauss_nodes_weights(J, x.data(), w.data(), st.data());
     for (int j = 0; j < J; ++j) {
       mu[j] = (double)x[j];
-      sint[j] = (double)sqrtl((1.0L - x[j]) * (1.0L + x[j]));
+      sint[j] = (double)st[j];
     }
     return;
   }
@@ -122,7 +143,7 @@ void grid_weights(int J, int kind, double* w) {
   const long double PI = 3.141592653589793238462643383279502884L;
   if (kind == SHT_GRID_GAUSS) {
     std::vector<long double> x(J), wl(J);
-    gauss_nodes_weights(J, x.data(), wl.data());
+    gauss_nodes_weights(J, x.data(), wl.data(), nullptr);
     for (int j = 0; j < J; ++j) w[j] = (double)wl[j];
     return;
   }

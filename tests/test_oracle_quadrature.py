@@ -249,13 +249,20 @@ def test_gauss_grid_pins(J):
         assert np.allclose(w, [1.0, 1.0], rtol=1e-15)
 
 
-@pytest.mark.parametrize("J", [1, 2, 5, 16, 33, 160])
+@pytest.mark.parametrize("J", [1, 2, 5, 16, 33, 160, 1440])
 def test_gauss_host_nodes_match_oracle(J):
-    """The library's Newton-iteration nodes and weights (host code, no GPU)
-    agree with numpy's Gauss-Legendre routine used by the oracle."""
+    """The library's extended-precision Newton nodes and weights (host code,
+    no GPU) agree with the oracle's 40-digit ones, and so does its sine of
+    the node: the sectoral P~_3^3 ~ sin^3(theta) of the library's table
+    matches the oracle's near the poles too (J = 1440: 1 - mu_0 ~ 1e-6)."""
     from paper_1711_11296_amd import host_tables
-    mu, w, _ = host_tables(3, J, "gauss")
-    _, mo, _ = O.nodes(J, "gauss")
+    mu, w, alf = host_tables(3, J, "gauss")
+    _, mo, so = O.nodes(J, "gauss")
     assert np.allclose(mu, mo, rtol=0, atol=2e-16)
     assert np.array_equal(mu, -mu[::-1])
     assert np.allclose(w, O.weights(J, "gauss"), rtol=1e-13, atol=0)
+    Jh = (J + 1) // 2
+    sect = O.alf_m(3, 3, mo[:Jh], so[:Jh])[0]
+    # the library's root carries about 1e-19 absolute error, so its sine
+    # near the pole is good to about 1e-19 / (1 - mu_0), some 1e-14 here
+    assert np.allclose(alf[O.spec_index(3, 3, 3)], sect, rtol=1e-13, atol=0)
