@@ -47,6 +47,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--aliasing", action="store_true",
                     help="time the Sec. 4.2 aliasing experiment at N_trunc=479 instead (own JSON line)")
+    ap.add_argument("--two-grid", action="store_true",
+                    help="time the residual and restriction steps of the App. C two-grid cycle instead "
+                         "(Tc479 fine, Tc239 coarse, 100 fields; own JSON line)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy a 1 GiB buffer 3 times (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -170,6 +173,72 @@ def bench_aliasing(args, torch):
         t.close()
 
 
+def bench_two_grid(args, torch):
+    """One step = the residual R = X - alpha kappa lap(X) - F of the App. C
+    elliptic problem on the fine level Tc479 (N=479, J=959, I=1440, paper's
+    grid) for 100 fields, in FP32 form, and its restriction to Tc239 spectra
+    (injection, coarse analysis).  Per-kernel times of the two elementwise
+    kernels come from events around them on the launch stream."""
+    from paper_1711_11296_amd import Plan, grid_inject, grid_residual, inputs, spec_laplacian
+    torch.cuda.set_device(0)
+    F, kind = 100, "fejer2"
+    Nf, Jf, If, Nc, Jc, Ic = 479, 959, 1440, 239, 479, 720
+    fine = Plan(Nf, Jf, If, F, grid=kind, form="fp32")
+    coarse = Plan(Nc, Jc, Ic, F, grid=kind, form="fp32")
+    X = fine.inverse(torch.from_numpy(inputs.random_spectra(Nf, F, seed=1, profile="k3")).to("cuda:0", torch.float32))
+    Fr = fine.inverse(torch.from_numpy(inputs.random_spectra(Nf, F, seed=2, profile="k3")).to("cuda:0", torch.float32))
+    kap = 1.0 + 0.5 * torch.rand((Jf, If), device="cuda:0", generator=torch.Generator("cuda:0").manual_seed(0))
+    alpha, scale = 0.2, 1.0 / 6.371e6 ** 2
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+
+    def step(timed):
+        s = fine.forward(X)
+        if timed:
+            ev[0].record()
+        lap = spec_laplacian(s, Nf, scale)
+        if timed:
+            ev[1].record()
+        y = fine.inverse(lap)
+        if timed:
+            ev[2].record()
+        r = grid_residual(X, kap, y, Fr, alpha)
+        if timed:
+            ev[3].record()
+        return coarse.forward(grid_inject(r, Jc, Ic, kind))
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    lap_ms = res_ms = 0.0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(True)
+        torch.cuda.synchronize()
+        lap_ms += ev[0].elapsed_time(ev[1])
+        res_ms += ev[2].elapsed_time(ev[3])
+    secs = time.perf_counter() - t0
+    lap_ms /= args.steps
+    res_ms /= args.steps
+    nc = (Nf + 1) * (Nf + 2) // 2
+    lap_bytes = 2 * F * nc * 2 * 4                   # spectra read and written
+    res_bytes = 4 * F * Jf * If * 4 + Jf * If * 4    # x, y, f read, r written; kappa once
+    out = {"metric": "two-grid residual+restriction steps/s", "value": args.steps / secs, "unit": "steps/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": secs / args.steps * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic: X, F synthesised from k^-3 spectra, kappa uniform in [1, 1.5]",
+           "config": {"workload": "App. C two-grid cycle, residual on Tc479 (N=479 J=959 I=1440) and restriction "
+                                  "to Tc239 (N=239 J=479 I=720), 100 fields, paper's grid, FP32 form",
+                      "fields": F},
+           "laplacian": {"ms": lap_ms, "GB/s": lap_bytes / (lap_ms * 1e-3) / 1e9,
+                         "frac_of_hbm": lap_bytes / (lap_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "bytes": lap_bytes},
+           "residual_update": {"ms": res_ms, "GB/s": res_bytes / (res_ms * 1e-3) / 1e9,
+                               "frac_of_hbm": res_bytes / (res_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                               "bytes": res_bytes}}
+    print(json.dumps(out), flush=True)
+    fine.close()
+    coarse.close()
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -184,6 +253,9 @@ def main():
         return
     if args.aliasing:
         bench_aliasing(args, torch)
+        return
+    if args.two_grid:
+        bench_two_grid(args, torch)
         return
     from paper_1711_11296_amd import Plan, inputs
 

@@ -242,6 +242,29 @@ int sht_grid_product(long long n, int dbl, const void* a, const void* b,
                      void* out, void* stream);
 
 /*
+ * The two pieces of the residual R = (I - dt/2 L) X - F of the elliptic
+ * problem of App. C (eq. elliptic), for a variable-coefficient Laplacian
+ * L X = kappa * lap(X) evaluated pseudo-spectrally: analyse X, apply the
+ * spectral Laplacian, synthesise, then the grid update.  Same conventions
+ * as the transfers above.
+ *
+ * sht_spec_laplacian: out(m, n) = c_n in(m, n) with c_n = -scale n (n+1)
+ *   (computed in double, rounded once to the element type): the Laplacian
+ *   on a sphere of radius 1/sqrt(scale), for nfields spectra of truncation
+ *   N in the layout of sht_forward.  out may equal in.
+ * sht_grid_residual: r[i] = x[i] - alpha * kappa[i mod n_per] * y[i] - f[i]
+ *   for i < n (n a multiple of n_per: kappa is one grid of n_per values
+ *   shared by all fields).  r may equal x, y or f.
+ * SHT_EINVAL on bad sizes, a non-finite scale or alpha, or bad pointers;
+ * SHT_EHIP on a launch failure.
+ */
+int sht_spec_laplacian(int N, int nfields, int dbl, double scale,
+                       const void* in, void* out, void* stream);
+int sht_grid_residual(long long n, long long n_per, int dbl, double alpha,
+                      const void* x, const void* kappa, const void* y,
+                      const void* f, void* r, void* stream);
+
+/*
  * Host-only planning (no GPU needed): nodes and weights of a grid, and the
  * FP64 table of P~_n^m for the northern rows, as sht_plan_tables.  Returns
  * SHT_EINVAL on bad arguments.

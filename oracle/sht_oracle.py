@@ -504,3 +504,34 @@ def inject(grid, Jc, Ic, kind):
         raise ValueError("grid kind %r does not nest" % (kind,))
     return grid[:, rows, :][:, :, ::t].copy()
 
+
+
+# --------------------------------------------------------------------------
+# residual of the elliptic problem of App. C (eq. elliptic)
+# --------------------------------------------------------------------------
+
+def laplacian(spec, N, scale=1.0):
+    """Spectral Laplacian: Y_n^m is an eigenfunction of the Laplacian on the
+    unit sphere with eigenvalue -n(n+1); on a sphere of radius 1/sqrt(scale)
+    the factor is -scale n(n+1).  spec [F, ncoef(N), 2] -> same shape."""
+    spec = np.asarray(spec, dtype=np.float64)
+    out = np.empty_like(spec)
+    for m in range(N + 1):
+        for n in range(m, N + 1):
+            c = -scale * float(n * (n + 1))
+            k = spec_index(N, m, n)
+            out[:, k, 0] = c * spec[:, k, 0]
+            out[:, k, 1] = c * spec[:, k, 1]
+    return out
+
+
+def helmholtz_residual(x, kappa, f, alpha, N, kind, scale=1.0):
+    """R = (I - alpha L) x - f with L x = kappa * lap(x), the Laplacian
+    evaluated pseudo-spectrally (analysis at truncation N, spectral
+    Laplacian, synthesis on the same grid): the residual of step 1 of the
+    two-grid cycle of App. C, alpha standing for dt/2.
+    x, f [F, J, I]; kappa [J, I]."""
+    x = np.asarray(x, dtype=np.float64)
+    _, J, I = x.shape
+    lap = inverse(laplacian(forward(x, N, kind), N, scale), N, J, I, kind)
+    return x - alpha * np.asarray(kappa, dtype=np.float64)[None] * lap - np.asarray(f, dtype=np.float64)

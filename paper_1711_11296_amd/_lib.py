@@ -24,7 +24,7 @@ EXPORTS = ["sht_plan", "sht_plan_ex", "sht_plan_multi", "sht_forward", "sht_inve
            "sht_forward_adjoint", "sht_inverse_adjoint", "sht_plan_query",
            "sht_plan_tables", "sht_plan_destroy", "sht_last_error", "sht_host_tables",
            "sht_plan_profile", "sht_plan_profile_read", "sht_spec_retruncate", "sht_grid_inject",
-           "sht_grid_product"]
+           "sht_grid_product", "sht_spec_laplacian", "sht_grid_residual"]
 
 
 class SHTError(RuntimeError):
@@ -82,6 +82,11 @@ def load(require_torch=True):
     lib.sht_spec_retruncate.argtypes = [c_int, c_int, c_int, c_int, vp, vp, vp]
     lib.sht_grid_product.restype = c_int
     lib.sht_grid_product.argtypes = [ctypes.c_longlong, c_int, vp, vp, vp, vp]
+    lib.sht_spec_laplacian.restype = c_int
+    lib.sht_spec_laplacian.argtypes = [c_int, c_int, c_int, ctypes.c_double, vp, vp, vp]
+    lib.sht_grid_residual.restype = c_int
+    lib.sht_grid_residual.argtypes = [ctypes.c_longlong, ctypes.c_longlong, c_int, ctypes.c_double,
+                                      vp, vp, vp, vp, vp, vp]
     lib.sht_grid_inject.restype = c_int
     lib.sht_grid_inject.argtypes = [c_int, c_int, c_int, c_int, c_int, c_int, c_int, vp, vp, vp]
     lib.sht_host_tables.restype = c_int

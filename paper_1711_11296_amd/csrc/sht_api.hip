@@ -872,6 +872,30 @@ int sht_grid_product(long long n, int dbl, const void* a, const void* b, void* o
   return hip_check((hipError_t)launch_product(n, dbl != 0, a, b, out, stream), "product launch");
 }
 
+int sht_spec_laplacian(int N, int nfields, int dbl, double scale, const void* in, void* out, void* stream) {
+  if (N < 0 || N > 65534 || nfields < 1 || nfields > 65535)
+    return fail(SHT_EINVAL, "need 0 <= N <= 65534 and 1 <= nfields <= 65535");
+  if (!std::isfinite(scale)) return fail(SHT_EINVAL, "scale must be finite");
+  int rc = check_ptr(in, "in");
+  if (!rc) rc = check_ptr(out, "out");
+  if (rc) return rc;
+  return hip_check((hipError_t)launch_laplacian(N, nfields, scale, dbl != 0, in, out, stream), "laplacian launch");
+}
+
+int sht_grid_residual(long long n, long long n_per, int dbl, double alpha, const void* x, const void* kappa,
+                      const void* y, const void* f, void* r, void* stream) {
+  if (n < 1 || n_per < 1 || n % n_per) return fail(SHT_EINVAL, "need n >= 1 a multiple of n_per >= 1");
+  if (!std::isfinite(alpha)) return fail(SHT_EINVAL, "alpha must be finite");
+  int rc = check_ptr(x, "x");
+  if (!rc) rc = check_ptr(kappa, "kappa");
+  if (!rc) rc = check_ptr(y, "y");
+  if (!rc) rc = check_ptr(f, "f");
+  if (!rc) rc = check_ptr(r, "r");
+  if (rc) return rc;
+  return hip_check((hipError_t)launch_residual(n, n_per, alpha, dbl != 0, x, kappa, y, f, r, stream),
+                   "residual launch");
+}
+
 int sht_grid_inject(int J_fine, int I_fine, int J_coarse, int I_coarse, int nfields, int grid, int dbl,
                     const void* fine, void* coarse, void* stream) {
   if (nfields < 1 || nfields > 65535 || I_coarse < 1 || I_fine < I_coarse || I_fine % I_coarse)

@@ -102,6 +102,9 @@ int launch_retruncate(int Nin, int Nout, int F, bool dbl, const void* in, void* 
 int launch_inject(int Jf, int If, int Jc, int Ic, int F, int rs, int r0, int cs, bool dbl, const void* fine,
                   void* coarse, void* stream);
 int launch_product(long long n, bool dbl, const void* a, const void* b, void* out, void* stream);
+int launch_laplacian(int N, int F, double scale, bool dbl, const void* in, void* out, void* stream);
+int launch_residual(long long n, long long n_per, double alpha, bool dbl, const void* x, const void* kappa,
+                    const void* y, const void* f, void* r, void* stream);
 // Widest column blocking (16-column units) a Legendre kernel of a form takes.
 int max_ncb(int form, bool analysis);
 

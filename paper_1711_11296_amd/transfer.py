@@ -1,6 +1,7 @@
 """Transfers between truncations and nested grids for multigrid cycles
-(App. C): spectral re-truncation and grid injection; and the pointwise
-product of grids (the nonlinear terms of Sec. 4.2).  Run by libsht.so on the
+(App. C): spectral re-truncation and grid injection; the pieces of the
+residual of the App. C elliptic problem (spectral Laplacian, grid update);
+and the pointwise product of grids (the nonlinear terms of Sec. 4.2).  Run by libsht.so on the
 tensors' device and current stream."""
 
 import ctypes
@@ -66,3 +67,40 @@ def grid_product(a, b):
                                     ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(stream)))
     return out
 
+
+
+def spec_laplacian(spec, N, scale=1.0):
+    """Spectra [F, (N+1)(N+2)/2, 2] -> c_n * spec with c_n = -scale n (n+1):
+    the Laplacian on a sphere of radius 1/sqrt(scale)."""
+    import torch
+    lib = _lib.load()
+    spec = spec.contiguous()
+    F = spec.shape[0]
+    if tuple(spec.shape) != (F, (N + 1) * (N + 2) // 2, 2):
+        raise ValueError("spec must be [F, %d, 2]" % ((N + 1) * (N + 2) // 2))
+    out = torch.empty_like(spec)
+    stream = torch.cuda.current_stream(spec.device).cuda_stream
+    _lib.check(lib.sht_spec_laplacian(N, F, _dbl(spec), float(scale), ctypes.c_void_p(spec.data_ptr()),
+                                      ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(stream)))
+    return out
+
+
+def grid_residual(x, kappa, y, f, alpha):
+    """r = x - alpha * kappa * y - f; x, y, f [F, J, I] (or any shape whose
+    trailing elements form whole copies of kappa), kappa [J, I] shared by
+    all fields."""
+    import torch
+    lib = _lib.load()
+    ts = [x.contiguous(), kappa.contiguous(), y.contiguous(), f.contiguous()]
+    if not (ts[0].shape == ts[2].shape == ts[3].shape):
+        raise ValueError("x, y and f must have the same shape")
+    if any(t.dtype != ts[0].dtype or t.device != ts[0].device for t in ts):
+        raise ValueError("all tensors must share dtype and device")
+    n, n_per = ts[0].numel(), ts[1].numel()
+    if n_per < 1 or n % n_per:
+        raise ValueError("kappa must tile x")
+    r = torch.empty_like(ts[0])
+    stream = torch.cuda.current_stream(x.device).cuda_stream
+    _lib.check(lib.sht_grid_residual(n, n_per, _dbl(ts[0]), float(alpha), *[ctypes.c_void_p(t.data_ptr()) for t in ts],
+                                     ctypes.c_void_p(r.data_ptr()), ctypes.c_void_p(stream)))
+    return r

@@ -126,8 +126,9 @@ def test_host_table_no_underflow_at_high_order():
 
 
 def test_transfer_arguments_are_rejected_without_a_gpu():
-    """Re-truncation and injection check their arguments before any GPU
-    call: bad sizes, grids that do not nest, NULL or misaligned pointers.
+    """Re-truncation, injection, the spectral Laplacian and the residual
+    update check their arguments before any GPU call: bad sizes, grids that
+    do not nest, non-finite scalars, NULL or misaligned pointers.
     (Every call here must fail validation: none may reach a launch, since
     the buffers are host memory.)"""
     lib = _lib.load(require_torch=False)
@@ -146,4 +147,17 @@ def test_transfer_arguments_are_rejected_without_a_gpu():
     assert lib.sht_grid_inject(33, 48, 17, 24, 1, 2, 0, p, q, None) == E    # shifted grid
     assert lib.sht_grid_inject(33, 48, 17, 24, 0, 0, 0, p, q, None) == E    # no fields
     assert lib.sht_grid_inject(33, 48, 17, 24, 1, 0, 0, None, q, None) == E
+    # spectral Laplacian and residual update of the App. C residual
+    assert lib.sht_spec_laplacian(-1, 1, 0, 1.0, p, q, None) == E
+    assert lib.sht_spec_laplacian(3, 0, 0, 1.0, p, q, None) == E
+    assert lib.sht_spec_laplacian(3, 1, 0, float("nan"), p, q, None) == E
+    assert lib.sht_spec_laplacian(3, 1, 0, float("inf"), p, q, None) == E
+    assert lib.sht_spec_laplacian(3, 1, 0, 1.0, None, q, None) == E
+    assert lib.sht_spec_laplacian(3, 1, 1, 1.0, p, ctypes.c_void_p(q.value + 8), None) == E
+    assert lib.sht_grid_residual(0, 1, 0, 1.0, p, p, q, q, q, None) == E
+    assert lib.sht_grid_residual(10, 3, 0, 1.0, p, p, q, q, q, None) == E      # 10 % 3
+    assert lib.sht_grid_residual(12, 0, 0, 1.0, p, p, q, q, q, None) == E
+    assert lib.sht_grid_residual(12, 3, 0, float("nan"), p, p, q, q, q, None) == E
+    assert lib.sht_grid_residual(12, 3, 0, 1.0, p, None, q, q, q, None) == E
+    assert lib.sht_grid_residual(12, 3, 0, 1.0, p, p, q, q, None, None) == E
 

@@ -405,3 +405,51 @@ def test_injection_rows_are_the_nested_nodes(kind, Jc, Jf):
         O.inject(g, Jc + 1, 3, kind)
     with pytest.raises(ValueError):
         O.inject(g, Jc, 3, "fejer1")
+
+
+def _xyz(J, I, kind):
+    _, mu, sint = O.nodes(J, kind)
+    lam = 2.0 * np.pi * np.arange(I) / I
+    x = sint[:, None] * np.cos(lam)[None, :]
+    y = sint[:, None] * np.sin(lam)[None, :]
+    z = mu[:, None] * np.ones(I)[None, :]
+    return x, y, z
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_laplacian_closed_forms(kind):
+    """On the unit sphere a harmonic homogeneous polynomial of degree l is an
+    eigenfunction of the Laplacian with eigenvalue -l(l+1): z -> -2 z,
+    xy -> -6 xy, x^3 - 3 x y^2 -> -12 (x^3 - 3 x y^2); z^2 = 1/3 + (z^2 - 1/3)
+    gives 2 - 6 z^2; constants give 0.  The pseudo-spectral Laplacian
+    (analysis, spectral factor, synthesis) reproduces each, and the factor
+    scales with 1/radius^2."""
+    N, J, I = 5, 11, 16
+    x, y, z = _xyz(J, I, kind)
+    cases = [(z, -2 * z), (x * y, -6 * x * y), (x ** 3 - 3 * x * y ** 2, -12 * (x ** 3 - 3 * x * y ** 2)),
+             (z ** 2, 2 - 6 * z ** 2), (np.full_like(z, 3.0), np.zeros_like(z))]
+    for g, lap in cases:
+        out = O.inverse(O.laplacian(O.forward(g[None], N, kind), N), N, J, I, kind)[0]
+        assert np.max(np.abs(out - lap)) < 1e-13
+        out4 = O.inverse(O.laplacian(O.forward(g[None], N, kind), N, scale=0.25), N, J, I, kind)[0]
+        assert np.max(np.abs(out4 - 0.25 * lap)) < 1e-13
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_helmholtz_residual_of_manufactured_solution(kind):
+    """App. C eq. elliptic with L X = kappa lap(X): for X = xy + z and a
+    variable kappa = 1 + x/2, the right-hand side F = X - alpha kappa
+    (-6 xy - 2 z) written out by hand makes the residual vanish; a wrong
+    sign of alpha, kappa on the wrong side or a dropped term would not."""
+    N, J, I = 5, 11, 16
+    x, y, z = _xyz(J, I, kind)
+    X = x * y + z
+    kappa = 1.0 + 0.5 * x
+    alpha = 0.3
+    F = X - alpha * kappa * (-6 * x * y - 2 * z)
+    R = O.helmholtz_residual(X[None], kappa, F[None], alpha, N, kind)
+    assert np.max(np.abs(R)) < 1e-13
+    # and the residual of another field is the hand-computed one
+    X2 = z ** 2
+    R2 = O.helmholtz_residual(X2[None], kappa, F[None], alpha, N, kind)
+    assert np.max(np.abs(R2[0] - (X2 - alpha * kappa * (2 - 6 * z ** 2) - F))) < 1e-13
