@@ -1209,6 +1209,24 @@ static bool launch_fixed(bool analysis, const FftArgs& a, int maxN, hipStream_t 
     case 480:
       *err = launch_p3<T, Plan3<480, 6, 5>, 256, FB, dbl ? 4 : 8>(analysis, a, maxN, st);
       return true;
+    case 1600:
+      if constexpr (FB > 8) return false;
+      else {
+        *err = launch_p3<T, Plan3<1600, 10, 10>, 512, FB, dbl ? 2 : 4>(analysis, a, maxN, st);
+        return true;
+      }
+    case 800:
+      if constexpr (FB > 8) return false;
+      else {
+        *err = launch_p3<T, Plan3<800, 5, 10>, 256, FB, 4>(analysis, a, maxN, st);
+        return true;
+      }
+    case 400:
+      if constexpr (FB > 8) return false;
+      else {
+        *err = launch_p3<T, Plan3<400, 5, 5>, 256, FB, dbl ? 4 : 8>(analysis, a, maxN, st);
+        return true;
+      }
     default:
       return false;
   }
@@ -1226,10 +1244,7 @@ static void ensure_num_cu() {
 }
 
 template <typename T, int FB, int FC>
-static hipError_t launch_zonal_t(bool analysis, const FftArgs& a, int maxN, hipStream_t st) {
-  ensure_num_cu();
-  hipError_t err = hipSuccess;
-  if (launch_fixed<T, FB>(analysis, a, maxN, st, &err)) return err;
+static hipError_t launch_generic(bool analysis, const FftArgs& a, int maxN, hipStream_t st) {
   int maxI = 0;
   for (int l = 0; l < a.nlev; ++l) maxI = a.lev[l].I > maxI ? a.lev[l].I : maxI;
   const int nm = maxN + 1;
@@ -1246,6 +1261,47 @@ static hipError_t launch_zonal_t(bool analysis, const FftArgs& a, int maxN, hipS
   if (nm <= 1024) return launch_cfg<T, 512, FB, FC, 2, 4096>(analysis, a, maxI, st);
   if (nm <= 1536) return launch_cfg<T, 512, FB, FC, 3, 4096>(analysis, a, maxI, st);
   return launch_cfg<T, 512, FB, FC, 4, 4096>(analysis, a, maxI, st);
+}
+
+// Multi-level plans: each level whose I has a compile-time three-pass plan
+// gets a launch of its own (one level per argument block, its items
+// renumbered from 0); the other levels share one launch of the
+// runtime-radix kernel.  All launches go to the same stream, and the levels
+// write disjoint parts of the output.
+template <typename T, int FB, int FC>
+static hipError_t launch_levels(bool analysis, const FftArgs& a, hipStream_t st) {
+  FftArgs rest = a;
+  rest.nlev = 0;
+  rest.nitems = 0;
+  int rest_maxN = 0;
+  for (int l = 0; l < a.nlev; ++l) {
+    FftArgs one = a;
+    one.nlev = 1;
+    one.lev[0] = a.lev[l];
+    one.lev[0].fft_item0 = 0;
+    one.nitems = a.lev[l].Jh * a.lev[l].nfb;
+    hipError_t e = hipSuccess;
+    if (launch_fixed<T, FB>(analysis, one, a.lev[l].N, st, &e)) {
+      if (e != hipSuccess) return e;
+      continue;
+    }
+    rest.lev[rest.nlev] = a.lev[l];
+    rest.lev[rest.nlev].fft_item0 = rest.nitems;
+    rest.nitems += one.nitems;
+    rest.nlev += 1;
+    rest_maxN = a.lev[l].N > rest_maxN ? a.lev[l].N : rest_maxN;
+  }
+  if (rest.nlev == 0) return hipSuccess;
+  return launch_generic<T, FB, FC>(analysis, rest, rest_maxN, st);
+}
+
+template <typename T, int FB, int FC>
+static hipError_t launch_zonal_t(bool analysis, const FftArgs& a, int maxN, hipStream_t st) {
+  ensure_num_cu();
+  if (a.nlev > 1) return launch_levels<T, FB, FC>(analysis, a, st);
+  hipError_t err = hipSuccess;
+  if (launch_fixed<T, FB>(analysis, a, maxN, st, &err)) return err;
+  return launch_generic<T, FB, FC>(analysis, a, maxN, st);
 }
 
 int zonal_fields_per_block(int form, int nlev, int N, int J, int I, int F) {

@@ -98,6 +98,11 @@ def test_multi_tile_parity(form, kind, N, J, I, F):
     ("fejer2", 700, 97, 1440, 9),       # I = 16*9*10, two wavenumbers per thread
     ("cc_poles", 30, 33, 2880, 2),      # I = 16*12*15, most bins zero
     ("cc_poles", 1040, 40, 2880, 3),    # N + 1 > 1024: three wavenumbers per thread
+    ("cc_poles", 150, 101, 400, 5),     # I = 16*5*5
+    ("fejer2", 200, 60, 800, 3),        # I = 16*5*10, one wavenumber per thread
+    ("fejer2", 300, 97, 800, 9),        # two wavenumbers per thread
+    ("cc_poles", 600, 81, 1600, 3),     # I = 16*10*10, two wavenumbers per thread
+    ("fejer1", 300, 64, 1600, 10),      # one wavenumber per thread, ragged field block
 ])
 def test_fixed_length_plans(form, kind, N, J, I, F):
     """Lengths with a compile-time three-pass FFT plan, away from the
