@@ -1200,7 +1200,8 @@ static bool launch_fixed(bool analysis, const FftArgs& a, int maxN, hipStream_t 
     case 2880:
       if constexpr (FB > 8) return false;  // several wavenumbers per thread: 8 fields at most
       else {
-        *err = launch_p3<T, Plan3<2880, 12, 15>, 512, FB, dbl ? 2 : 4>(analysis, a, maxN, st);
+        // two fields per round (four spill registers and ~5 % more time with four)
+        *err = launch_p3<T, Plan3<2880, 12, 15>, 512, FB, 2>(analysis, a, maxN, st);
         return true;
       }
     case 1440:
