@@ -15,7 +15,9 @@ def helmholtz_residual(plan, x, kappa, f, alpha, scale=1.0):
 
     x, f: grids [F, J, I] in the plan's dtype; kappa: [J, I]; scale: 1 /
     radius^2.  Analysis, spectral Laplacian, synthesis, fused update."""
-    (N, J, I, F), = plan.levels
+    if len(plan.levels) != 1:
+        raise ValueError("helmholtz_residual needs a single-level plan")
+    N = plan.levels[0][0]
     lap = plan.inverse(spec_laplacian(plan.forward(x), N, scale))
     return grid_residual(x, kappa, lap, f, alpha)
 
@@ -24,5 +26,7 @@ def restrict_to_coarse_spectra(r_fine, coarse_plan, kind):
     """Restriction of a fine-grid field to the coarse level's spectral space
     (Sec. 3.2, App. C step 2): inject the coarse grid's nodes, then analyse
     on the coarse grid."""
-    (_, Jc, Ic, _), = coarse_plan.levels
+    if len(coarse_plan.levels) != 1:
+        raise ValueError("restrict_to_coarse_spectra needs a single-level coarse plan")
+    _, Jc, Ic, _ = coarse_plan.levels[0]
     return coarse_plan.forward(grid_inject(r_fine, Jc, Ic, kind))
