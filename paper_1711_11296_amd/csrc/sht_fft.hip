@@ -1210,6 +1210,18 @@ static bool launch_fixed(bool analysis, const FftArgs& a, int maxN, hipStream_t 
     case 480:
       *err = launch_p3<T, Plan3<480, 6, 5>, 256, FB, dbl ? 4 : 8>(analysis, a, maxN, st);
       return true;
+    case 1920:
+      if constexpr (FB > 8) return false;
+      else {
+        *err = launch_p3<T, Plan3<1920, 12, 10>, 512, FB, dbl ? 2 : 4>(analysis, a, maxN, st);
+        return true;
+      }
+    case 960:
+      if constexpr (FB > 8) return false;
+      else {
+        *err = launch_p3<T, Plan3<960, 6, 10>, 512, FB, dbl ? 2 : 4>(analysis, a, maxN, st);
+        return true;
+      }
     case 1600:
       if constexpr (FB > 8) return false;
       else {

@@ -103,6 +103,8 @@ def test_multi_tile_parity(form, kind, N, J, I, F):
     ("fejer2", 300, 97, 800, 9),        # two wavenumbers per thread
     ("cc_poles", 600, 81, 1600, 3),     # I = 16*10*10, two wavenumbers per thread
     ("fejer1", 300, 64, 1600, 10),      # one wavenumber per thread, ragged field block
+    ("gauss", 479, 80, 960, 3),         # I = 16*6*10 (the Tl479 Gaussian grid's length)
+    ("fejer2", 600, 71, 1920, 5),       # I = 16*12*10, two wavenumbers per thread
 ])
 def test_fixed_length_plans(form, kind, N, J, I, F):
     """Lengths with a compile-time three-pass FFT plan, away from the
