@@ -146,9 +146,11 @@ int sht_plan_ex(int N, int J, int I, int nfields, const sht_options* opts,
                 sht_plan_t* out);
 
 /*
- * A hierarchy of nlevels (1..8) independent transforms executed together:
- * one launch per stage covers all levels (e.g. the nested truncations of
- * Sec. 3.2).  Arrays have nlevels entries; buffers are concatenated.
+ * A hierarchy of nlevels (1..8) independent transforms executed together
+ * (e.g. the nested truncations of Sec. 3.2): one Legendre launch per
+ * direction covers all levels; the zonal stage launches once per level
+ * whose I has a compile-time FFT plan and once for all other levels.
+ * Arrays have nlevels entries; buffers are concatenated.
  */
 int sht_plan_multi(int nlevels, const int* N, const int* J, const int* I,
                    const int* nfields, const sht_options* opts,

@@ -30,7 +30,7 @@ class Plan:
     """A transform plan on the current GPU.
 
     levels: one (N, J, I, nfields) tuple, or a list of them for a batched
-    hierarchy run in one launch per stage.  grid: "cc_poles", "fejer2" or "fejer1";
+    hierarchy run together (one Legendre launch per direction for all levels).  grid: "cc_poles", "fejer2" or "fejer1";
     form: "fp64", "fp32" or "bf16x6".  reduced: leave out, per m, the polar
     latitudes where every |P~_n^m| < 1e-16 (the reduced transform of
     Sec. 4.1; see sht_options.reduced).

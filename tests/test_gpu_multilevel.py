@@ -1,4 +1,4 @@
-"""The nested hierarchy batched in one launch per stage (Sec. 3.2 nesting):
+"""The nested hierarchy batched in one plan (Sec. 3.2 nesting):
 N = 32..512, J = 2N+1 on the grid with the poles, I = 100..1600, 32 fields
 per level, FP32, autotuned Legendre tiles, graph replay.  Each level is
 checked against the oracle; a coarse level fed the injected fine grid must
