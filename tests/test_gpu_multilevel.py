@@ -125,3 +125,25 @@ def test_autotune_cache_written(plan):
     path = os.environ["SHT_TUNE_CACHE"]
     txt = open(path).read()
     assert "form1 lev5" in txt and "|" in txt
+
+
+@pytest.mark.parametrize("form", ["fp64", "bf16x6"])
+def test_mixed_length_levels_other_forms(form):
+    """A multi-level plan whose levels mix lengths with a compile-time FFT
+    plan (I = 400, 800) and without one (I = 200, 300), in the FP64 and
+    split forms: the per-length zonal launches and the shared runtime-radix
+    launch together cover every level, each against the oracle."""
+    from paper_1711_11296_amd import Plan
+    levels = [(64, 129, 200, 3), (128, 257, 400, 2), (149, 150, 300, 5), (399, 97, 800, 2)]
+    dt = torch.float64 if form == "fp64" else torch.float32
+    tol = 1e-12 if form == "fp64" else 1e-6
+    p = Plan(levels=levels, grid="cc_poles", form=form)
+    specs = [inputs.random_spectra(N, F, seed=30 + k, profile="inv1") for k, (N, J, I, F) in enumerate(levels)]
+    a = torch.from_numpy(np.concatenate([s.ravel() for s in specs])).to(_dev(), dt)
+    g = p.inverse(a)
+    s = p.forward(g)
+    al, gl, sl = _split(p, _np(a), "spec"), _split(p, _np(g), "grid"), _split(p, _np(s), "spec")
+    for k, (N, J, I, F) in enumerate(levels):
+        assert rel(gl[k], O.inverse(al[k], N, J, I, "cc_poles")) < tol, ("inverse", levels[k])
+        assert rel(sl[k], O.forward(gl[k], N, "cc_poles")) < tol, ("forward", levels[k])
+    p.close()
