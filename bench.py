@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--two-grid", action="store_true",
                     help="time the residual and restriction steps of the App. C two-grid cycle instead "
                          "(Tc479 fine, Tc239 coarse, 100 fields; own JSON line)")
+    ap.add_argument("--otf", action="store_true",
+                    help="with --aliasing: FP64 analyses generate P~ from seed rows (plan option otf)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy a 1 GiB buffer 3 times (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -146,7 +148,7 @@ def bench_aliasing(args, torch):
     Nt = 479
     U, V, W = [torch.from_numpy(inputs.random_spectra(Nt, 1, seed=k, profile="uniform13")).to("cuda:0")
                for k in range(3)]
-    terms = {k: aliasing.NonlinearTerms(*v) for k, v in aliasing.grids(Nt).items()}
+    terms = {k: aliasing.NonlinearTerms(*v, otf=args.otf) for k, v in aliasing.grids(Nt).items()}
     ev = {k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for k in terms}
     for _ in range(args.warmup):
         for t in terms.values():
@@ -169,7 +171,8 @@ def bench_aliasing(args, torch):
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
            "data": "synthetic: U, V, W with Re, Im ~ U[(n+1)^-1/3, 2 (n+1)^-1/3], n <= 479",
            "config": {"workload": "Sec. 4.2 aliasing experiment, N_trunc=479: Tl1439 Gaussian reference, "
-                                  "Tl479 Gaussian linear, Tc479 CC cubic (fejer2), FP64",
+                                  "Tl479 Gaussian linear, Tc479 CC cubic (fejer2), FP64%s"
+                                  % (", analysis with generated P~" if args.otf else ""), "otf": bool(args.otf),
                       "grids": {k: list(v) for k, v in aliasing.grids(Nt).items()}},
            "last_step_ms_per_grid": ms,
            "reference_legendre_flops_per_direction": p.legendre_flops}

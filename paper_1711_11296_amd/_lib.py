@@ -36,7 +36,7 @@ class SHTError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("grid", ctypes.c_int), ("form", ctypes.c_int),
                 ("autotune", ctypes.c_int), ("use_graph", ctypes.c_int),
-                ("reduced", ctypes.c_int)]
+                ("reduced", ctypes.c_int), ("otf", ctypes.c_int)]
 
 
 _lib = None

@@ -28,9 +28,9 @@ class NonlinearTerms:
     stream and does not synchronise.
     """
 
-    def __init__(self, N, J, I, grid, form="fp64"):
+    def __init__(self, N, J, I, grid, form="fp64", otf=False):
         self.N = N
-        self.plan = Plan(N, J, I, 3, grid=grid, form=form)
+        self.plan = Plan(N, J, I, 3, grid=grid, form=form, otf=otf)
 
     def __call__(self, U, V, W):
         import torch

@@ -49,6 +49,12 @@ struct sht_plan_s {
   int autotune = 0;
   int use_graph = 0;
   int reduced = 0;             // reduced transform (Sec. 4.1)
+  int otf = 0;                 // analysis generates P~ from seed rows (FP64)
+  double* d_seeds = nullptr;   // per (level, m, 16-degree group): two seed rows of Kp
+  long long* d_seedoff = nullptr;
+  double* d_rec = nullptr;     // per (level, m, r): recurrence coefficients (A_r, B_r)
+  long long* d_recoff = nullptr;
+  double* d_mu = nullptr;      // per level: Kp nodes of the northern rows
   std::vector<int> jst;        // per (level, m): first latitude kept (0 if not reduced)
   int* d_jst = nullptr;
   int device = 0;
@@ -260,7 +266,8 @@ std::vector<Tile> build_tiles(const sht_plan_s* P, bool analysis, int ncb, int s
 
 template <typename T>
 void fill_table_level(const LevelDesc& L, const double* mu, const double* sint,
-                      T* dst, const long long* off_a, T* dsyn, const long long* off_s, int* j0) {
+                      T* dst, const long long* off_a, T* dsyn, const long long* off_s, int* j0,
+                      double* seeds, const long long* off_seed) {
   const int N = L.N, Jh = L.Jh, Kp = L.Kp;
   int nth = (int)std::thread::hardware_concurrency();
   nth = std::max(1, std::min(nth, 64));
@@ -284,6 +291,16 @@ void fill_table_level(const LevelDesc& L, const double* mu, const double* sint,
                 break;
               }
           j0[m] = first;
+        }
+        if (seeds) {
+          // generated analysis: rows 16 g and 16 g + 1 of every 16-degree group
+          double* sd = seeds + off_seed[m];
+          for (int g = 0; g < (nm + 15) / 16; ++g)
+            for (int t2 = 0; t2 < 2; ++t2) {
+              const int r = 16 * g + t2;
+              for (int j = 0; j < Kp; ++j)
+                sd[(size_t)(2 * g + t2) * Kp + j] = (r < nm && j < Jh) ? col[(size_t)r * Jh + j] : 0.0;
+            }
         }
         T* blk = dst + off_a[m];
         const int R = (int)roundup(nm, 128);
@@ -337,9 +354,11 @@ int build_plan(int nlev, const int* Nv, const int* Jv, const int* Iv, const int*
   *out = nullptr;
   if (nlev < 1 || nlev > SHT_MAX_LEVELS) return fail(SHT_EINVAL, "nlevels must be 1..8");
   if (!Nv || !Jv || !Iv || !Fv) return fail(SHT_EINVAL, "level arrays must not be NULL");
-  sht_options o{SHT_GRID_CC_POLES, SHT_FORM_FP64, 0, 0, 0};
+  sht_options o{SHT_GRID_CC_POLES, SHT_FORM_FP64, 0, 0, 0, 0};
   if (opts) o = *opts;
   if (o.form < SHT_FORM_FP64 || o.form > SHT_FORM_BF16X6) return fail(SHT_EINVAL, "unknown form");
+  if (o.otf && (o.form != SHT_FORM_FP64 || o.reduced || o.autotune))
+    return fail(SHT_EINVAL, "otf needs the FP64 form, without reduced or autotune");
   for (int l = 0; l < nlev; ++l) {
     int rc = check_level_args(Nv[l], Jv[l], Iv[l], Fv[l], o.grid);
     if (rc) return rc;
@@ -352,6 +371,7 @@ int build_plan(int nlev, const int* Nv, const int* Jv, const int* Iv, const int*
   P->autotune = o.autotune;
   P->use_graph = o.use_graph;
   P->reduced = o.reduced != 0;
+  P->otf = o.otf != 0;
   P->nlev = nlev;
   P->elem = o.form == SHT_FORM_FP64 ? 8 : 4;
   int rc = hip_check(hipGetDevice(&P->device), "hipGetDevice");
@@ -373,8 +393,8 @@ int build_plan(int nlev, const int* Nv, const int* Jv, const int* Iv, const int*
 
   // ---- level descriptors and sizes ----
   long long goff = 0, soff = 0, woff = 0, moff = 0, item = 0;
-  std::vector<long long> taboff, taboff_syn;
-  long long tab = 0, tabs = 0;
+  std::vector<long long> taboff, taboff_syn, seedoff, recoff;
+  long long tab = 0, tabs = 0, seeds_total = 0, rec_total = 0;
   for (int l = 0; l < nlev; ++l) {
     LevelDesc& L = P->lev[l];
     std::memset(&L, 0, sizeof(L));
@@ -409,6 +429,10 @@ int build_plan(int nlev, const int* Nv, const int* Jv, const int* Iv, const int*
       taboff_syn.push_back(tabs);
       const int kr2 = 32;  // natural rows per K block
       tabs += (long long)((L.Jh + 127) / 128) * ((L.N - m + kr2) / kr2) * 128 * kr2;
+      seedoff.push_back(seeds_total);
+      seeds_total += 2LL * ((L.N - m + 16) / 16) * L.Kp;
+      recoff.push_back(rec_total);
+      rec_total += 2LL * (L.N - m + 1);
     }
     P->maxN = std::max(P->maxN, L.N);
     P->flops += 2.0 * L.Jh * (double)(L.N + 1) * (L.N + 2) * L.F;
@@ -436,8 +460,9 @@ int build_plan(int nlev, const int* Nv, const int* Jv, const int* Iv, const int*
   std::vector<double> hw;
   std::vector<std::vector<unsigned char>> htw(nlev);
   size_t tw_total = 0;
-  std::vector<size_t> tw_off(nlev), w_off(nlev);
-  size_t w_total = 0;
+  std::vector<size_t> tw_off(nlev), w_off(nlev), mu_off(nlev);
+  size_t w_total = 0, mu_total = 0;
+  std::vector<double> hseeds(P->otf ? (size_t)seeds_total : 0), hrec(P->otf ? (size_t)rec_total : 0), hmu;
   for (int l = 0; l < nlev; ++l) {
     LevelDesc& L = P->lev[l];
     std::vector<double> mu(L.J), sint(L.J), w(L.J);
@@ -446,14 +471,33 @@ int build_plan(int nlev, const int* Nv, const int* Jv, const int* Iv, const int*
     w_off[l] = w_total;
     w_total += L.Jh;
     hw.insert(hw.end(), w.begin(), w.begin() + L.Jh);
+    if (P->otf) {
+      mu_off[l] = mu_total;
+      mu_total += L.Kp;
+      for (int j = 0; j < L.Kp; ++j) hmu.push_back(j < L.Jh ? mu[j] : 0.0);
+      // P~_n = a_n (mu P~_{n-1} - P~_{n-2} / a_{n-1}), a_n = sqrt((4n^2-1)/(n^2-m^2))
+      for (int m = 0; m <= L.N; ++m) {
+        double* rc2 = hrec.data() + recoff[L.m_base + m];
+        long double aprev = 0.0L;
+        for (int r = 0; r <= L.N - m; ++r) {
+          const long double n = (long double)(m + r), mm = (long double)m * m;
+          const long double a = r >= 1 ? sqrtl((4.0L * n * n - 1.0L) / (n * n - mm)) : 0.0L;
+          rc2[2 * r] = (double)a;
+          rc2[2 * r + 1] = r >= 2 ? (double)(a / aprev) : 0.0;
+          aprev = a;
+        }
+      }
+    }
     const long long* to = taboff.data() + L.m_base;
     const long long* ts = taboff_syn.data() + L.m_base;
     if (o.form == SHT_FORM_FP64)
       fill_table_level<double>(L, mu.data(), sint.data(), reinterpret_cast<double*>(htab.data()), to,
-                               reinterpret_cast<double*>(htabs.data()), ts, P->reduced ? P->jst.data() + L.m_base : nullptr);
+                               reinterpret_cast<double*>(htabs.data()), ts, P->reduced ? P->jst.data() + L.m_base : nullptr,
+                               P->otf ? hseeds.data() : nullptr, seedoff.data() + L.m_base);
     else
       fill_table_level<float>(L, mu.data(), sint.data(), reinterpret_cast<float*>(htab.data()), to,
-                              reinterpret_cast<float*>(htabs.data()), ts, P->reduced ? P->jst.data() + L.m_base : nullptr);
+                              reinterpret_cast<float*>(htabs.data()), ts, P->reduced ? P->jst.data() + L.m_base : nullptr,
+                              nullptr, nullptr);
     // twiddles exp(-2 pi i k / I)
     const size_t cs = 2 * P->elem;
     htw[l].resize((size_t)L.I * cs);
@@ -499,6 +543,8 @@ int build_plan(int nlev, const int* Nv, const int* Jv, const int* Iv, const int*
     for (int m = 0; m <= L.N; ++m)
       P->flops_kept += 4.0 * (L.N - m + 1) * L.F * (double)(L.Jh - P->jst[L.m_base + m] / kb * kb);
   }
+  // the generated analysis takes one column block
+  if (P->otf) P->ncb_fwd = 1;
   std::vector<Tile> sf = build_tiles(P, true, P->ncb_fwd, 0), si = build_tiles(P, false, P->ncb_inv, 0);
   P->ntiles_fwd = (int)sf.size();
   P->ntiles_inv = (int)si.size();
@@ -551,6 +597,34 @@ int build_plan(int nlev, const int* Nv, const int* Jv, const int* Iv, const int*
   if (!rc)
     rc = hip_check(hipMemcpy(djs, P->jst.data(), P->jst.size() * sizeof(int), hipMemcpyHostToDevice),
                    "upload latitude starts");
+  if (!rc && P->otf) {
+    void *dsd = nullptr, *dso = nullptr, *drc = nullptr, *dro = nullptr, *dmu = nullptr;
+    if (!(rc = dev_alloc(P, &dsd, hseeds.size() * sizeof(double))) &&
+        !(rc = dev_alloc(P, &dso, seedoff.size() * sizeof(long long))) &&
+        !(rc = dev_alloc(P, &drc, hrec.size() * sizeof(double))) &&
+        !(rc = dev_alloc(P, &dro, recoff.size() * sizeof(long long))) &&
+        !(rc = dev_alloc(P, &dmu, hmu.size() * sizeof(double)))) {
+      P->d_seeds = static_cast<double*>(dsd);
+      P->d_seedoff = static_cast<long long*>(dso);
+      P->d_rec = static_cast<double*>(drc);
+      P->d_recoff = static_cast<long long*>(dro);
+      P->d_mu = static_cast<double*>(dmu);
+      for (int l = 0; l < nlev; ++l) P->lev[l].murow = P->d_mu + mu_off[l];
+      rc = hip_check(hipMemcpy(dsd, hseeds.data(), hseeds.size() * sizeof(double), hipMemcpyHostToDevice),
+                     "upload seeds");
+      if (!rc)
+        rc = hip_check(hipMemcpy(dso, seedoff.data(), seedoff.size() * sizeof(long long), hipMemcpyHostToDevice),
+                       "upload seed offsets");
+      if (!rc)
+        rc = hip_check(hipMemcpy(drc, hrec.data(), hrec.size() * sizeof(double), hipMemcpyHostToDevice),
+                       "upload recurrence");
+      if (!rc)
+        rc = hip_check(hipMemcpy(dro, recoff.data(), recoff.size() * sizeof(long long), hipMemcpyHostToDevice),
+                       "upload recurrence offsets");
+      if (!rc)
+        rc = hip_check(hipMemcpy(dmu, hmu.data(), hmu.size() * sizeof(double), hipMemcpyHostToDevice), "upload nodes");
+    }
+  }
   if (!rc) rc = hip_check(hipDeviceSynchronize(), "plan synchronize");
   if (!rc && o.autotune) rc = autotune(P);
   if (rc) {
@@ -608,6 +682,10 @@ GemmArgs gemm_args(const sht_plan_s* P, bool analysis, const void* spec_in, void
   g.spec_in = spec_in;
   g.spec_out = spec_out;
   g.ws = P->d_ws;
+  g.seeds = P->d_seeds;
+  g.seed_off = P->d_seedoff;
+  g.rec = P->d_rec;
+  g.rec_off = P->d_recoff;
   return g;
 }
 
@@ -641,7 +719,7 @@ int run_analysis(sht_plan_s* P, const void* grid, void* spec, void* stream, int 
   if (e) return hip_check((hipError_t)e, "zonal analysis launch");
   GemmArgs g = gemm_args(P, true, nullptr, spec);
   prof_mark(P, stream, ST_LEG_A, true);
-  e = launch_legendre(P->form, true, g, P->ncb_fwd, stream);
+  e = P->otf ? launch_legendre_analysis_otf(g, stream) : launch_legendre(P->form, true, g, P->ncb_fwd, stream);
   prof_mark(P, stream, ST_LEG_A, false);
   if (e) return hip_check((hipError_t)e, "Legendre analysis launch");
   return SHT_OK;

@@ -49,6 +49,7 @@ struct LevelDesc {
   long long ws_off;    // element offset in the workspace
   const void* tw;      // I twiddles exp(-2 pi i k / I), complex, data type
   const double* wrow;  // Jh quadrature weights of the northern rows
+  const double* murow; // Kp nodes mu_j of the northern rows, zero past Jh (analysis with generated P~)
 };
 
 struct FftArgs {
@@ -85,6 +86,14 @@ struct GemmArgs {
   const void* spec_in;         // synthesis: spectra
   void* spec_out;              // analysis: spectra
   void* ws;                    // workspace
+  // analysis with P~ generated in the kernel (FP64): per (level, m) the two
+  // seed rows P~_{m+16g}, P~_{m+16g+1} of every 16-degree group g, each Kp
+  // long, and the recurrence coefficients (A_r, B_r) of the rows r = n - m,
+  // P~_n = A_r mu P~_{n-1} - B_r P~_{n-2}
+  const double* seeds;
+  const long long* seed_off;
+  const double* rec;
+  const long long* rec_off;
 };
 
 // ---- kernel launchers (sht_fft.hip, sht_legendre.hip) ----
@@ -97,6 +106,7 @@ struct GemmArgs {
 int zonal_fields_per_block(int form, int nlev, int N, int J, int I, int F);
 int launch_zonal(int form, bool analysis, const FftArgs& a, int maxN, void* stream);
 int launch_legendre(int form, bool analysis, const GemmArgs& g, int ncb, void* stream);
+int launch_legendre_analysis_otf(const GemmArgs& g, void* stream);
 // Transfers between truncations and nested grids (sht_transfer.hip).
 int launch_retruncate(int Nin, int Nout, int F, bool dbl, const void* in, void* out, void* stream);
 int launch_inject(int Jf, int If, int Jc, int Ic, int F, int rs, int r0, int cs, bool dbl, const void* fine,

@@ -269,6 +269,99 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
 }
 
 // ---------------------------------------------------------------------------
+// analysis with P~ generated in the kernel (FP64; plan option otf).
+// Same tiles and output as the FP64 analysis with one column block: 128
+// rows r = n - m by 16 columns.  Per K block of 32 latitudes, wave w runs
+// the three-term recurrence of Sec. 4.1 (in the form
+// P~_n = A_r mu P~_{n-1} - B_r P~_{n-2}) for the 16 rows 16 w .. 16 w + 15
+// of the tile, one latitude per lane, from the two stored seed rows of its
+// 16-degree group, and writes them to LDS; with the workspace block (both
+// parities) staged beside them, each wave then runs the MFMA products of
+// the ordinary kernel (rows 32 q + 2 i + p) with both operands from LDS.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(512) void k_legendre_analysis_otf(const GemmArgs g) {
+  constexpr int KB = 32, PP = KB + 1, BP = 17;
+  __shared__ double Ps[128 * PP];      // generated rows of the tile: [row][latitude]
+  __shared__ double Bs[2 * KB * BP];   // workspace block: [parity][latitude][column]
+
+  const Tile t = g.tiles[blockIdx.x];
+  if (t.level < 0) return;
+  const LevelDesc& L = g.lev[t.level];
+  const int N = L.N, m = t.m;
+  const int nm = N - m + 1;
+  const int r0 = t.rb * 128;
+  const int c0 = t.cb * 16;
+  const int Kp = L.Kp;
+  const long long Cp = L.Cp;
+  const long long plane = (long long)Kp * Cp;
+  const double* wsm = static_cast<const double*>(g.ws) + L.ws_off + (2LL * m) * plane + c0;
+
+  const int tid = threadIdx.x;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  const int p = w & 1, q = w >> 1;
+  const int li = lane & 15, lg = lane >> 4;
+  // this wave's 16-degree group: rows 16 w .. 16 w + 15 of the tile
+  const int gi = t.rb * 8 + w;
+  const int rg = 16 * gi;
+  const bool gen = rg < nm;
+  const double* seed = g.seeds + g.seed_off[L.m_base + m] + (gen ? (long long)(2 * gi) * Kp : 0);
+  const double* rec = g.rec + g.rec_off[L.m_base + m];
+
+  f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+  const int nkb = Kp / KB;
+  for (int kb = 0; kb < nkb; ++kb) {
+    if (lane < KB) {
+      const int j = kb * KB + lane;
+      double* dst = Ps + (16 * w) * PP + lane;
+      if (gen) {
+        const double mu = L.murow[j];
+        double x0 = seed[j], x1 = rg + 1 < nm ? seed[Kp + j] : 0.0;
+        dst[0] = x0;
+        dst[PP] = x1;
+#pragma unroll
+        for (int s2 = 2; s2 < 16; ++s2) {
+          const int r = rg + s2;
+          const double x2 = r < nm ? rec[2 * r] * mu * x1 - rec[2 * r + 1] * x0 : 0.0;
+          dst[s2 * PP] = x2;
+          x0 = x1;
+          x1 = x2;
+        }
+      } else {
+#pragma unroll
+        for (int s2 = 0; s2 < 16; ++s2) dst[s2 * PP] = 0.0;
+      }
+    }
+    for (int e = tid; e < 2 * KB * 16; e += 512) {
+      const int par = e / (KB * 16), rem = e - par * (KB * 16);
+      const int k = rem >> 4, c = rem & 15;
+      Bs[(par * KB + k) * BP + c] = wsm[par * plane + (long long)(kb * KB + k) * Cp + c];
+    }
+    __syncthreads();
+    const double* Ap = Ps + (32 * q + 2 * li + p) * PP + lg;
+    const double* Bp = Bs + (p * KB + lg) * BP + li;
+#pragma unroll
+    for (int kk = 0; kk < KB / 4; ++kk) acc = mfma16(Ap[4 * kk], Bp[4 * kk * BP], acc);
+    __syncthreads();
+  }
+
+  double* spec = static_cast<double*>(g.spec_out) + L.spec_off;
+  const long long nc = (long long)(N + 1) * (N + 2) / 2;
+  const long long base = spec_idx(N, m, m);
+  const int c = c0 + li, f = c >> 1;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int r = r0 + 32 * q + 2 * out_row<double>(lg, i) + p;
+    if (r < nm && f < L.F) spec[((long long)f * nc + base + r) * 2 + (c & 1)] = acc[i];
+  }
+}
+
+int launch_legendre_analysis_otf(const GemmArgs& g, void* stream) {
+  if (g.ntiles <= 0) return (int)hipSuccess;
+  hipLaunchKernelGGL(k_legendre_analysis_otf, dim3(g.ntiles), dim3(512), 0, static_cast<hipStream_t>(stream), g);
+  return (int)hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // synthesis: S_p[j][c] = sum_{r of parity p} P[r][j] * a[r][c]
 // tile = 128 latitudes j x BN = 16*NCB columns, both parities, 8 waves.
 // Wave w: parity p = w & 1, latitude quarter q = w >> 1; it owns the 32

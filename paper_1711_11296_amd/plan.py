@@ -33,11 +33,13 @@ class Plan:
     hierarchy run together (one Legendre launch per direction for all levels).  grid: "cc_poles", "fejer2" or "fejer1";
     form: "fp64", "fp32" or "bf16x6".  reduced: leave out, per m, the polar
     latitudes where every |P~_n^m| < 1e-16 (the reduced transform of
-    Sec. 4.1; see sht_options.reduced).
+    Sec. 4.1; see sht_options.reduced).  otf (FP64 form only): the
+    analysis generates P~ from two stored seed rows per 16 degrees instead
+    of reading the table (see sht_options.otf).
     """
 
     def __init__(self, N=None, J=None, I=None, nfields=None, *, levels=None, grid="cc_poles",
-                 form="fp64", autotune=False, use_graph=False, reduced=False):
+                 form="fp64", autotune=False, use_graph=False, reduced=False, otf=False):
         import torch
         lib = _lib.load()
         if levels is None:
@@ -46,7 +48,7 @@ class Plan:
         self.grid_kind = grid
         self.form = form
         self.dtype = torch.float64 if form == "fp64" else torch.float32
-        opts = _lib.Options(_lib.GRID[grid], _lib.FORM[form], int(autotune), int(use_graph), int(reduced))
+        opts = _lib.Options(_lib.GRID[grid], _lib.FORM[form], int(autotune), int(use_graph), int(reduced), int(otf))
         h = ctypes.c_void_p()
         n = len(self.levels)
         arr = lambda k: (ctypes.c_int * n)(*[lv[k] for lv in self.levels])  # noqa: E731

@@ -1,0 +1,87 @@
+"""The FP64 analysis with P~ generated in the kernel (plan option otf):
+the three-term recurrence of Sec. 4.1 run from two stored seed rows per 16
+degrees.  Checked against the oracle (several tiles, ragged row tiles and
+column tiles, every grid kind, a multi-level plan) and against the
+table-reading kernel; invalid combinations are refused."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1711_11296_amd import Plan, SHTError, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.cpu().double().numpy()
+
+
+def _rel(x, y):
+    return float(np.linalg.norm(x - y) / np.linalg.norm(y))
+
+
+@pytest.mark.parametrize("kind,N,J,I,F", [("cc_poles", 21, 43, 64, 1), ("fejer2", 200, 401, 480, 3),
+                                          ("gauss", 300, 301, 640, 2), ("fejer1", 100, 150, 216, 9),
+                                          ("cc_poles", 15, 5, 32, 4)])
+def test_otf_analysis_matches_oracle(kind, N, J, I, F):
+    g = torch.from_numpy(inputs.random_grid(F, J, I, seed=N + J)).to("cuda:0")
+    p = Plan(N, J, I, F, grid=kind, form="fp64", otf=True)
+    s = _host(p.forward(g))
+    ref = O.forward(_host(g), N, kind)
+    assert _rel(s, ref) < 1e-12
+    q = Plan(N, J, I, F, grid=kind, form="fp64")
+    assert _rel(s, _host(q.forward(g))) < 1e-13
+    # the synthesis of an otf plan is the ordinary one
+    a = torch.from_numpy(inputs.random_spectra(N, F, seed=3, profile="inv1")).to("cuda:0")
+    assert np.array_equal(_host(p.inverse(a)), _host(q.inverse(a)))
+    p.close()
+    q.close()
+
+
+def test_otf_multilevel():
+    levels = [(64, 129, 200, 3), (128, 257, 400, 2), (33, 20, 100, 5)]
+    p = Plan(levels=levels, grid="cc_poles", form="fp64", otf=True)
+    q = Plan(levels=levels, grid="cc_poles", form="fp64")
+    g = torch.from_numpy(np.random.default_rng(1).standard_normal(p.grid_elems)).to("cuda:0")
+    s, s0 = _host(p.forward(g)), _host(q.forward(g))
+    gh = _host(g)
+    for k, (N, J, I, F) in enumerate(levels):
+        go, so = p.grid_offsets[k], p.spec_offsets[k]
+        n = F * (N + 1) * (N + 2)
+        ref = O.forward(gh[go:go + F * J * I].reshape(F, J, I), N, "cc_poles")
+        assert _rel(s[so:so + n].reshape(ref.shape), ref) < 1e-12, levels[k]
+    assert _rel(s, s0) < 1e-13
+    p.close()
+    q.close()
+
+
+def test_otf_tl1439_matches_table_kernel():
+    """The reference grid of the aliasing experiment (Gaussian, N = 1439,
+    J = 1440, 3 fields): the generated analysis equals the table-reading one
+    to rounding, and sampled outputs match the oracle."""
+    N, J, I, F = 1439, 1440, 2880, 3
+    g = torch.from_numpy(inputs.random_grid(F, J, I, seed=9)).to("cuda:0")
+    p = Plan(N, J, I, F, grid="gauss", form="fp64", otf=True)
+    s = _host(p.forward(g))
+    p.close()
+    q = Plan(N, J, I, F, grid="gauss", form="fp64")
+    s0 = _host(q.forward(g))
+    q.close()
+    assert _rel(s, s0) < 1e-12
+    gh = _host(g)[1]
+    for mm, ns in ((0, [0, 700, 1439]), (5, [5, 1000]), (1400, [1400, 1439])):
+        ref = O.forward_sample(gh, N, "gauss", mm, ns)
+        got = np.array([s[1][O.spec_index(N, mm, k)] for k in ns])
+        assert np.max(np.abs(got - ref)) < 1e-12 * np.max(np.abs(s[1])), (mm, ns)
+
+
+def test_otf_refused_outside_fp64():
+    with pytest.raises(SHTError):
+        Plan(21, 43, 64, 1, form="fp32", otf=True)
+    with pytest.raises(SHTError):
+        Plan(21, 43, 64, 1, form="fp64", otf=True, reduced=True)
+    with pytest.raises(SHTError):
+        Plan(21, 43, 64, 1, form="fp64", otf=True, autotune=True)
