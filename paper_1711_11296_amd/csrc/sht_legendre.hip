@@ -307,15 +307,33 @@ __global__ __launch_bounds__(512) void k_legendre_analysis_otf(const GemmArgs g)
   const double* seed = g.seeds + g.seed_off[L.m_base + m] + (gen ? (long long)(2 * gi) * Kp : 0);
   const double* rec = g.rec + g.rec_off[L.m_base + m];
 
+  // operands of the next K block (seed values, node, workspace elements)
+  // are fetched into registers while the matrix cores work on this one
+  double smu = 0.0, sx0 = 0.0, sx1 = 0.0, bv[2];
+  auto fetch = [&](int kb) __attribute__((always_inline)) {
+    if (gen && lane < KB) {
+      const int j = kb * KB + lane;
+      smu = L.murow[j];
+      sx0 = seed[j];
+      sx1 = rg + 1 < nm ? seed[Kp + j] : 0.0;
+    }
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int idx = tid + e * 512;  // 2 * KB * 16 = 1024 elements
+      const int par = idx / (KB * 16), rem = idx - par * (KB * 16);
+      bv[e] = wsm[par * plane + (long long)(kb * KB + (rem >> 4)) * Cp + (rem & 15)];
+    }
+  };
+
   f64x4 acc = {0.0, 0.0, 0.0, 0.0};
   const int nkb = Kp / KB;
+  fetch(0);
   for (int kb = 0; kb < nkb; ++kb) {
     if (lane < KB) {
-      const int j = kb * KB + lane;
       double* dst = Ps + (16 * w) * PP + lane;
       if (gen) {
-        const double mu = L.murow[j];
-        double x0 = seed[j], x1 = rg + 1 < nm ? seed[Kp + j] : 0.0;
+        const double mu = smu;
+        double x0 = sx0, x1 = sx1;
         dst[0] = x0;
         dst[PP] = x1;
 #pragma unroll
@@ -331,12 +349,14 @@ __global__ __launch_bounds__(512) void k_legendre_analysis_otf(const GemmArgs g)
         for (int s2 = 0; s2 < 16; ++s2) dst[s2 * PP] = 0.0;
       }
     }
-    for (int e = tid; e < 2 * KB * 16; e += 512) {
-      const int par = e / (KB * 16), rem = e - par * (KB * 16);
-      const int k = rem >> 4, c = rem & 15;
-      Bs[(par * KB + k) * BP + c] = wsm[par * plane + (long long)(kb * KB + k) * Cp + c];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int idx = tid + e * 512;
+      const int par = idx / (KB * 16), rem = idx - par * (KB * 16);
+      Bs[(par * KB + (rem >> 4)) * BP + (rem & 15)] = bv[e];
     }
     __syncthreads();
+    if (kb + 1 < nkb) fetch(kb + 1);
     const double* Ap = Ps + (32 * q + 2 * li + p) * PP + lg;
     const double* Bp = Bs + (p * KB + lg) * BP + li;
 #pragma unroll
