@@ -93,11 +93,10 @@ typedef struct {
                      FP64 analysis; 128 in the synthesis).  The terms left
                      out are below 1e-16 relative. */
   int otf;        /* nonzero (FP64 form only, not with reduced or
-                     autotune): the analysis generates P~_n^m in the kernel
-                     by the three-term recurrence (Sec. 4.1) from two stored
-                     seed rows per 16 degrees instead of reading the table,
-                     cutting its table traffic eightfold; the synthesis
-                     still reads the table. */
+                     autotune): both Legendre kernels generate P~_n^m by the
+                     three-term recurrence (Sec. 4.1) from two stored seed
+                     rows per 16 degrees instead of reading a table; the
+                     plan keeps no table (1/8 of its size in seed rows). */
 } sht_options;
 
 enum {

@@ -302,6 +302,7 @@ void fill_table_level(const LevelDesc& L, const double* mu, const double* sint,
                 sd[(size_t)(2 * g + t2) * Kp + j] = (r < nm && j < Jh) ? col[(size_t)r * Jh + j] : 0.0;
             }
         }
+        if (!dst) continue;  // generated P~: seed rows only
         T* blk = dst + off_a[m];
         const int R = (int)roundup(nm, 128);
         constexpr int KB = sizeof(T) == 4 ? 32 : 16, E = 16 / (int)sizeof(T);
@@ -447,8 +448,9 @@ int build_plan(int nlev, const int* Nv, const int* Jv, const int* Iv, const int*
   P->grid_elems = (size_t)goff;
   P->spec_elems = (size_t)soff;
   P->ws_elems = (size_t)woff;
-  P->table_elems = (size_t)tab;
-  P->table_syn_elems = (size_t)tabs;
+  // with generated P~ no table copy is kept (seed rows only)
+  P->table_elems = P->otf ? 0 : (size_t)tab;
+  P->table_syn_elems = P->otf ? 0 : (size_t)tabs;
   // bytes per table element (the split form reads the FP32 copies)
   const size_t tel = P->elem;
   P->table_bytes = (P->table_elems + P->table_syn_elems) * tel;
@@ -491,8 +493,9 @@ int build_plan(int nlev, const int* Nv, const int* Jv, const int* Iv, const int*
     const long long* to = taboff.data() + L.m_base;
     const long long* ts = taboff_syn.data() + L.m_base;
     if (o.form == SHT_FORM_FP64)
-      fill_table_level<double>(L, mu.data(), sint.data(), reinterpret_cast<double*>(htab.data()), to,
-                               reinterpret_cast<double*>(htabs.data()), ts, P->reduced ? P->jst.data() + L.m_base : nullptr,
+      fill_table_level<double>(L, mu.data(), sint.data(), P->otf ? nullptr : reinterpret_cast<double*>(htab.data()), to,
+                               P->otf ? nullptr : reinterpret_cast<double*>(htabs.data()), ts,
+                               P->reduced ? P->jst.data() + L.m_base : nullptr,
                                P->otf ? hseeds.data() : nullptr, seedoff.data() + L.m_base);
     else
       fill_table_level<float>(L, mu.data(), sint.data(), reinterpret_cast<float*>(htab.data()), to,
@@ -543,8 +546,8 @@ int build_plan(int nlev, const int* Nv, const int* Jv, const int* Iv, const int*
     for (int m = 0; m <= L.N; ++m)
       P->flops_kept += 4.0 * (L.N - m + 1) * L.F * (double)(L.Jh - P->jst[L.m_base + m] / kb * kb);
   }
-  // the generated analysis takes one column block
-  if (P->otf) P->ncb_fwd = 1;
+  // the generated-P~ kernels take one column block
+  if (P->otf) P->ncb_fwd = P->ncb_inv = 1;
   std::vector<Tile> sf = build_tiles(P, true, P->ncb_fwd, 0), si = build_tiles(P, false, P->ncb_inv, 0);
   P->ntiles_fwd = (int)sf.size();
   P->ntiles_inv = (int)si.size();
@@ -729,7 +732,7 @@ int run_synthesis(sht_plan_s* P, const void* spec, void* grid, void* stream, int
                   double mscale) {
   GemmArgs g = gemm_args(P, false, spec, nullptr);
   prof_mark(P, stream, ST_LEG_S, true);
-  int e = launch_legendre(P->form, false, g, P->ncb_inv, stream);
+  int e = P->otf ? launch_legendre_synthesis_otf(g, stream) : launch_legendre(P->form, false, g, P->ncb_inv, stream);
   prof_mark(P, stream, ST_LEG_S, false);
   if (e) return hip_check((hipError_t)e, "Legendre synthesis launch");
   FftArgs a = fft_args(P, P->d_ws, grid, use_w, use_inv_I, mscale);

@@ -375,6 +375,116 @@ __global__ __launch_bounds__(512) void k_legendre_analysis_otf(const GemmArgs g)
   }
 }
 
+// Synthesis with P~ generated in the kernel (FP64; plan option otf):
+// S_p[j][c] = sum_{r of parity p} P~[r][j] a[r][c] over blocks of 64 rows.
+// Tile = 128 latitudes x 16 columns.  Per block, wave w regenerates the 16
+// rows of group w & 3 for the latitudes 64 (w >> 2) + lane from the stored
+// seed rows (the node of a lane's latitude stays in a register), the block's
+// spectra are staged beside them, and wave (p, q) runs the MFMA products
+// for its 32 latitudes 32 q + 16 jb + i and parity p.  The next block's seed
+// values and spectra are fetched while the matrix cores run.
+__global__ __launch_bounds__(512) void k_legendre_synthesis_otf(const GemmArgs g) {
+  constexpr int RB = 64, LP = 129, AP = 17;
+  __shared__ double Ps[RB * LP];   // generated rows of the block: [row][latitude]
+  __shared__ double As[RB * AP];   // spectra of the block: [row][column]
+
+  const Tile t = g.tiles[blockIdx.x];
+  if (t.level < 0) return;
+  const LevelDesc& L = g.lev[t.level];
+  const int N = L.N, m = t.m;
+  const int nm = N - m + 1;
+  const int jt = t.rb, c0 = t.cb * 16;
+  const int Kp = L.Kp;
+  const long long Cp = L.Cp;
+  const double* spec = static_cast<const double*>(g.spec_in) + L.spec_off;
+  const long long nc = (long long)(N + 1) * (N + 2) / 2;
+  const long long sbase = spec_idx(N, m, m);
+
+  const int tid = threadIdx.x;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  const int p = w & 1, q = w >> 1;
+  const int li = lane & 15, lg = lane >> 4;
+  const int gsub = w & 3;                 // group of the block this wave generates
+  const int jl = (w >> 2) * 64 + lane;    // latitude of the tile this lane generates
+  const int j = jt * 128 + jl;
+  const bool jin = j < Kp;
+  const double mu = jin ? L.murow[j] : 0.0;
+  const double* seeds = g.seeds + g.seed_off[L.m_base + m];
+  const double* rec = g.rec + g.rec_off[L.m_base + m];
+  const int nblk = (nm + RB - 1) / RB;
+
+  double sx0 = 0.0, sx1 = 0.0, av[2];
+  auto fetch = [&](int b) __attribute__((always_inline)) {
+    const int gi = 4 * b + gsub, rg = 16 * gi;
+    if (jin && rg < nm) {
+      sx0 = seeds[(long long)(2 * gi) * Kp + j];
+      sx1 = rg + 1 < nm ? seeds[(long long)(2 * gi + 1) * Kp + j] : 0.0;
+    }
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int idx = tid + e * 512;  // 64 rows x 16 columns
+      const int r = b * RB + (idx >> 4), cc = c0 + (idx & 15), f = cc >> 1;
+      av[e] = (r < nm && f < L.F) ? spec[((long long)f * nc + sbase + r) * 2 + (cc & 1)] : 0.0;
+    }
+  };
+
+  f64x4 acc[2] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+  fetch(0);
+  for (int b = 0; b < nblk; ++b) {
+    {
+      const int rg = 16 * (4 * b + gsub);
+      double* dst = Ps + (16 * gsub) * LP + jl;
+      if (jin && rg < nm) {
+        double x0 = sx0, x1 = sx1;
+        dst[0] = x0;
+        dst[LP] = x1;
+#pragma unroll
+        for (int s2 = 2; s2 < 16; ++s2) {
+          const int r = rg + s2;
+          const double x2 = r < nm ? rec[2 * r] * mu * x1 - rec[2 * r + 1] * x0 : 0.0;
+          dst[s2 * LP] = x2;
+          x0 = x1;
+          x1 = x2;
+        }
+      } else {
+#pragma unroll
+        for (int s2 = 0; s2 < 16; ++s2) dst[s2 * LP] = 0.0;
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int idx = tid + e * 512;
+      As[(idx >> 4) * AP + (idx & 15)] = av[e];
+    }
+    __syncthreads();
+    if (b + 1 < nblk) fetch(b + 1);
+#pragma unroll
+    for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+      for (int kk = 0; kk < RB / 8; ++kk) {
+        const int rr = 2 * (4 * kk + lg) + p;
+        acc[jb] = mfma16(Ps[rr * LP + 32 * q + 16 * jb + li], As[rr * AP + li], acc[jb]);
+      }
+    __syncthreads();
+  }
+
+  const long long plane = (long long)Kp * Cp;
+  double* ws = static_cast<double*>(g.ws) + L.ws_off + (2LL * m + p) * plane;
+#pragma unroll
+  for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int jj = jt * 128 + 32 * q + 16 * jb + out_row<double>(lg, i);
+      if (jj < L.Jh) ws[(long long)jj * Cp + c0 + li] = acc[jb][i];
+    }
+}
+
+int launch_legendre_synthesis_otf(const GemmArgs& g, void* stream) {
+  if (g.ntiles <= 0) return (int)hipSuccess;
+  hipLaunchKernelGGL(k_legendre_synthesis_otf, dim3(g.ntiles), dim3(512), 0, static_cast<hipStream_t>(stream), g);
+  return (int)hipGetLastError();
+}
+
 int launch_legendre_analysis_otf(const GemmArgs& g, void* stream) {
   if (g.ntiles <= 0) return (int)hipSuccess;
   hipLaunchKernelGGL(k_legendre_analysis_otf, dim3(g.ntiles), dim3(512), 0, static_cast<hipStream_t>(stream), g);

@@ -33,9 +33,9 @@ class Plan:
     hierarchy run together (one Legendre launch per direction for all levels).  grid: "cc_poles", "fejer2" or "fejer1";
     form: "fp64", "fp32" or "bf16x6".  reduced: leave out, per m, the polar
     latitudes where every |P~_n^m| < 1e-16 (the reduced transform of
-    Sec. 4.1; see sht_options.reduced).  otf (FP64 form only): the
-    analysis generates P~ from two stored seed rows per 16 degrees instead
-    of reading the table (see sht_options.otf).
+    Sec. 4.1; see sht_options.reduced).  otf (FP64 form only): both
+    Legendre kernels generate P~ from two stored seed rows per 16 degrees
+    instead of reading a table (see sht_options.otf).
     """
 
     def __init__(self, N=None, J=None, I=None, nfields=None, *, levels=None, grid="cc_poles",

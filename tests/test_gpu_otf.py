@@ -1,8 +1,9 @@
-"""The FP64 analysis with P~ generated in the kernel (plan option otf):
-the three-term recurrence of Sec. 4.1 run from two stored seed rows per 16
-degrees.  Checked against the oracle (several tiles, ragged row tiles and
-column tiles, every grid kind, a multi-level plan) and against the
-table-reading kernel; invalid combinations are refused."""
+"""The FP64 Legendre kernels with P~ generated in the kernel (plan option
+otf): the three-term recurrence of Sec. 4.1 run from two stored seed rows
+per 16 degrees, no table kept.  Both directions are checked against the
+oracle (several tiles, ragged row, latitude and column tiles, every grid
+kind, a multi-level plan) and against the table-reading kernels; invalid
+combinations are refused."""
 
 import numpy as np
 import pytest
@@ -34,9 +35,11 @@ def test_otf_analysis_matches_oracle(kind, N, J, I, F):
     assert _rel(s, ref) < 1e-12
     q = Plan(N, J, I, F, grid=kind, form="fp64")
     assert _rel(s, _host(q.forward(g))) < 1e-13
-    # the synthesis of an otf plan is the ordinary one
     a = torch.from_numpy(inputs.random_spectra(N, F, seed=3, profile="inv1")).to("cuda:0")
-    assert np.array_equal(_host(p.inverse(a)), _host(q.inverse(a)))
+    x = _host(p.inverse(a))
+    assert _rel(x, O.inverse(_host(a), N, J, I, kind)) < 1e-12
+    assert _rel(x, _host(q.inverse(a))) < 1e-13
+    assert p.table_bytes == 0 < q.table_bytes
     p.close()
     q.close()
 
@@ -47,6 +50,8 @@ def test_otf_multilevel():
     q = Plan(levels=levels, grid="cc_poles", form="fp64")
     g = torch.from_numpy(np.random.default_rng(1).standard_normal(p.grid_elems)).to("cuda:0")
     s, s0 = _host(p.forward(g)), _host(q.forward(g))
+    a = torch.from_numpy(np.random.default_rng(2).standard_normal(p.spec_elems)).to("cuda:0")
+    assert _rel(_host(p.inverse(a)), _host(q.inverse(a))) < 1e-13
     gh = _host(g)
     for k, (N, J, I, F) in enumerate(levels):
         go, so = p.grid_offsets[k], p.spec_offsets[k]
@@ -60,17 +65,23 @@ def test_otf_multilevel():
 
 def test_otf_tl1439_matches_table_kernel():
     """The reference grid of the aliasing experiment (Gaussian, N = 1439,
-    J = 1440, 3 fields): the generated analysis equals the table-reading one
-    to rounding, and sampled outputs match the oracle."""
+    J = 1440, 3 fields): both generated directions equal the table-reading
+    kernels to rounding, and sampled outputs match the oracle."""
     N, J, I, F = 1439, 1440, 2880, 3
     g = torch.from_numpy(inputs.random_grid(F, J, I, seed=9)).to("cuda:0")
+    a = torch.from_numpy(inputs.random_spectra(N, F, seed=10, profile="uniform13")).to("cuda:0")
     p = Plan(N, J, I, F, grid="gauss", form="fp64", otf=True)
     s = _host(p.forward(g))
+    x = _host(p.inverse(a))
     p.close()
     q = Plan(N, J, I, F, grid="gauss", form="fp64")
     s0 = _host(q.forward(g))
+    x0 = _host(q.inverse(a))
     q.close()
     assert _rel(s, s0) < 1e-12
+    assert _rel(x, x0) < 1e-12
+    for j in (100, 700):
+        assert _rel(x[0, j], O.inverse_sample_row(_host(a)[0], N, J, I, "gauss", j)) < 1e-12, j
     gh = _host(g)[1]
     for mm, ns in ((0, [0, 700, 1439]), (5, [5, 1000]), (1400, [1400, 1439])):
         ref = O.forward_sample(gh, N, "gauss", mm, ns)
