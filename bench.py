@@ -56,7 +56,7 @@ def parse():
                     help="time the residual and restriction steps of the App. C two-grid cycle instead "
                          "(Tc479 fine, Tc239 coarse, 100 fields; own JSON line)")
     ap.add_argument("--otf", action="store_true",
-                    help="with --aliasing: FP64 analyses generate P~ from seed rows (plan option otf)")
+                    help="with --aliasing: the FP64 Legendre kernels generate P~ from seed rows (plan option otf)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy a 1 GiB buffer 3 times (calibrates HBM byte counters)")
     return ap.parse_args()
