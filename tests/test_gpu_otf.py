@@ -26,7 +26,7 @@ def _rel(x, y):
 
 @pytest.mark.parametrize("kind,N,J,I,F", [("cc_poles", 21, 43, 64, 1), ("fejer2", 200, 401, 480, 3),
                                           ("gauss", 300, 301, 640, 2), ("fejer1", 100, 150, 216, 9),
-                                          ("cc_poles", 15, 5, 32, 4)])
+                                          ("cc_poles", 15, 5, 32, 4), ("cc_poles", 0, 3, 4, 2)])
 def test_otf_analysis_matches_oracle(kind, N, J, I, F):
     g = torch.from_numpy(inputs.random_grid(F, J, I, seed=N + J)).to("cuda:0")
     p = Plan(N, J, I, F, grid=kind, form="fp64", otf=True)
