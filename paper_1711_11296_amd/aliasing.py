@@ -50,10 +50,10 @@ class NonlinearTerms:
         self.plan.close()
 
 
-def nonlinear_spectra(U, V, W, N, J, I, grid, form="fp64"):
-    """One-off NonlinearTerms(N, J, I, grid, form)(U, V, W), synchronised."""
+def nonlinear_spectra(U, V, W, N, J, I, grid, form="fp64", otf=False):
+    """One-off NonlinearTerms(N, J, I, grid, form, otf)(U, V, W), synchronised."""
     import torch
-    t = NonlinearTerms(N, J, I, grid, form)
+    t = NonlinearTerms(N, J, I, grid, form, otf)
     try:
         out = t(U, V, W)
         torch.cuda.current_stream(out.device).synchronize()
@@ -84,19 +84,19 @@ def grids(N_trunc):
     }
 
 
-def experiment(N_trunc=479, seed=0, form="fp64", device="cuda:0"):
+def experiment(N_trunc=479, seed=0, form="fp64", device="cuda:0", otf=False):
     """Run the experiment at truncation N_trunc with the random spectra of
     Sec. 4.2 (real and imaginary parts uniform on [(n+1)^(-1/3),
     2 (n+1)^(-1/3)]).  Returns a dict: for "gauss_linear" and "cc_cubic",
     the normalised errors [2 (quadratic, cubic), ncoef] against the
     reference grid, plus "spectra" (device tensors of every grid) and the
-    input spectra."""
+    input spectra.  otf: FP64 plans generate P~ instead of reading tables."""
     import torch
     U, V, W = [torch.from_numpy(inputs.random_spectra(N_trunc, 1, seed=seed + k, profile="uniform13")).to(device)
                for k in range(3)]
     out = {"U": U, "V": V, "W": W, "spectra": {}}
     for name, (N, J, I, kind) in grids(N_trunc).items():
-        out["spectra"][name] = nonlinear_spectra(U, V, W, N, J, I, kind, form)
+        out["spectra"][name] = nonlinear_spectra(U, V, W, N, J, I, kind, form, otf)
     ref = out["spectra"]["reference"].cpu().double().numpy()
     for name in ("gauss_linear", "cc_cubic"):
         out[name] = normalised_error(out["spectra"][name].cpu().double().numpy(), ref)

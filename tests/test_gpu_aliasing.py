@@ -95,12 +95,15 @@ def _oracle_nonlinear(U, V, W, N, J, I, kind):
     return O.retruncate(O.forward(np.concatenate([q, c]), N, kind), N, Nt)
 
 
-def test_aliasing_experiment_small_matches_oracle():
+@pytest.mark.parametrize("otf", [False, True])
+def test_aliasing_experiment_small_matches_oracle(otf):
     """The Sec. 4.2 experiment at N_trunc = 23 (reference Gaussian grid
-    N = 71, J = 72; N_trunc + 1 = 24 keeps every I a product of 2, 3, 5): every grid's UV and UVW spectra agree with the oracle's
-    run of the same steps, and the normalised errors follow."""
+    N = 71, J = 72; N_trunc + 1 = 24 keeps every I a product of 2, 3, 5):
+    every grid's UV and UVW spectra agree with the oracle's run of the same
+    steps, with tables or with generated P~, and the normalised errors
+    follow."""
     from paper_1711_11296_amd import aliasing
-    res = aliasing.experiment(N_trunc=23, seed=3)
+    res = aliasing.experiment(N_trunc=23, seed=3, otf=otf)
     U, V, W = (_host(res[k]) for k in "UVW")
     for name, (N, J, I, kind) in aliasing.grids(23).items():
         ref = _oracle_nonlinear(U, V, W, N, J, I, kind)
