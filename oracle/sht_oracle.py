@@ -283,7 +283,9 @@ def zonal_synthesis(X, I):
     s = np.sin(al)
     c[1:] *= 2.0
     s[1:] *= 2.0
-    return X.real @ c - X.imag @ s
+    # contiguous copies of the real and imaginary parts, so that the matrix
+    # products run in BLAS (a strided view takes numpy's plain loop)
+    return np.ascontiguousarray(X.real) @ c - np.ascontiguousarray(X.imag) @ s
 
 
 # --------------------------------------------------------------------------
@@ -365,16 +367,16 @@ def forward_adjoint(spec_bar, N, J, I, kind):
     _, mu, sint = nodes(J, kind)
     w = weights(J, kind)
     al = _phase(N, I)
-    out = np.zeros((F, J, I))
+    br = np.zeros((F, J, N + 1))       # sum_n abar_re(n, m) P~_n^m(mu_j)
+    bi = np.zeros((F, J, N + 1))       # sum_n abar_im(n, m) P~_n^m(mu_j), 0 for m = 0
     for m in range(N + 1):
         P = alf_m(N, m, mu, sint)
         k0 = spec_index(N, m, m)
-        br = spec_bar[:, k0:k0 + N - m + 1, 0] @ P          # [F, J]
-        bi = spec_bar[:, k0:k0 + N - m + 1, 1] @ P
-        if m == 0:
-            bi = np.zeros_like(bi)
-        out += br[:, :, None] * np.cos(al[m])[None, None, :]
-        out -= bi[:, :, None] * np.sin(al[m])[None, None, :]
+        br[:, :, m] = spec_bar[:, k0:k0 + N - m + 1, 0] @ P
+        if m > 0:
+            bi[:, :, m] = spec_bar[:, k0:k0 + N - m + 1, 1] @ P
+    # the sum over m of br cos(m lambda_i) - bi sin(m lambda_i), as matrix products
+    out = br @ np.cos(al) - bi @ np.sin(al)
     return out * (w / I)[None, :, None]
 
 
