@@ -217,6 +217,16 @@ int sht_plan_destroy(sht_plan_t plan);
 const char* sht_last_error(void);
 
 /*
+ * Device bytes held by all live plans of the process (tables, workspaces,
+ * schedules), written to *out.  A plan whose construction fails frees what
+ * it had allocated, so this is unchanged by a failed sht_plan_ex.  The
+ * environment variable SHT_TEST_MAX_BYTES, when set, caps this total: a plan
+ * whose allocations would exceed it fails with SHT_ENOMEM (for tests of the
+ * out-of-memory path).  SHT_EINVAL if out is NULL.
+ */
+int sht_device_bytes(size_t* out);
+
+/*
  * Transfers for multigrid cycles (App. C: restriction and prolongation
  * between a finer and a coarser level), enqueued on `stream`; no plan
  * needed.  dbl nonzero: double elements, else float.  Buffers are device

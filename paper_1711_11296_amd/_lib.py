@@ -24,7 +24,7 @@ EXPORTS = ["sht_plan", "sht_plan_ex", "sht_plan_multi", "sht_forward", "sht_inve
            "sht_forward_adjoint", "sht_inverse_adjoint", "sht_plan_query",
            "sht_plan_tables", "sht_plan_destroy", "sht_last_error", "sht_host_tables",
            "sht_plan_profile", "sht_plan_profile_read", "sht_spec_retruncate", "sht_grid_inject",
-           "sht_grid_product", "sht_spec_laplacian", "sht_grid_residual"]
+           "sht_grid_product", "sht_spec_laplacian", "sht_grid_residual", "sht_device_bytes"]
 
 
 class SHTError(RuntimeError):
@@ -91,6 +91,8 @@ def load(require_torch=True):
     lib.sht_grid_inject.argtypes = [c_int, c_int, c_int, c_int, c_int, c_int, c_int, vp, vp, vp]
     lib.sht_host_tables.restype = c_int
     lib.sht_host_tables.argtypes = [c_int, c_int, c_int, dp, dp, dp]
+    lib.sht_device_bytes.restype = c_int
+    lib.sht_device_bytes.argtypes = [ctypes.POINTER(ctypes.c_size_t)]
     _lib = lib
     return lib
 
@@ -103,3 +105,11 @@ def check(rc):
 
 def last_error():
     return load(False).sht_last_error().decode()
+
+
+def device_bytes():
+    """Device bytes held by all live plans of the process."""
+    lib = load(False)
+    v = ctypes.c_size_t(0)
+    check(lib.sht_device_bytes(ctypes.byref(v)))
+    return int(v.value)

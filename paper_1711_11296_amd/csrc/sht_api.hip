@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -95,6 +96,8 @@ struct sht_plan_s {
     void* out;
     hipGraph_t graph;
     hipGraphExec_t exec;
+    hipEvent_t done;  // recorded after each launch; waited on before the exec is destroyed
+    bool launched;
   };
   std::vector<GraphEntry> graphs;
   bool capturing = false;
@@ -105,33 +108,45 @@ struct sht_plan_s {
 
 namespace {
 
-size_t g_alloc_total = 0;
+// device bytes held by all live plans (checked against SHT_TEST_MAX_BYTES);
+// plans may be built and destroyed from several threads
+std::atomic<size_t> g_alloc_total{0};
 
-// Device allocation with an optional test limit (SHT_TEST_MAX_BYTES).
+// Device allocation with an optional test limit (SHT_TEST_MAX_BYTES, read at
+// every call): the bytes are reserved in g_alloc_total before hipMalloc and
+// released again if it fails.
 int dev_alloc(sht_plan_s* P, void** out, size_t bytes) {
-  static const char* lim_s = std::getenv("SHT_TEST_MAX_BYTES");
-  size_t lim = lim_s ? (size_t)std::strtoull(lim_s, nullptr, 10) : 0;
-  if (lim && g_alloc_total + bytes > lim)
-    return fail(SHT_ENOMEM, "device allocation of " + std::to_string(bytes) +
-                                " bytes exceeds SHT_TEST_MAX_BYTES");
+  const char* lim_s = std::getenv("SHT_TEST_MAX_BYTES");
+  const size_t lim = lim_s ? (size_t)std::strtoull(lim_s, nullptr, 10) : 0;
+  size_t cur = g_alloc_total.load();
+  do {
+    if (lim && cur + bytes > lim)
+      return fail(SHT_ENOMEM, "device allocation of " + std::to_string(bytes) +
+                                  " bytes exceeds SHT_TEST_MAX_BYTES");
+  } while (!g_alloc_total.compare_exchange_weak(cur, cur + bytes));
   void* p = nullptr;
   hipError_t e = hipMalloc(&p, bytes ? bytes : 16);
   if (e != hipSuccess) {
     (void)hipGetLastError();
+    g_alloc_total -= bytes;
     return fail(SHT_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
   }
-  g_alloc_total += bytes;
   P->alloc_bytes += bytes;
   P->allocs.push_back(p);
   *out = p;
   return SHT_OK;
 }
 
+void destroy_graph_entry(sht_plan_s::GraphEntry& g) {
+  // the exec may still run on the caller's stream: wait for its last launch
+  if (g.launched) (void)hipEventSynchronize(g.done);
+  (void)hipGraphExecDestroy(g.exec);
+  (void)hipGraphDestroy(g.graph);
+  if (g.done) (void)hipEventDestroy(g.done);
+}
+
 void free_plan(sht_plan_s* P) {
-  for (auto& g : P->graphs) {
-    (void)hipGraphExecDestroy(g.exec);
-    (void)hipGraphDestroy(g.graph);
-  }
+  for (auto& g : P->graphs) destroy_graph_entry(g);
   P->graphs.clear();
   if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
   P->cap_stream = nullptr;
@@ -712,15 +727,17 @@ void prof_mark(sht_plan_s* P, void* stream, int stage, bool start) {
   if (start) P->ev_stage.push_back(stage);
 }
 
-// grid -> spec through the zonal analysis (row scale and m scale given)
+// grid -> spec through the zonal analysis (row scale and m scale given);
+// ws is the workspace to use
 int run_analysis(sht_plan_s* P, const void* grid, void* spec, void* stream, int use_w, int use_inv_I,
-                 double mscale) {
-  FftArgs a = fft_args(P, grid, P->d_ws, use_w, use_inv_I, mscale);
+                 double mscale, void* ws) {
+  FftArgs a = fft_args(P, grid, ws, use_w, use_inv_I, mscale);
   prof_mark(P, stream, ST_ZONAL_A, true);
   int e = launch_zonal(P->form, true, a, P->maxN, stream);
   prof_mark(P, stream, ST_ZONAL_A, false);
   if (e) return hip_check((hipError_t)e, "zonal analysis launch");
   GemmArgs g = gemm_args(P, true, nullptr, spec);
+  g.ws = ws;
   prof_mark(P, stream, ST_LEG_A, true);
   e = P->otf ? launch_legendre_analysis_otf(g, stream) : launch_legendre(P->form, true, g, P->ncb_fwd, stream);
   prof_mark(P, stream, ST_LEG_A, false);
@@ -747,10 +764,10 @@ enum { DIR_FWD = 0, DIR_INV = 1, DIR_FWD_ADJ = 2, DIR_INV_ADJ = 3 };
 
 int run_eager(sht_plan_s* P, int dir, const void* in, void* out, void* stream) {
   switch (dir) {
-    case DIR_FWD: return run_analysis(P, in, out, stream, 1, 1, 1.0);
+    case DIR_FWD: return run_analysis(P, in, out, stream, 1, 1, 1.0, P->d_ws);
     case DIR_INV: return run_synthesis(P, in, out, stream, 0, 0, 1.0);
     case DIR_FWD_ADJ: return run_synthesis(P, in, out, stream, 1, 1, 0.5);
-    default: return run_analysis(P, in, out, stream, 0, 0, 2.0);
+    default: return run_analysis(P, in, out, stream, 0, 0, 2.0, P->d_ws);
   }
 }
 
@@ -760,8 +777,13 @@ int run_eager(sht_plan_s* P, int dir, const void* in, void* out, void* stream) {
 int run_dir(sht_plan_s* P, int dir, const void* in, void* out, void* stream) {
   if (!P->use_graph) return run_eager(P, dir, in, out, stream);
   for (auto& g : P->graphs)
-    if (g.dir == dir && g.in == in && g.out == out)
-      return hip_check(hipGraphLaunch(g.exec, static_cast<hipStream_t>(stream)), "hipGraphLaunch");
+    if (g.dir == dir && g.in == in && g.out == out) {
+      int rc = hip_check(hipGraphLaunch(g.exec, static_cast<hipStream_t>(stream)), "hipGraphLaunch");
+      if (rc) return rc;
+      rc = hip_check(hipEventRecord(g.done, static_cast<hipStream_t>(stream)), "record graph event");
+      if (!rc) g.launched = true;
+      return rc;
+    }
   int rc = run_eager(P, dir, in, out, stream);
   if (rc) return rc;
   if (!P->cap_stream && (rc = hip_check(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking),
@@ -778,16 +800,19 @@ int run_dir(sht_plan_s* P, int dir, const void* in, void* out, void* stream) {
   }
   P->capturing = false;
   if (!rc) rc = hip_check(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "instantiate graph");
+  hipEvent_t done = nullptr;
+  if (!rc) rc = hip_check(hipEventCreateWithFlags(&done, hipEventDisableTiming), "create graph event");
   if (rc) {
+    if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
     return rc;
   }
+  // at most 16 cached graphs: the oldest goes once its last launch is done
   if (P->graphs.size() >= 16) {
-    (void)hipGraphExecDestroy(P->graphs.front().exec);
-    (void)hipGraphDestroy(P->graphs.front().graph);
+    destroy_graph_entry(P->graphs.front());
     P->graphs.erase(P->graphs.begin());
   }
-  P->graphs.push_back({dir, in, out, graph, exec});
+  P->graphs.push_back({dir, in, out, graph, exec, done, false});
   return SHT_OK;
 }
 
@@ -799,17 +824,33 @@ std::string tune_path() {
   return std::string(h ? h : "/tmp") + "/.cache/sht_tune.txt";
 }
 
+// The key pins everything a cached choice depends on: device architecture,
+// HIP runtime version, the tuner's version, form, every level's sizes and the
+// workspace layout (row length Cp, fields per zonal item).
 std::string tune_key(const sht_plan_s* P) {
   hipDeviceProp_t prop;
   std::string arch = "unknown";
   if (hipGetDeviceProperties(&prop, P->device) == hipSuccess) arch = prop.gcnArchName;
   for (auto& ch : arch)
     if (ch == ' ') ch = '_';
-  std::string k = arch + " v1 form" + std::to_string(P->form) + " lev" + std::to_string(P->nlev);
+  int rt = 0;
+  (void)hipRuntimeGetVersion(&rt);
+  std::string k = arch + " hip" + std::to_string(rt) + " v2 form" + std::to_string(P->form) + " fb" +
+                  std::to_string(P->fb) + " lev" + std::to_string(P->nlev);
   for (int l = 0; l < P->nlev; ++l)
     k += " " + std::to_string(P->lev[l].N) + "," + std::to_string(P->lev[l].J) + "," + std::to_string(P->lev[l].I) +
-         "," + std::to_string(P->lev[l].F);
+         "," + std::to_string(P->lev[l].F) + "," + std::to_string(P->lev[l].Cp);
   return k;
+}
+
+// A column blocking c (16-column units) is admissible for a direction when
+// the kernel takes it and it tiles every level's workspace row exactly with
+// no tile wholly past the last field.
+bool blocking_ok(const sht_plan_s* P, bool analysis, int c) {
+  if (c < 1 || c > max_ncb(P->form, analysis)) return false;
+  for (int l = 0; l < P->nlev; ++l)
+    if (P->lev[l].Cp % (16 * c) || roundup(2LL * P->lev[l].F, 16LL * c) != P->lev[l].Cp) return false;
+  return true;
 }
 
 bool tune_lookup(const std::string& key, int v[4]) {
@@ -852,17 +893,17 @@ int upload_tiles(sht_plan_s* P, bool analysis, const std::vector<Tile>& t) {
 int autotune(sht_plan_s* P) {
   const std::string key = tune_key(P);
   int v[4];
-  if (!tune_lookup(key, v)) {
+  // a cached entry is used only if it passes the same filter as the search
+  // (a stale or foreign line could otherwise leave columns uncomputed)
+  // (the plan's default blocking, which the search keeps when no candidate
+  // passes, is also accepted)
+  const bool cached = tune_lookup(key, v) && (v[0] == P->ncb_fwd || blocking_ok(P, true, v[0])) &&
+                      (v[2] == P->ncb_inv || blocking_ok(P, false, v[2])) && (v[1] == 0 || v[1] == 1) &&
+                      (v[3] == 0 || v[3] == 1);
+  if (!cached) {
     const int all64[] = {1, 2, 4, 8}, all32[] = {1, 2, 4, 5, 8, 10};
     const int* all = P->form == SHT_FORM_FP64 ? all64 : all32;
     const int na = P->form == SHT_FORM_FP64 ? 4 : 6;
-    std::vector<int> cands;
-    for (int k = 0; k < na; ++k) {
-      bool ok = true;
-      for (int l = 0; l < P->nlev; ++l)
-        if (P->lev[l].Cp % (16 * all[k]) || roundup(2LL * P->lev[l].F, 16LL * all[k]) != P->lev[l].Cp) ok = false;
-      if (ok) cands.push_back(all[k]);
-    }
     void* spec = nullptr;
     hipStream_t st = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -878,9 +919,10 @@ int autotune(sht_plan_s* P) {
       const bool analysis = dir == 0;
       float best = 1e30f;
       int bc = analysis ? P->ncb_fwd : P->ncb_inv, bs = 0;
-      for (int c : cands)
+      for (int k = 0; k < na; ++k)
         for (int sched = 0; sched < 2 && !rc; ++sched) {
-          if (c > max_ncb(P->form, analysis)) continue;
+          const int c = all[k];
+          if (!blocking_ok(P, analysis, c)) continue;
           std::vector<Tile> t = build_tiles(P, analysis, c, sched);
           Tile* dt = nullptr;
           if ((rc = hip_check(hipMalloc(reinterpret_cast<void**>(&dt), t.size() * sizeof(Tile)), "tune alloc"))) break;
@@ -931,6 +973,12 @@ int autotune(sht_plan_s* P) {
 extern "C" {
 
 const char* sht_last_error(void) { return g_err.c_str(); }
+
+int sht_device_bytes(size_t* out) {
+  if (!out) return fail(SHT_EINVAL, "out must not be NULL");
+  *out = g_alloc_total.load();
+  return SHT_OK;
+}
 
 int sht_spec_retruncate(int N_in, int N_out, int nfields, int dbl, const void* spec_in, void* spec_out,
                         void* stream) {

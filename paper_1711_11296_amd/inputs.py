@@ -8,6 +8,9 @@ Workloads (each draw in one call, in m-major triangular order):
   * "inv1":  re, im ~ N(0, sigma_n^2) with sigma_n = (n+1)^-1;
   * "k3":    sigma_n = (n+1)^(-3/2) (2n+1)^(-1/2), i.e. an energy spectrum
              E(n) ~ (n+1)^-3 spread over the 2n+1 orders of degree n;
+  * "white": sigma_n = 1, every coefficient of every degree with the same
+             variance, so that an error confined to a few degrees or orders
+             is as visible as one spread over all of them;
   * "uniform13": re, im ~ U[(n+1)^(-1/3), 2 (n+1)^(-1/3)], the random spectra
              of the paper's aliasing experiment (Sec. 4.2).
 Im of every m = 0 coefficient is set to 0 (real fields).
@@ -36,6 +39,8 @@ def sigma(N, profile):
         return 1.0 / (n + 1.0)
     if profile == "k3":
         return (n + 1.0) ** -1.5 * (2.0 * n + 1.0) ** -0.5
+    if profile == "white":
+        return np.ones_like(n)
     raise ValueError("unknown spectral profile %r" % (profile,))
 
 

@@ -33,7 +33,11 @@ class Plan:
     hierarchy run together (one Legendre launch per direction for all levels).  grid: "cc_poles", "fejer2" or "fejer1";
     form: "fp64", "fp32" or "bf16x6".  reduced: leave out, per m, the polar
     latitudes where every |P~_n^m| < 1e-16 (the reduced transform of
-    Sec. 4.1; see sht_options.reduced).  otf (FP64 form only): both
+    Sec. 4.1; see sht_options.reduced).  use_graph: each (direction, input
+    buffer, output buffer) triple is captured into a hipGraph on its first
+    call and replayed afterwards; at most 16 graphs are kept per plan, so pass
+    the same out= buffers on every call (without out= a new output tensor,
+    hence a new capture, may be made each time).  otf (FP64 form only): both
     Legendre kernels generate P~ from two stored seed rows per 16 degrees
     instead of reading a table (see sht_options.otf).
     """
