@@ -164,6 +164,26 @@ int sht_plan_multi(int nlevels, const int* N, const int* J, const int* I,
 /* Analysis, grid -> spec (Sec. 2 eq. dSHT; Sec. 3.1 eq. cc-quad). */
 int sht_forward(sht_plan_t plan, const void* grid, void* spec, void* stream);
 
+/*
+ * sht_forward_noalloc: the analysis of sht_forward, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  It runs the same kernels with the
+ * plan's zonal-to-Legendre workspace replaced by a static device array of
+ * SHT_NOALLOC_WORKSPACE_BYTES (64 MiB) that the library holds on every GPU
+ * it runs on until the process ends; it calls no hipMalloc, hipFree, event,
+ * graph or allocating library routine (a plan built with use_graph runs
+ * eagerly here).  The caller passes the plan (built beforehand), the grid
+ * and the spec as for sht_forward; the result equals sht_forward's.
+ * Every call on one GPU shares that GPU's array, and each call first clears
+ * the part that must start at zero: calls that overlap in time on one GPU
+ * (on different streams, or from different threads) race and must be
+ * ordered by the caller.  Errors: as sht_forward; SHT_EINVAL if the plan's
+ * workspace (SHT_Q_WORKSPACE_BYTES) exceeds SHT_NOALLOC_WORKSPACE_BYTES or
+ * the plan belongs to another device than the current one.
+ */
+#define SHT_NOALLOC_WORKSPACE_BYTES ((size_t)64 << 20)
+int sht_forward_noalloc(sht_plan_t plan, const void* grid, void* spec, void* stream);
+
 /* Synthesis, spec -> grid (Sec. 2 eq. iSHT, eq. iLT). */
 int sht_inverse(sht_plan_t plan, const void* spec, void* grid, void* stream);
 

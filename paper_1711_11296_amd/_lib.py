@@ -24,7 +24,8 @@ EXPORTS = ["sht_plan", "sht_plan_ex", "sht_plan_multi", "sht_forward", "sht_inve
            "sht_forward_adjoint", "sht_inverse_adjoint", "sht_plan_query",
            "sht_plan_tables", "sht_plan_destroy", "sht_last_error", "sht_host_tables",
            "sht_plan_profile", "sht_plan_profile_read", "sht_spec_retruncate", "sht_grid_inject",
-           "sht_grid_product", "sht_spec_laplacian", "sht_grid_residual", "sht_device_bytes"]
+           "sht_grid_product", "sht_spec_laplacian", "sht_grid_residual", "sht_device_bytes",
+           "sht_forward_noalloc"]
 
 
 class SHTError(RuntimeError):
@@ -62,7 +63,7 @@ def load(require_torch=True):
     lib.sht_plan_ex.argtypes = [c_int, c_int, c_int, c_int, ctypes.POINTER(Options), ctypes.POINTER(vp)]
     lib.sht_plan_multi.restype = c_int
     lib.sht_plan_multi.argtypes = [c_int, ip, ip, ip, ip, ctypes.POINTER(Options), ctypes.POINTER(vp)]
-    for name in ("sht_forward", "sht_inverse", "sht_forward_adjoint", "sht_inverse_adjoint"):
+    for name in ("sht_forward", "sht_inverse", "sht_forward_adjoint", "sht_inverse_adjoint", "sht_forward_noalloc"):
         f = getattr(lib, name)
         f.restype = c_int
         f.argtypes = [vp, vp, vp, vp]

@@ -19,6 +19,12 @@
 
 using namespace sht;
 
+// Workspace of sht_forward_noalloc: a static device array, one copy per GPU
+// the library runs on, held until the process ends.  Host code never uses
+// this name as an address: the device address of each GPU's copy is looked
+// up once per device (scratch_ptr) and passed to the kernels.
+static __device__ __align__(256) unsigned char scratch[SHT_NOALLOC_WORKSPACE_BYTES];
+
 namespace {
 
 constexpr uint32_t kMagic = 0x53485443u;  // "SHTC"
@@ -728,7 +734,7 @@ void prof_mark(sht_plan_s* P, void* stream, int stage, bool start) {
 }
 
 // grid -> spec through the zonal analysis (row scale and m scale given);
-// ws is the workspace to use
+// ws is the workspace to use (the plan's, or the static scratch)
 int run_analysis(sht_plan_s* P, const void* grid, void* spec, void* stream, int use_w, int use_inv_I,
                  double mscale, void* ws) {
   FftArgs a = fft_args(P, grid, ws, use_w, use_inv_I, mscale);
@@ -814,6 +820,61 @@ int run_dir(sht_plan_s* P, int dir, const void* in, void* out, void* stream) {
   }
   P->graphs.push_back({dir, in, out, graph, exec, done, false});
   return SHT_OK;
+}
+
+// ---- allocation-free analysis ----
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's copy of `scratch` (dev must be the
+// current device); looked up on the first call per device.
+int scratch_ptr(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(SHT_EINVAL, "device id out of range for the static workspace");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    int rc = hip_check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    if (rc) return rc;
+    if (!p) return fail(SHT_EHIP, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return SHT_OK;
+}
+
+// The analysis with the workspace in the static array.  The Legendre
+// analysis reads the padding rows ceil(J/2) <= j < Kp of every workspace
+// plane (their table entries are zero), and an earlier call, of this or
+// another plan, may have left any value there (NaN included): they are
+// cleared first by a fill kernel on the same stream.  No events, graphs or
+// allocations.
+int run_forward_noalloc(sht_plan_s* P, const void* grid, void* spec, void* stream) {
+  if (P->ws_bytes > SHT_NOALLOC_WORKSPACE_BYTES)
+    return fail(SHT_EINVAL, "the plan's workspace (" + std::to_string(P->ws_bytes) +
+                                " bytes) exceeds the static workspace of sht_forward_noalloc (" +
+                                std::to_string((size_t)SHT_NOALLOC_WORKSPACE_BYTES) + " bytes)");
+  int dev = -1;
+  int rc = hip_check(hipGetDevice(&dev), "hipGetDevice");
+  if (rc) return rc;
+  if (dev != P->device)
+    return fail(SHT_EINVAL, "the plan was built on device " + std::to_string(P->device) +
+                                " but the current device is " + std::to_string(dev));
+  void* ws = nullptr;
+  if ((rc = scratch_ptr(dev, &ws))) return rc;
+  for (int l = 0; l < P->nlev; ++l) {
+    const LevelDesc& L = P->lev[l];
+    const long long row16 = (long long)L.Cp * (long long)P->elem / 16;  // Cp is a multiple of 16
+    const int e = launch_clear_span(static_cast<unsigned char*>(ws) + L.ws_off * (long long)P->elem,
+                                    2LL * (L.N + 1), row16 * L.Kp, row16 * L.Jh, row16 * (L.Kp - L.Jh), stream);
+    if (e) return hip_check((hipError_t)e, "workspace clear launch");
+  }
+  const int saved_profile = P->profile;  // profiling would create events
+  P->profile = 0;
+  rc = run_analysis(P, grid, spec, stream, 1, 1, 1.0, ws);
+  P->profile = saved_profile;
+  return rc;
 }
 
 // ---- autotuner ----
@@ -1072,6 +1133,12 @@ int sht_forward(sht_plan_t plan, const void* grid, void* spec, void* stream) {
   int rc;
   if ((rc = check_plan(plan)) || (rc = check_ptr(grid, "grid")) || (rc = check_ptr(spec, "spec"))) return rc;
   return run_dir(plan, DIR_FWD, grid, spec, stream);
+}
+
+int sht_forward_noalloc(sht_plan_t plan, const void* grid, void* spec, void* stream) {
+  int rc;
+  if ((rc = check_plan(plan)) || (rc = check_ptr(grid, "grid")) || (rc = check_ptr(spec, "spec"))) return rc;
+  return run_forward_noalloc(plan, grid, spec, stream);
 }
 
 int sht_inverse(sht_plan_t plan, const void* spec, void* grid, void* stream) {

@@ -112,6 +112,10 @@ int launch_legendre_synthesis_otf(const GemmArgs& g, void* stream);
 int launch_retruncate(int Nin, int Nout, int F, bool dbl, const void* in, void* out, void* stream);
 int launch_inject(int Jf, int If, int Jc, int Ic, int F, int rs, int r0, int cs, bool dbl, const void* fine,
                   void* coarse, void* stream);
+// Zero units [first16, first16 + len16) (16-byte units) of nplanes planes
+// spaced pitch16 units apart, starting at base (16-byte aligned).
+int launch_clear_span(void* base, long long nplanes, long long pitch16, long long first16, long long len16,
+                      void* stream);
 int launch_product(long long n, bool dbl, const void* a, const void* b, void* out, void* stream);
 int launch_laplacian(int N, int F, double scale, bool dbl, const void* in, void* out, void* stream);
 int launch_residual(long long n, long long n_per, double alpha, bool dbl, const void* x, const void* kappa,

@@ -12,6 +12,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "sht_internal.h"
 
 namespace sht {
@@ -40,6 +42,18 @@ __global__ __launch_bounds__(256) void k_inject(int Jf, int If, int Jc, int Ic, 
   const T* src = fine + ((long long)f * Jf + (long long)r0 + (long long)rs * jc) * If;
   T* dst = coarse + ((long long)f * Jc + jc) * Ic;
   for (int i = threadIdx.x; i < Ic; i += 256) dst[i] = src[(long long)cs * i];
+}
+
+// Zero a span of 16-byte units in each of nplanes equally spaced planes:
+// units [first, first + len) of plane p start at base + p * pitch.  Used to
+// clear the padding rows of a workspace that other calls share.
+__global__ __launch_bounds__(256) void k_clear_span(uint4* base, long long nplanes, long long pitch, long long first,
+                                                    long long len) {
+  const long long total = nplanes * len;
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < total; i += (long long)gridDim.x * 256) {
+    const long long p = i / len, k = i - p * len;
+    base[p * pitch + first + k] = uint4{0u, 0u, 0u, 0u};
+  }
 }
 
 // out = a * b elementwise, four elements per thread (n a multiple of 4
@@ -136,6 +150,16 @@ int launch_residual(long long n, long long n_per, double alpha, bool dbl, const 
       hipLaunchKernelGGL((k_residual<float, false>), grid, block, 0, st, n_per, nf, (float)alpha, a[0], a[1], a[2],
                          a[3], static_cast<float*>(r));
   }
+  return (int)hipGetLastError();
+}
+
+int launch_clear_span(void* base, long long nplanes, long long pitch16, long long first16, long long len16,
+                      void* stream) {
+  const long long total = nplanes * len16;
+  if (total <= 0) return (int)hipSuccess;
+  const long long blocks = std::min<long long>((total + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_clear_span, dim3((unsigned)blocks), dim3(256), 0, static_cast<hipStream_t>(stream),
+                     static_cast<uint4*>(base), nplanes, pitch16, first16, len16);
   return (int)hipGetLastError();
 }
 

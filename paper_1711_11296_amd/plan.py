@@ -122,6 +122,13 @@ class Plan:
         return self._run(self._lib.sht_forward, grid, self.grid_elems, self.spec_elems,
                          self.spec_shape, out, ("grid", "spec"))
 
+    def forward_noalloc(self, grid, out=None):
+        """Analysis grid -> spec through sht_forward_noalloc: the workspace is
+        the library's static device array instead of the plan's (the plan's
+        workspace must fit in 64 MiB); pass out= to allocate nothing."""
+        return self._run(self._lib.sht_forward_noalloc, grid, self.grid_elems, self.spec_elems,
+                         self.spec_shape, out, ("grid", "spec"))
+
     def inverse(self, spec, out=None):
         """Synthesis spec -> grid."""
         return self._run(self._lib.sht_inverse, spec, self.spec_elems, self.grid_elems,

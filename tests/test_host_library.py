@@ -43,6 +43,8 @@ def test_invalid_arguments_are_rejected_without_a_gpu():
     buf = (ctypes.c_double * 4)()
     assert lib.sht_forward(None, buf, buf, None) == _lib.SHT_EINVAL
     assert lib.sht_forward(bogus, buf, buf, None) == _lib.SHT_ESTATE
+    assert lib.sht_forward_noalloc(None, buf, buf, None) == _lib.SHT_EINVAL
+    assert lib.sht_forward_noalloc(bogus, buf, buf, None) == _lib.SHT_ESTATE
     assert lib.sht_device_bytes(None) == _lib.SHT_EINVAL
     assert _lib.device_bytes() == 0      # no plan is live in this process
     assert lib.sht_plan_destroy(bogus) == _lib.SHT_ESTATE
