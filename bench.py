@@ -57,7 +57,8 @@ def parse():
                     help="time the residual and restriction steps of the App. C two-grid cycle instead "
                          "(Tc479 fine, Tc239 coarse, 100 fields; own JSON line)")
     ap.add_argument("--otf", action="store_true",
-                    help="with --aliasing: the FP64 Legendre kernels generate P~ from seed rows (plan option otf)")
+                    help="the Legendre kernels generate P~ from seed rows instead of reading a table (plan option "
+                         "otf); reported in config, never the default")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy a 1 GiB buffer 3 times (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -390,7 +391,7 @@ def main():
 
     # ---- workload: grids synthesised from k^-3 band-limited spectra ----
     spec0 = inputs.random_spectra(N, F, seed=0, profile="k3")
-    plan = Plan(N, J, I, F, grid=args.grid, form=args.form, reduced=args.reduced)
+    plan = Plan(N, J, I, F, grid=args.grid, form=args.form, reduced=args.reduced, otf=args.otf)
     a = torch.from_numpy(spec0).to("cuda:0", dt)
     g = plan.inverse(a)
     torch.cuda.synchronize()
@@ -448,7 +449,7 @@ def main():
     fp64 = None
     if not args.no_fp64 and args.form != "fp64":
         del s_out, g_out
-        p64 = Plan(N, J, I, F, grid=args.grid, form="fp64", reduced=args.reduced)
+        p64 = Plan(N, J, I, F, grid=args.grid, form="fp64", reduced=args.reduced, otf=args.otf)
         g64 = g.double()
         st = max(2, args.steps // 4)
         secs64, per64, _, _ = time_pairs(p64, g64, st, 1, torch)
@@ -474,11 +475,13 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if args.form == "fp32" else ("f64" if args.form == "fp64" else "bf16x6/f32"),
         "data": "synthetic: grids synthesised from k^-3 random spectra (seed 0)",
-        "config": {"workload": "T%d batch: N=%d J=%d I=%d, %d fields, %s grid, %s form, forward+inverse%s"
+        "config": {"workload": "T%d batch: N=%d J=%d I=%d, %d fields, %s grid, %s form, forward+inverse%s%s"
                                % (N, N, J, I, F, args.grid, args.form,
-                                  ", reduced transform" if args.reduced else ""),
+                                  ", reduced transform" if args.reduced else "",
+                                  ", P~ generated in the kernels (no table)" if args.otf else ""),
                    "N": N, "J": J, "I": I, "fields": F, "grid": args.grid, "form": args.form,
-                   "reduced": bool(args.reduced)},
+                   "reduced": bool(args.reduced), "otf": bool(args.otf)},
+        "table_bytes": plan.table_bytes,
         "legendre_tflops": leg_tflops,
         "legendre_mfma_frac": leg_tflops / peak,
         "end_to_end_mfma_frac": 2 * flops_dir / (ms_step * 1e-3) / 1e12 / peak,
@@ -491,7 +494,7 @@ def main():
         "roofline": {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak,
                      # the committed counters were taken on the full transform
-                     "traffic": None if args.reduced else counted_traffic(dom, args.form, args.config),
+                     "traffic": None if (args.reduced or args.otf) else counted_traffic(dom, args.form, args.config),
                      "algorithmic_flops_per_launch": flops_dir},
         "cpu_baseline": cpu,
     }

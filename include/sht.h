@@ -92,11 +92,13 @@ typedef struct {
                      whole blocks of the kernels (32 latitudes; 16 in the
                      FP64 analysis; 128 in the synthesis).  The terms left
                      out are below 1e-16 relative. */
-  int otf;        /* nonzero (FP64 form only, not with reduced or
-                     autotune): both Legendre kernels generate P~_n^m by the
-                     three-term recurrence (Sec. 4.1) from two stored seed
-                     rows per 16 degrees instead of reading a table; the
-                     plan keeps no table (1/8 of its size in seed rows). */
+  int otf;        /* nonzero (any form; not with reduced or autotune):
+                     both Legendre kernels generate P~_n^m by the three-term
+                     recurrence (Sec. 4.1), in FP64, from two stored FP64
+                     seed rows per 16 degrees instead of reading a table,
+                     and round it once to the form's element type; the plan
+                     keeps no table (seed rows: 1/8 of the table's entries,
+                     in FP64). */
 } sht_options;
 
 enum {

@@ -56,7 +56,7 @@ struct sht_plan_s {
   int autotune = 0;
   int use_graph = 0;
   int reduced = 0;             // reduced transform (Sec. 4.1)
-  int otf = 0;                 // analysis generates P~ from seed rows (FP64)
+  int otf = 0;                 // Legendre kernels generate P~ from seed rows (no table kept)
   double* d_seeds = nullptr;   // per (level, m, 16-degree group): two seed rows of Kp
   long long* d_seedoff = nullptr;
   double* d_rec = nullptr;     // per (level, m, r): recurrence coefficients (A_r, B_r)
@@ -379,8 +379,7 @@ int build_plan(int nlev, const int* Nv, const int* Jv, const int* Iv, const int*
   sht_options o{SHT_GRID_CC_POLES, SHT_FORM_FP64, 0, 0, 0, 0};
   if (opts) o = *opts;
   if (o.form < SHT_FORM_FP64 || o.form > SHT_FORM_BF16X6) return fail(SHT_EINVAL, "unknown form");
-  if (o.otf && (o.form != SHT_FORM_FP64 || o.reduced || o.autotune))
-    return fail(SHT_EINVAL, "otf needs the FP64 form, without reduced or autotune");
+  if (o.otf && (o.reduced || o.autotune)) return fail(SHT_EINVAL, "otf cannot be combined with reduced or autotune");
   for (int l = 0; l < nlev; ++l) {
     int rc = check_level_args(Nv[l], Jv[l], Iv[l], Fv[l], o.grid);
     if (rc) return rc;
@@ -519,9 +518,10 @@ int build_plan(int nlev, const int* Nv, const int* Jv, const int* Iv, const int*
                                P->reduced ? P->jst.data() + L.m_base : nullptr,
                                P->otf ? hseeds.data() : nullptr, seedoff.data() + L.m_base);
     else
-      fill_table_level<float>(L, mu.data(), sint.data(), reinterpret_cast<float*>(htab.data()), to,
-                              reinterpret_cast<float*>(htabs.data()), ts, P->reduced ? P->jst.data() + L.m_base : nullptr,
-                              nullptr, nullptr);
+      fill_table_level<float>(L, mu.data(), sint.data(), P->otf ? nullptr : reinterpret_cast<float*>(htab.data()), to,
+                              P->otf ? nullptr : reinterpret_cast<float*>(htabs.data()), ts,
+                              P->reduced ? P->jst.data() + L.m_base : nullptr, P->otf ? hseeds.data() : nullptr,
+                              seedoff.data() + L.m_base);
     // twiddles exp(-2 pi i k / I)
     const size_t cs = 2 * P->elem;
     htw[l].resize((size_t)L.I * cs);
@@ -567,8 +567,6 @@ int build_plan(int nlev, const int* Nv, const int* Jv, const int* Iv, const int*
     for (int m = 0; m <= L.N; ++m)
       P->flops_kept += 4.0 * (L.N - m + 1) * L.F * (double)(L.Jh - P->jst[L.m_base + m] / kb * kb);
   }
-  // the generated-P~ kernels take one column block
-  if (P->otf) P->ncb_fwd = P->ncb_inv = 1;
   std::vector<Tile> sf = build_tiles(P, true, P->ncb_fwd, 0), si = build_tiles(P, false, P->ncb_inv, 0);
   P->ntiles_fwd = (int)sf.size();
   P->ntiles_inv = (int)si.size();
@@ -745,7 +743,7 @@ int run_analysis(sht_plan_s* P, const void* grid, void* spec, void* stream, int 
   GemmArgs g = gemm_args(P, true, nullptr, spec);
   g.ws = ws;
   prof_mark(P, stream, ST_LEG_A, true);
-  e = P->otf ? launch_legendre_analysis_otf(g, stream) : launch_legendre(P->form, true, g, P->ncb_fwd, stream);
+  e = launch_legendre(P->form, true, g, P->ncb_fwd, P->otf != 0, stream);
   prof_mark(P, stream, ST_LEG_A, false);
   if (e) return hip_check((hipError_t)e, "Legendre analysis launch");
   return SHT_OK;
@@ -755,7 +753,7 @@ int run_synthesis(sht_plan_s* P, const void* spec, void* grid, void* stream, int
                   double mscale) {
   GemmArgs g = gemm_args(P, false, spec, nullptr);
   prof_mark(P, stream, ST_LEG_S, true);
-  int e = P->otf ? launch_legendre_synthesis_otf(g, stream) : launch_legendre(P->form, false, g, P->ncb_inv, stream);
+  int e = launch_legendre(P->form, false, g, P->ncb_inv, P->otf != 0, stream);
   prof_mark(P, stream, ST_LEG_S, false);
   if (e) return hip_check((hipError_t)e, "Legendre synthesis launch");
   FftArgs a = fft_args(P, P->d_ws, grid, use_w, use_inv_I, mscale);
@@ -991,9 +989,9 @@ int autotune(sht_plan_s* P) {
           GemmArgs g = gemm_args(P, analysis, spec, spec);
           g.tiles = dt;
           g.ntiles = (int)t.size();
-          int e = launch_legendre(P->form, analysis, g, c, st);
+          int e = launch_legendre(P->form, analysis, g, c, false, st);
           (void)hipEventRecord(e0, st);
-          for (int r = 0; r < 3 && !e; ++r) e = launch_legendre(P->form, analysis, g, c, st);
+          for (int r = 0; r < 3 && !e; ++r) e = launch_legendre(P->form, analysis, g, c, false, st);
           (void)hipEventRecord(e1, st);
           (void)hipEventSynchronize(e1);
           float ms = 0.f;

@@ -111,8 +111,29 @@ static void lds_optin(size_t bytes) {
   }
 }
 
+// Generated P~ (plan option otf), shared by both directions and all forms: the rows
+// r = n - m of a block are produced by the three-term recurrence of
+// Sec. 4.1, P~_r = A_r mu P~_{r-1} - B_r P~_{r-2}, in FP64 from the two
+// stored seed rows of each 16-degree group (rows 16 gi and 16 gi + 1 of
+// every latitude), one latitude per thread, and rounded once to the element
+// type; st(s, value) receives row r0 + s.  Rows at or beyond n_m are zero.
+template <class Store>
+__device__ __forceinline__ void gen_rows16(const double* rec, int r0, int nm, double mu, double x0, double x1,
+                                           Store st) {
+  st(0, r0 < nm ? x0 : 0.0);
+  st(1, r0 + 1 < nm ? x1 : 0.0);
+#pragma unroll
+  for (int s = 2; s < 16; ++s) {
+    const int r = r0 + s;
+    const double x2 = r < nm ? rec[2 * r] * mu * x1 - rec[2 * r + 1] * x0 : 0.0;
+    st(s, x2);
+    x0 = x1;
+    x1 = x2;
+  }
+}
+
 // Split-bfloat16 Legendre kernels (sht_legendre_bf16.hip).
-hipError_t launch_legendre_bf16(bool analysis, const GemmArgs& g, int ncb, hipStream_t st);
+hipError_t launch_legendre_bf16(bool analysis, const GemmArgs& g, int ncb, bool gen, hipStream_t st);
 
 }  // namespace sht
 

@@ -105,9 +105,9 @@ struct GemmArgs {
 // planner checks and falls back to 8).
 int zonal_fields_per_block(int form, int nlev, int N, int J, int I, int F);
 int launch_zonal(int form, bool analysis, const FftArgs& a, int maxN, void* stream);
-int launch_legendre(int form, bool analysis, const GemmArgs& g, int ncb, void* stream);
-int launch_legendre_analysis_otf(const GemmArgs& g, void* stream);
-int launch_legendre_synthesis_otf(const GemmArgs& g, void* stream);
+// gen: generate P~ in the kernels from the plan's seed rows instead of
+// reading a table (plan option otf)
+int launch_legendre(int form, bool analysis, const GemmArgs& g, int ncb, bool gen, void* stream);
 // Transfers between truncations and nested grids (sht_transfer.hip).
 int launch_retruncate(int Nin, int Nout, int F, bool dbl, const void* in, void* out, void* stream);
 int launch_inject(int Jf, int If, int Jc, int Ic, int F, int rs, int r0, int cs, bool dbl, const void* fine,

@@ -68,14 +68,33 @@ struct AnalysisShape {
   static constexpr int BV = 2 * KB * BN / E;           // 16-byte vectors per block
   static constexpr int NB = (BV + 511) / 512;
   static constexpr int CS = BN + 1;                    // staging pitch of the output
-  static constexpr size_t lds_bytes() {
-    const size_t main = (size_t)2 * STAGE * sizeof(T);
+  static constexpr int PS = 128 * KB;                  // generated P~ of one block (GEN)
+  static constexpr size_t lds_bytes(bool gen) {
+    const size_t main = (size_t)(2 * STAGE + (gen ? PS : 0)) * sizeof(T);
     const size_t cst = (size_t)64 * CS * sizeof(T);
     return main > cst ? main : cst;
   }
 };
 
-template <typename T, int NCB>
+// Swizzle of the generated analysis block [128 rows][KB latitudes]: element
+// (row, lat) sits at row * KB + (lat ^ gen_swz(row)), so that the 32
+// latitudes one store instruction writes and the rows 2 i + p of one read
+// instruction fall on distinct banks.
+template <int KB>
+__device__ __forceinline__ int gen_swz(int row) {
+  return (2 * ((row >> 1) & 15)) & (KB - 1);
+}
+
+// GEN: the table operand is generated in the kernel (see gen_rows16): per K
+// block, wave w produces the 16 rows of group w of the tile (lane l <
+// KB at latitude l) into an LDS block, and after a barrier each wave reads
+// its rows' values from it into the registers the table path fills from
+// memory.
+// The seed values of block kb + 2 are fetched while block kb is multiplied;
+// the generated block is written after the products (its previous contents
+// were read into registers before the last barrier), read after the next
+// barrier, and a second barrier guards it against the next block's writes.
+template <typename T, int NCB, bool GEN>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_legendre_analysis(const GemmArgs g) {
   typedef typename Acc<T>::type AccT;
   typedef typename V16<T>::type V;
@@ -104,8 +123,46 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
   const int li = lane & 15, lg = lane >> 4;
   const bool active = r0 + 32 * q + p < nm;
   // this wave's run of the blocked table (see the table layout above)
-  const T* arow = static_cast<const T*>(g.table) + g.tab_off[L.m_base + m] +
-                  (long long)t.rb * Kp * 128 + w * 16 * KB + lane * E;
+  const T* arow = GEN ? nullptr
+                      : static_cast<const T*>(g.table) + g.tab_off[L.m_base + m] + (long long)t.rb * Kp * 128 +
+                            w * 16 * KB + lane * E;
+  T* Ps = Bs + 2 * S::STAGE;  // GEN: [128 rows][KB latitudes], swizzled (gen_swz)
+  // GEN: wave w generates group w (rows 16 w .. 16 w + 15 of the tile), lane
+  // l < KB latitude l of each block; the group is uniform across the wave,
+  // so the recurrence coefficients come through scalar loads
+  const int ggrp = w, glat = lane;
+  const int gi = t.rb * 8 + ggrp;
+  const bool gthr = GEN && lane < KB;
+  const bool gon = gthr && 16 * gi < nm;
+  const double* gseed = GEN ? g.seeds + g.seed_off[L.m_base + m] + (gon ? 2LL * gi * Kp : 0LL) : nullptr;
+  const double* grec = GEN ? g.rec + g.rec_off[L.m_base + m] : nullptr;
+  double gmu[2] = {0.0, 0.0}, gx0[2] = {0.0, 0.0}, gx1[2] = {0.0, 0.0};
+  auto gen_fetch = [&](int kb, int set) __attribute__((always_inline)) {
+    if constexpr (GEN) {
+      if (gon) {
+        const int j = kb * KB + glat;
+        gmu[set] = L.murow[j];
+        gx0[set] = gseed[j];
+        gx1[set] = 16 * gi + 1 < nm ? gseed[Kp + j] : 0.0;
+      }
+    }
+  };
+  auto gen_store = [&](int set) __attribute__((always_inline)) {
+    if constexpr (GEN) {
+      if (gthr) {
+        gen_rows16(grec, 16 * gi, 16 * gi < nm ? nm : 0, gmu[set], gx0[set], gx1[set], [&](int s2, double x) {
+          const int row = 16 * ggrp + s2;
+          Ps[row * KB + (glat ^ gen_swz<KB>(row))] = (T)x;
+        });
+      }
+    }
+  };
+  T areg[KQ];
+  auto gen_read = [&]() __attribute__((always_inline)) {
+    const int rr = 32 * q + 2 * li + p;
+#pragma unroll
+    for (int kk = 0; kk < KQ; ++kk) areg[kk] = Ps[rr * KB + ((4 * kk + lg) ^ gen_swz<KB>(rr))];
+  };
 
   AccT acc[NCB];
 #pragma unroll
@@ -174,15 +231,23 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
   auto wait_fills = [&]() {
     if constexpr (S::DMA) {
       static_assert(KQ / E == 2, "two table loads per block");
-      asm volatile("s_waitcnt vmcnt(2)" ::: "memory");
+      if constexpr (GEN)
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // nothing else is worth keeping in flight
+      else
+        asm volatile("s_waitcnt vmcnt(2)" ::: "memory");
     }
   };
   auto compute = [&](int stage) {
     T a[KQ];
+    if constexpr (GEN) {
 #pragma unroll
-    for (int v = 0; v < KQ / E; ++v)
+      for (int kk = 0; kk < KQ; ++kk) a[kk] = areg[kk];
+    } else {
 #pragma unroll
-      for (int e = 0; e < E; ++e) a[v * E + e] = ac[v][e];
+      for (int v = 0; v < KQ / E; ++v)
+#pragma unroll
+        for (int e = 0; e < E; ++e) a[v * E + e] = ac[v][e];
+    }
     const T* Bp = Bs + stage * S::STAGE + (p * KB + lg) * BS + li;
     // swizzled column-block offsets (rows g + 4 kk have the parity of g)
     const int sw = (S::DMA && (lg & 1)) ? 16 : 0;
@@ -207,16 +272,24 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     // nothing reads, which keeps the loop free of branches around memory
     // operations
     const int kn = kb + 1 < nkb ? kb + 1 : nkb - 1;
+    gen_fetch(kb + 2 < nkb ? kb + 2 : nkb - 1, H);
     dma(kn, 1 - H);
     gload_b(kn);
     asm volatile("" ::: "memory");  // the table loads below are issued after the fills
-    gload_a(kb + 2 < nkb ? kb + 2 : nkb - 1, an[H]);
+    if constexpr (!GEN) gload_a(kb + 2 < nkb ? kb + 2 : nkb - 1, an[H]);
     if (active) compute(H);
+    gen_store(1 - H);  // block kb + 1 (clamped after the last: nothing reads it)
     lstore(1 - H);
     wait_fills();
+    if constexpr (!GEN) {
 #pragma unroll
-    for (int v = 0; v < KQ / E; ++v) ac[v] = an[1 - H][v];
+      for (int v = 0; v < KQ / E; ++v) ac[v] = an[1 - H][v];
+    }
     lds_barrier();
+    if constexpr (GEN) {
+      gen_read();
+      lds_barrier();
+    }
   };
 
   // reduced transform: the blocks before kb0 hold only latitudes where
@@ -225,13 +298,25 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
   dma(kb0, 0);
   gload_b(kb0);
   asm volatile("" ::: "memory");
-  gload_a(kb0, an[0]);
-  gload_a(kb0 + 1 < nkb ? kb0 + 1 : nkb - 1, an[1]);
+  if constexpr (GEN) {
+    gen_fetch(kb0, 0);
+    gen_store(0);
+    gen_fetch(kb0 + 1 < nkb ? kb0 + 1 : nkb - 1, 1);
+  } else {
+    gload_a(kb0, an[0]);
+    gload_a(kb0 + 1 < nkb ? kb0 + 1 : nkb - 1, an[1]);
+  }
   lstore(0);
   wait_fills();
+  if constexpr (!GEN) {
 #pragma unroll
-  for (int v = 0; v < KQ / E; ++v) ac[v] = an[0][v];
+    for (int v = 0; v < KQ / E; ++v) ac[v] = an[0][v];
+  }
   __syncthreads();
+  if constexpr (GEN) {
+    gen_read();
+    __syncthreads();
+  }
   for (int kb = kb0; kb < nkb; kb += 2) {
     step(std::integral_constant<int, 0>{}, kb);
     if (kb + 1 < nkb) step(std::integral_constant<int, 1>{}, kb + 1);
@@ -269,229 +354,6 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
 }
 
 // ---------------------------------------------------------------------------
-// analysis with P~ generated in the kernel (FP64; plan option otf).
-// Same tiles and output as the FP64 analysis with one column block: 128
-// rows r = n - m by 16 columns.  Per K block of 32 latitudes, wave w runs
-// the three-term recurrence of Sec. 4.1 (in the form
-// P~_n = A_r mu P~_{n-1} - B_r P~_{n-2}) for the 16 rows 16 w .. 16 w + 15
-// of the tile, one latitude per lane, from the two stored seed rows of its
-// 16-degree group, and writes them to LDS; with the workspace block (both
-// parities) staged beside them, each wave then runs the MFMA products of
-// the ordinary kernel (rows 32 q + 2 i + p) with both operands from LDS.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(512) void k_legendre_analysis_otf(const GemmArgs g) {
-  constexpr int KB = 32, PP = KB + 1, BP = 17;
-  __shared__ double Ps[128 * PP];      // generated rows of the tile: [row][latitude]
-  __shared__ double Bs[2 * KB * BP];   // workspace block: [parity][latitude][column]
-
-  const Tile t = g.tiles[blockIdx.x];
-  if (t.level < 0) return;
-  const LevelDesc& L = g.lev[t.level];
-  const int N = L.N, m = t.m;
-  const int nm = N - m + 1;
-  const int r0 = t.rb * 128;
-  const int c0 = t.cb * 16;
-  const int Kp = L.Kp;
-  const long long Cp = L.Cp;
-  const long long plane = (long long)Kp * Cp;
-  const double* wsm = static_cast<const double*>(g.ws) + L.ws_off + (2LL * m) * plane + c0;
-
-  const int tid = threadIdx.x;
-  const int w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
-  const int p = w & 1, q = w >> 1;
-  const int li = lane & 15, lg = lane >> 4;
-  // this wave's 16-degree group: rows 16 w .. 16 w + 15 of the tile
-  const int gi = t.rb * 8 + w;
-  const int rg = 16 * gi;
-  const bool gen = rg < nm;
-  const double* seed = g.seeds + g.seed_off[L.m_base + m] + (gen ? (long long)(2 * gi) * Kp : 0);
-  const double* rec = g.rec + g.rec_off[L.m_base + m];
-
-  // operands of the next K block (seed values, node, workspace elements)
-  // are fetched into registers while the matrix cores work on this one
-  double smu = 0.0, sx0 = 0.0, sx1 = 0.0, bv[2];
-  auto fetch = [&](int kb) __attribute__((always_inline)) {
-    if (gen && lane < KB) {
-      const int j = kb * KB + lane;
-      smu = L.murow[j];
-      sx0 = seed[j];
-      sx1 = rg + 1 < nm ? seed[Kp + j] : 0.0;
-    }
-#pragma unroll
-    for (int e = 0; e < 2; ++e) {
-      const int idx = tid + e * 512;  // 2 * KB * 16 = 1024 elements
-      const int par = idx / (KB * 16), rem = idx - par * (KB * 16);
-      bv[e] = wsm[par * plane + (long long)(kb * KB + (rem >> 4)) * Cp + (rem & 15)];
-    }
-  };
-
-  f64x4 acc = {0.0, 0.0, 0.0, 0.0};
-  const int nkb = Kp / KB;
-  fetch(0);
-  for (int kb = 0; kb < nkb; ++kb) {
-    if (lane < KB) {
-      double* dst = Ps + (16 * w) * PP + lane;
-      if (gen) {
-        const double mu = smu;
-        double x0 = sx0, x1 = sx1;
-        dst[0] = x0;
-        dst[PP] = x1;
-#pragma unroll
-        for (int s2 = 2; s2 < 16; ++s2) {
-          const int r = rg + s2;
-          const double x2 = r < nm ? rec[2 * r] * mu * x1 - rec[2 * r + 1] * x0 : 0.0;
-          dst[s2 * PP] = x2;
-          x0 = x1;
-          x1 = x2;
-        }
-      } else {
-#pragma unroll
-        for (int s2 = 0; s2 < 16; ++s2) dst[s2 * PP] = 0.0;
-      }
-    }
-#pragma unroll
-    for (int e = 0; e < 2; ++e) {
-      const int idx = tid + e * 512;
-      const int par = idx / (KB * 16), rem = idx - par * (KB * 16);
-      Bs[(par * KB + (rem >> 4)) * BP + (rem & 15)] = bv[e];
-    }
-    __syncthreads();
-    if (kb + 1 < nkb) fetch(kb + 1);
-    const double* Ap = Ps + (32 * q + 2 * li + p) * PP + lg;
-    const double* Bp = Bs + (p * KB + lg) * BP + li;
-#pragma unroll
-    for (int kk = 0; kk < KB / 4; ++kk) acc = mfma16(Ap[4 * kk], Bp[4 * kk * BP], acc);
-    __syncthreads();
-  }
-
-  double* spec = static_cast<double*>(g.spec_out) + L.spec_off;
-  const long long nc = (long long)(N + 1) * (N + 2) / 2;
-  const long long base = spec_idx(N, m, m);
-  const int c = c0 + li, f = c >> 1;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int r = r0 + 32 * q + 2 * out_row<double>(lg, i) + p;
-    if (r < nm && f < L.F) spec[((long long)f * nc + base + r) * 2 + (c & 1)] = acc[i];
-  }
-}
-
-// Synthesis with P~ generated in the kernel (FP64; plan option otf):
-// S_p[j][c] = sum_{r of parity p} P~[r][j] a[r][c] over blocks of 64 rows.
-// Tile = 128 latitudes x 16 columns.  Per block, wave w regenerates the 16
-// rows of group w & 3 for the latitudes 64 (w >> 2) + lane from the stored
-// seed rows (the node of a lane's latitude stays in a register), the block's
-// spectra are staged beside them, and wave (p, q) runs the MFMA products
-// for its 32 latitudes 32 q + 16 jb + i and parity p.  The next block's seed
-// values and spectra are fetched while the matrix cores run.
-__global__ __launch_bounds__(512) void k_legendre_synthesis_otf(const GemmArgs g) {
-  constexpr int RB = 64, LP = 129, AP = 17;
-  __shared__ double Ps[RB * LP];   // generated rows of the block: [row][latitude]
-  __shared__ double As[RB * AP];   // spectra of the block: [row][column]
-
-  const Tile t = g.tiles[blockIdx.x];
-  if (t.level < 0) return;
-  const LevelDesc& L = g.lev[t.level];
-  const int N = L.N, m = t.m;
-  const int nm = N - m + 1;
-  const int jt = t.rb, c0 = t.cb * 16;
-  const int Kp = L.Kp;
-  const long long Cp = L.Cp;
-  const double* spec = static_cast<const double*>(g.spec_in) + L.spec_off;
-  const long long nc = (long long)(N + 1) * (N + 2) / 2;
-  const long long sbase = spec_idx(N, m, m);
-
-  const int tid = threadIdx.x;
-  const int w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
-  const int p = w & 1, q = w >> 1;
-  const int li = lane & 15, lg = lane >> 4;
-  const int gsub = w & 3;                 // group of the block this wave generates
-  const int jl = (w >> 2) * 64 + lane;    // latitude of the tile this lane generates
-  const int j = jt * 128 + jl;
-  const bool jin = j < Kp;
-  const double mu = jin ? L.murow[j] : 0.0;
-  const double* seeds = g.seeds + g.seed_off[L.m_base + m];
-  const double* rec = g.rec + g.rec_off[L.m_base + m];
-  const int nblk = (nm + RB - 1) / RB;
-
-  double sx0 = 0.0, sx1 = 0.0, av[2];
-  auto fetch = [&](int b) __attribute__((always_inline)) {
-    const int gi = 4 * b + gsub, rg = 16 * gi;
-    if (jin && rg < nm) {
-      sx0 = seeds[(long long)(2 * gi) * Kp + j];
-      sx1 = rg + 1 < nm ? seeds[(long long)(2 * gi + 1) * Kp + j] : 0.0;
-    }
-#pragma unroll
-    for (int e = 0; e < 2; ++e) {
-      const int idx = tid + e * 512;  // 64 rows x 16 columns
-      const int r = b * RB + (idx >> 4), cc = c0 + (idx & 15), f = cc >> 1;
-      av[e] = (r < nm && f < L.F) ? spec[((long long)f * nc + sbase + r) * 2 + (cc & 1)] : 0.0;
-    }
-  };
-
-  f64x4 acc[2] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
-  fetch(0);
-  for (int b = 0; b < nblk; ++b) {
-    {
-      const int rg = 16 * (4 * b + gsub);
-      double* dst = Ps + (16 * gsub) * LP + jl;
-      if (jin && rg < nm) {
-        double x0 = sx0, x1 = sx1;
-        dst[0] = x0;
-        dst[LP] = x1;
-#pragma unroll
-        for (int s2 = 2; s2 < 16; ++s2) {
-          const int r = rg + s2;
-          const double x2 = r < nm ? rec[2 * r] * mu * x1 - rec[2 * r + 1] * x0 : 0.0;
-          dst[s2 * LP] = x2;
-          x0 = x1;
-          x1 = x2;
-        }
-      } else {
-#pragma unroll
-        for (int s2 = 0; s2 < 16; ++s2) dst[s2 * LP] = 0.0;
-      }
-    }
-#pragma unroll
-    for (int e = 0; e < 2; ++e) {
-      const int idx = tid + e * 512;
-      As[(idx >> 4) * AP + (idx & 15)] = av[e];
-    }
-    __syncthreads();
-    if (b + 1 < nblk) fetch(b + 1);
-#pragma unroll
-    for (int jb = 0; jb < 2; ++jb)
-#pragma unroll
-      for (int kk = 0; kk < RB / 8; ++kk) {
-        const int rr = 2 * (4 * kk + lg) + p;
-        acc[jb] = mfma16(Ps[rr * LP + 32 * q + 16 * jb + li], As[rr * AP + li], acc[jb]);
-      }
-    __syncthreads();
-  }
-
-  const long long plane = (long long)Kp * Cp;
-  double* ws = static_cast<double*>(g.ws) + L.ws_off + (2LL * m + p) * plane;
-#pragma unroll
-  for (int jb = 0; jb < 2; ++jb)
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int jj = jt * 128 + 32 * q + 16 * jb + out_row<double>(lg, i);
-      if (jj < L.Jh) ws[(long long)jj * Cp + c0 + li] = acc[jb][i];
-    }
-}
-
-int launch_legendre_synthesis_otf(const GemmArgs& g, void* stream) {
-  if (g.ntiles <= 0) return (int)hipSuccess;
-  hipLaunchKernelGGL(k_legendre_synthesis_otf, dim3(g.ntiles), dim3(512), 0, static_cast<hipStream_t>(stream), g);
-  return (int)hipGetLastError();
-}
-
-int launch_legendre_analysis_otf(const GemmArgs& g, void* stream) {
-  if (g.ntiles <= 0) return (int)hipSuccess;
-  hipLaunchKernelGGL(k_legendre_analysis_otf, dim3(g.ntiles), dim3(512), 0, static_cast<hipStream_t>(stream), g);
-  return (int)hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
 // synthesis: S_p[j][c] = sum_{r of parity p} P[r][j] * a[r][c]
 // tile = 128 latitudes j x BN = 16*NCB columns, both parities, 8 waves.
 // Wave w: parity p = w & 1, latitude quarter q = w >> 1; it owns the 32
@@ -518,10 +380,16 @@ struct SynthesisShape {
   static constexpr int QUADS = (BN / 2) * (KR / 2);    // 4 natural rows of one field
   static constexpr int NQ = (QUADS + 511) / 512;
   static constexpr int CHUNK = 128 * 2 * KR;           // table elements per block
-  static constexpr size_t lds_bytes() { return (size_t)2 * STAGE * sizeof(T); }
+  static constexpr int GP = 130;                       // GEN: pitch of the generated block [2 KR rows][128 latitudes]
+  static constexpr size_t lds_bytes(bool gen) { return (size_t)(2 * STAGE + (gen ? 2 * KR * GP : 0)) * sizeof(T); }
 };
 
-template <typename T, int NCB>
+// GEN: the table operand is generated in the kernel (see gen_rows16): per K
+// block of 2 KR natural rows (two 16-degree groups), waves 0..3 produce the
+// 16 rows of one group for 64 latitudes of the tile each into an LDS block
+// [row][latitude] (pitch 130: the reads of one instruction, 16 latitudes by
+// 4 rows, fall on distinct banks); barriers as in the analysis.
+template <typename T, int NCB, bool GEN>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2))) void k_legendre_synthesis(const GemmArgs g) {
   typedef typename Acc<T>::type AccT;
   typedef typename V16<T>::type V;
@@ -549,8 +417,46 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
   const int p = w & 1, q = w >> 1;
   const int li = lane & 15, lg = lane >> 4;
   const bool active = jt * 128 + 32 * q < L.Jh;
-  const T* arun = static_cast<const T*>(g.table) + g.tab_off[L.m_base + m] +
-                  (long long)jt * nkb * S::CHUNK + w * (S::CHUNK / 8) + lane * E;
+  const T* arun = GEN ? nullptr
+                      : static_cast<const T*>(g.table) + g.tab_off[L.m_base + m] + (long long)jt * nkb * S::CHUNK +
+                            w * (S::CHUNK / 8) + lane * E;
+  T* Ps = Bs + 2 * S::STAGE;  // GEN: [2 KR rows][GP]
+  // GEN: waves 0..3 generate; wave w takes group gsub = w >> 1 of each block
+  // (rows 16 gsub .. + 15 of the block, uniform across the wave) at
+  // latitude glat = 64 (w & 1) + lane of the tile
+  const int gsub = w >> 1, glat = 64 * (w & 1) + lane;
+  const int gj = jt * 128 + glat;
+  const bool gthr = GEN && tid < 256;
+  const bool gjin = gthr && gj < L.Kp;
+  const double* gseeds = GEN ? g.seeds + g.seed_off[L.m_base + m] : nullptr;
+  const double* grec = GEN ? g.rec + g.rec_off[L.m_base + m] : nullptr;
+  const double gmu = (GEN && gjin) ? L.murow[gj] : 0.0;
+  double gx0[2] = {0.0, 0.0}, gx1[2] = {0.0, 0.0};
+  auto gen_fetch = [&](int kb, int set) __attribute__((always_inline)) {
+    if constexpr (GEN) {
+      const int gi = 2 * kb + gsub;
+      if (gjin && 16 * gi < nm) {
+        gx0[set] = gseeds[2LL * gi * L.Kp + gj];
+        gx1[set] = 16 * gi + 1 < nm ? gseeds[(2LL * gi + 1) * L.Kp + gj] : 0.0;
+      }
+    }
+  };
+  auto gen_store = [&](int kb, int set) __attribute__((always_inline)) {
+    if constexpr (GEN) {
+      if (gthr) {
+        const int gi = 2 * kb + gsub;
+        gen_rows16(grec, 16 * gi, gjin ? nm : 0, gmu, gx0[set], gx1[set],
+                   [&](int s2, double x) { Ps[(16 * gsub + s2) * S::GP + glat] = (T)x; });
+      }
+    }
+  };
+  T areg[2][KQ];
+  auto gen_read = [&]() __attribute__((always_inline)) {
+#pragma unroll
+    for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+      for (int kk = 0; kk < KQ; ++kk) areg[jb][kk] = Ps[(2 * (lg * KQ + kk) + p) * S::GP + 32 * q + 16 * jb + li];
+  };
 
   AccT acc[2][NCB];
 #pragma unroll
@@ -579,9 +485,11 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
   // and for blocks past the end, clamped: with straight-line loads the
   // compiler's wait counts cover exactly the block that is consumed)
   auto gload = [&](int kb, V (&av)[S::NV], V (&bq)[S::NQ][QV]) {
+    if constexpr (!GEN) {
 #pragma unroll
-    for (int v = 0; v < S::NV; ++v)
-      av[v] = *reinterpret_cast<const V*>(arun + (long long)kb * S::CHUNK + v * 64 * E);
+      for (int v = 0; v < S::NV; ++v)
+        av[v] = *reinterpret_cast<const V*>(arun + (long long)kb * S::CHUNK + v * 64 * E);
+    }
 #pragma unroll
     for (int i = 0; i < S::NQ; ++i) {
       const int qq = tid + i * 512;
@@ -622,10 +530,17 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
   };
   auto compute = [&](int stage) {
     T a[2][KQ];
+    if constexpr (GEN) {
 #pragma unroll
-    for (int v = 0; v < S::NV; ++v)
+      for (int jb = 0; jb < 2; ++jb)
 #pragma unroll
-      for (int e = 0; e < E; ++e) a[v / (KQ / E)][(v % (KQ / E)) * E + e] = ac[v][e];
+        for (int kk = 0; kk < KQ; ++kk) a[jb][kk] = areg[jb][kk];
+    } else {
+#pragma unroll
+      for (int v = 0; v < S::NV; ++v)
+#pragma unroll
+        for (int e = 0; e < E; ++e) a[v / (KQ / E)][(v % (KQ / E)) * E + e] = ac[v][e];
+    }
     const T* Bp = Bs + stage * S::STAGE + (p * BN + li) * PITCH + lg * KQ;
 #pragma unroll
     for (int c = 0; c < NCB; ++c) {
@@ -649,15 +564,23 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
   // kb + 2), 1 - H that of block kb + 1
   auto step = [&](auto hc, int kb) {
     constexpr int H = decltype(hc)::value;
+    gen_fetch(kb + 2 < nkb ? kb + 2 : nkb - 1, H);
     gload(kb + 2 < nkb ? kb + 2 : nkb - 1, an[H], rq[H]);
     if (active) compute(H);
     // after the last block this fills the idle stage with a clamped block
     // (nothing reads it), which keeps the loop free of branches around
     // memory operations
     lstore(1 - H, rq[1 - H], kb + 1 < nkb ? kb + 1 : nkb - 1);
+    gen_store(kb + 1 < nkb ? kb + 1 : nkb - 1, 1 - H);
+    if constexpr (!GEN) {
 #pragma unroll
-    for (int v = 0; v < S::NV; ++v) ac[v] = an[1 - H][v];
+      for (int v = 0; v < S::NV; ++v) ac[v] = an[1 - H][v];
+    }
     lds_barrier();
+    if constexpr (GEN) {
+      gen_read();
+      lds_barrier();
+    }
   };
 
   // reduced transform: a tile whose latitudes all lie below the first one
@@ -666,9 +589,19 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
     gload(0, an[0], rq[0]);
     gload(nkb > 1 ? 1 : 0, an[1], rq[1]);
     lstore(0, rq[0], 0);
+    if constexpr (GEN) {
+      gen_fetch(0, 0);
+      gen_store(0, 0);
+      gen_fetch(nkb > 1 ? 1 : 0, 1);
+    } else {
 #pragma unroll
-    for (int v = 0; v < S::NV; ++v) ac[v] = an[0][v];
+      for (int v = 0; v < S::NV; ++v) ac[v] = an[0][v];
+    }
     __syncthreads();
+    if constexpr (GEN) {
+      gen_read();
+      __syncthreads();
+    }
     for (int kb = 0; kb < nkb; kb += 2) {
       step(std::integral_constant<int, 0>{}, kb);
       if (kb + 1 < nkb) step(std::integral_constant<int, 1>{}, kb + 1);
@@ -694,59 +627,60 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
 // launchers
 // ---------------------------------------------------------------------------
 template <typename T>
-static size_t lds_analysis(int ncb) {
+static size_t lds_analysis(int ncb, bool gen) {
   switch (ncb) {
-    case 1: return AnalysisShape<T, 1>::lds_bytes();
-    case 2: return AnalysisShape<T, 2>::lds_bytes();
-    case 4: return AnalysisShape<T, 4>::lds_bytes();
-    case 5: return AnalysisShape<T, 5>::lds_bytes();
-    case 8: return AnalysisShape<T, 8>::lds_bytes();
-    default: return AnalysisShape<T, 10>::lds_bytes();
+    case 1: return AnalysisShape<T, 1>::lds_bytes(gen);
+    case 2: return AnalysisShape<T, 2>::lds_bytes(gen);
+    case 4: return AnalysisShape<T, 4>::lds_bytes(gen);
+    case 5: return AnalysisShape<T, 5>::lds_bytes(gen);
+    case 8: return AnalysisShape<T, 8>::lds_bytes(gen);
+    default: return AnalysisShape<T, 10>::lds_bytes(gen);
   }
 }
 
 template <typename T>
-static size_t lds_synthesis(int ncb) {
+static size_t lds_synthesis(int ncb, bool gen) {
   switch (ncb) {
-    case 1: return SynthesisShape<T, 1>::lds_bytes();
-    case 2: return SynthesisShape<T, 2>::lds_bytes();
-    case 4: return SynthesisShape<T, 4>::lds_bytes();
-    case 5: return SynthesisShape<T, 5>::lds_bytes();
-    case 8: return SynthesisShape<T, 8>::lds_bytes();
-    default: return SynthesisShape<T, 8>::lds_bytes();
+    case 1: return SynthesisShape<T, 1>::lds_bytes(gen);
+    case 2: return SynthesisShape<T, 2>::lds_bytes(gen);
+    case 4: return SynthesisShape<T, 4>::lds_bytes(gen);
+    case 5: return SynthesisShape<T, 5>::lds_bytes(gen);
+    case 8: return SynthesisShape<T, 8>::lds_bytes(gen);
+    default: return SynthesisShape<T, 8>::lds_bytes(gen);
   }
 }
 
 constexpr int kMaxSynthesisNcb = 8;
 
-template <typename T, int NCB>
+template <typename T, int NCB, bool GEN>
 static hipError_t launch_ncb(bool analysis, const GemmArgs& g, hipStream_t st) {
   const dim3 grid(g.ntiles), block(512);
   if constexpr (sizeof(T) == 8 && NCB > 8) return hipErrorInvalidValue;  // FP64 takes at most 8
   else if (analysis) {
-    lds_optin<k_legendre_analysis<T, NCB>>(lds_analysis<T>(NCB));
-    hipLaunchKernelGGL((k_legendre_analysis<T, NCB>), grid, block, lds_analysis<T>(NCB), st, g);
+    const size_t lds = lds_analysis<T>(NCB, GEN);
+    lds_optin<k_legendre_analysis<T, NCB, GEN>>(lds);
+    hipLaunchKernelGGL((k_legendre_analysis<T, NCB, GEN>), grid, block, lds, st, g);
   } else {
     // wider synthesis tiles do not fit the register file
     if constexpr (NCB > kMaxSynthesisNcb) return hipErrorInvalidValue;
     else {
-      lds_optin<k_legendre_synthesis<T, NCB>>(lds_synthesis<T>(NCB));
-      hipLaunchKernelGGL((k_legendre_synthesis<T, NCB>), grid, block, lds_synthesis<T>(NCB), st, g);
+      const size_t lds = lds_synthesis<T>(NCB, GEN);
+      lds_optin<k_legendre_synthesis<T, NCB, GEN>>(lds);
+      hipLaunchKernelGGL((k_legendre_synthesis<T, NCB, GEN>), grid, block, lds, st, g);
     }
   }
   return hipGetLastError();
 }
 
-template <typename T>
-static hipError_t launch_legendre_t(bool analysis, const GemmArgs& g, int ncb,
-                                    hipStream_t st) {
+template <typename T, bool GEN>
+static hipError_t launch_legendre_t(bool analysis, const GemmArgs& g, int ncb, hipStream_t st) {
   switch (ncb) {
-    case 1: return launch_ncb<T, 1>(analysis, g, st);
-    case 2: return launch_ncb<T, 2>(analysis, g, st);
-    case 4: return launch_ncb<T, 4>(analysis, g, st);
-    case 5: return launch_ncb<T, 5>(analysis, g, st);
-    case 8: return launch_ncb<T, 8>(analysis, g, st);
-    case 10: return launch_ncb<T, 10>(analysis, g, st);
+    case 1: return launch_ncb<T, 1, GEN>(analysis, g, st);
+    case 2: return launch_ncb<T, 2, GEN>(analysis, g, st);
+    case 4: return launch_ncb<T, 4, GEN>(analysis, g, st);
+    case 5: return launch_ncb<T, 5, GEN>(analysis, g, st);
+    case 8: return launch_ncb<T, 8, GEN>(analysis, g, st);
+    case 10: return launch_ncb<T, 10, GEN>(analysis, g, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -757,12 +691,15 @@ int max_ncb(int form, bool analysis) {
   return analysis ? 10 : kMaxSynthesisNcb;
 }
 
-int launch_legendre(int form, bool analysis, const GemmArgs& g, int ncb,
-                    void* stream) {
+int launch_legendre(int form, bool analysis, const GemmArgs& g, int ncb, bool gen, void* stream) {
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if (form == SHT_FORM_BF16X6) return (int)launch_legendre_bf16(analysis, g, ncb, st);
-  if (form == SHT_FORM_FP64) return (int)launch_legendre_t<double>(analysis, g, ncb, st);
-  return (int)launch_legendre_t<float>(analysis, g, ncb, st);
+  if (g.ntiles <= 0) return (int)hipSuccess;
+  if (form == SHT_FORM_BF16X6) return (int)launch_legendre_bf16(analysis, g, ncb, gen, st);
+  if (form == SHT_FORM_FP64)
+    return (int)(gen ? launch_legendre_t<double, true>(analysis, g, ncb, st)
+                     : launch_legendre_t<double, false>(analysis, g, ncb, st));
+  return (int)(gen ? launch_legendre_t<float, true>(analysis, g, ncb, st)
+                   : launch_legendre_t<float, false>(analysis, g, ncb, st));
 }
 
 }  // namespace sht

@@ -143,14 +143,26 @@ struct X6Analysis {
   static constexpr int TASKS = 4 * BN;               // (parity, column quad, g, half)
   static constexpr int TR = (TASKS + 511) / 512;     // task rounds per thread
   static constexpr int CS = BN + 1;                  // output staging pitch
-  static constexpr size_t lds_bytes() {
-    const size_t main = (size_t)2 * STAGE * 2;
+  static constexpr int PS = 256 * KB;                // GEN: generated block, FP32
+  static constexpr size_t lds_bytes(bool gen) {
+    const size_t main = (size_t)2 * STAGE * 2 + (gen ? (size_t)PS * 4 : 0);
     const size_t cst = (size_t)64 * CS * 4;
     return main > cst ? main : cst;
   }
 };
 
-template <int NCB>
+// Swizzle of the generated analysis block [256 rows][32 latitudes] (FP32):
+// element (row, lat) at row * 32 + (lat ^ x6_swz(row)).
+__device__ __forceinline__ int x6_swz(int row) { return 2 * ((row >> 1) & 15); }
+
+// GEN: the FP32 table values are generated in the kernel instead (the
+// three-term recurrence of Sec. 4.1 in FP64 from the plan's seed rows,
+// rounded once to FP32, so that the pieces equal those of the table path):
+// per K block thread t produces the 16 rows of group t / 32 of the tile at
+// latitude t % 32 into an LDS block; after a barrier each wave reads and
+// splits its values, and a second barrier guards the block against the
+// next block's writes.
+template <int NCB, bool GEN>
 __global__ __launch_bounds__(X6Analysis<NCB>::NT) __attribute__((amdgpu_waves_per_eu(2))) void k_legendre_analysis_bf16(const GemmArgs g) {
   using S = X6Analysis<NCB>;
   constexpr int BN = S::BN, KB = S::KB, P = kX6Pitch, TR = S::TR;
@@ -179,8 +191,34 @@ __global__ __launch_bounds__(X6Analysis<NCB>::NT) __attribute__((amdgpu_waves_pe
   const int nrb = (nm + 127) / 128;
   const int rbt = 2 * t.rb + th < nrb ? 2 * t.rb + th : nrb - 1;
   // run 4 q + p of the table block; row block h adds two runs
-  const float* arow = static_cast<const float*>(g.table) + g.tab_off[L.m_base + m] +
-                      (long long)rbt * Kp * 128 + (4 * q + p) * 16 * KB + lane * 4;
+  const float* arow = GEN ? nullptr
+                          : static_cast<const float*>(g.table) + g.tab_off[L.m_base + m] +
+                                (long long)rbt * Kp * 128 + (4 * q + p) * 16 * KB + lane * 4;
+  float* Ps = reinterpret_cast<float*>(Bs + 2 * S::STAGE);  // GEN: [256 rows][32 latitudes], swizzled
+  const int ggrp = tid >> 5, glat = tid & 31;
+  const int gi = t.rb * 16 + ggrp;
+  const bool gon = GEN && 16 * gi < nm;
+  const double* gseed = GEN ? g.seeds + g.seed_off[L.m_base + m] + (gon ? 2LL * gi * Kp : 0LL) : nullptr;
+  const double* grec = GEN ? g.rec + g.rec_off[L.m_base + m] : nullptr;
+  double gmu[2] = {0.0, 0.0}, gx0[2] = {0.0, 0.0}, gx1[2] = {0.0, 0.0};
+  auto gen_fetch = [&](int kb, int set) __attribute__((always_inline)) {
+    if constexpr (GEN) {
+      if (gon) {
+        const int j = kb * KB + glat;
+        gmu[set] = L.murow[j];
+        gx0[set] = gseed[j];
+        gx1[set] = 16 * gi + 1 < nm ? gseed[Kp + j] : 0.0;
+      }
+    }
+  };
+  auto gen_store = [&](int set) __attribute__((always_inline)) {
+    if constexpr (GEN) {
+      gen_rows16(grec, 16 * gi, gon ? nm : 0, gmu[set], gx0[set], gx1[set], [&](int s2, double x) {
+        const int row = 16 * ggrp + s2;
+        Ps[row * 32 + (glat ^ x6_swz(row))] = (float)x;
+      });
+    }
+  };
 
   // right-hand tasks: source offset (latitude 0 of the block) and LDS offset
   const float* bsrc[TR];
@@ -206,11 +244,13 @@ __global__ __launch_bounds__(X6Analysis<NCB>::NT) __attribute__((amdgpu_waves_pe
   bf16x8 acur[2][3];   // pieces of the table block being multiplied
 
   auto gload = [&](int kb, int set) __attribute__((always_inline)) {
+    if constexpr (!GEN) {
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
+      for (int h = 0; h < 2; ++h)
 #pragma unroll
-      for (int v = 0; v < 2; ++v)
-        araw[set][h][v] = *reinterpret_cast<const f4*>(arow + (long long)kb * 128 * KB + h * 32 * KB + v * 256);
+        for (int v = 0; v < 2; ++v)
+          araw[set][h][v] = *reinterpret_cast<const f4*>(arow + (long long)kb * 128 * KB + h * 32 * KB + v * 256);
+    }
 #pragma unroll
     for (int i = 0; i < TR; ++i)
 #pragma unroll
@@ -222,6 +262,18 @@ __global__ __launch_bounds__(X6Analysis<NCB>::NT) __attribute__((amdgpu_waves_pe
     for (int h = 0; h < 2; ++h) {
       const float x[8] = {araw[set][h][0][0], araw[set][h][0][1], araw[set][h][0][2], araw[set][h][0][3],
                           araw[set][h][1][0], araw[set][h][1][1], araw[set][h][1][2], araw[set][h][1][3]};
+      split3(x, acur[h]);
+    }
+  };
+  // GEN: the wave's values of the generated block, split (slot 8 g + e holds
+  // latitude 4 e + g)
+  auto gen_split_a = [&]() __attribute__((always_inline)) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int rr = 128 * th + 64 * q + 32 * h + 2 * li + p;
+      float x[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) x[e] = Ps[rr * 32 + ((4 * e + lg) ^ x6_swz(rr))];
       split3(x, acur[h]);
     }
   };
@@ -261,16 +313,22 @@ __global__ __launch_bounds__(X6Analysis<NCB>::NT) __attribute__((amdgpu_waves_pe
   auto step = [&](auto act, auto hc, int kb) __attribute__((always_inline)) {
     constexpr bool ACT = decltype(act)::value;
     constexpr int H = decltype(hc)::value;
+    gen_fetch(kb + 2 < nkb ? kb + 2 : nkb - 1, H);
     gload(kb + 2 < nkb ? kb + 2 : nkb - 1, H);
     // keep the loads ahead of the block's work (the scheduler would sink
     // them towards their distant uses)
     __builtin_amdgcn_sched_barrier(0);
     if constexpr (ACT) {
       compute(H);
-      split_a(1 - H);
+      if constexpr (!GEN) split_a(1 - H);
     }
+    gen_store(1 - H);  // block kb + 1 (clamped after the last: nothing reads it)
     split_b(1 - H, 1 - H);
     lds_barrier();
+    if constexpr (GEN) {
+      if constexpr (ACT) gen_split_a();
+      lds_barrier();
+    }
   };
   // pairs of blocks with a branch-free body, then an odd last block
   // reduced transform: the blocks before kb0 hold only latitudes where
@@ -287,9 +345,19 @@ __global__ __launch_bounds__(X6Analysis<NCB>::NT) __attribute__((amdgpu_waves_pe
 
   gload(kb0, 0);
   gload(kb0 + 1 < nkb ? kb0 + 1 : nkb - 1, 1);
-  split_a(0);
+  if constexpr (GEN) {
+    gen_fetch(kb0, 0);
+    gen_store(0);
+    gen_fetch(kb0 + 1 < nkb ? kb0 + 1 : nkb - 1, 1);
+  } else {
+    split_a(0);
+  }
   split_b(0, 0);
   __syncthreads();
+  if constexpr (GEN) {
+    if (active) gen_split_a();
+    __syncthreads();
+  }
   if (active)
     run(std::true_type{});
   else
@@ -350,10 +418,15 @@ struct X6Synthesis {
   static constexpr int TASKS = 4 * BN;              // (field, g, s): 8 natural rows
   static constexpr int TR = (TASKS + 511) / 512;
   static constexpr int CHUNK = 128 * 32;            // FP32 table block (32 natural rows)
-  static constexpr size_t lds_bytes() { return (size_t)2 * STAGE * 2; }
+  static constexpr int GP = 130;                    // GEN: pitch of the generated block [64 rows][128 latitudes]
+  static constexpr size_t lds_bytes(bool gen) { return (size_t)2 * STAGE * 2 + (gen ? (size_t)64 * GP * 4 : 0); }
 };
 
-template <int NCB>
+// GEN: the FP32 table values are generated in the kernel (as in the
+// analysis): per block of 64 natural rows wave w produces the 16 rows of
+// group w >> 1 at the latitudes 64 (w & 1) + lane of the tile into an LDS
+// block [row][GP].
+template <int NCB, bool GEN>
 __global__ __launch_bounds__(X6Synthesis<NCB>::NT) __attribute__((amdgpu_waves_per_eu(2))) void k_legendre_synthesis_bf16(const GemmArgs g) {
   using S = X6Synthesis<NCB>;
   constexpr int BN = S::BN, P = kX6Pitch, TR = S::TR;
@@ -381,8 +454,35 @@ __global__ __launch_bounds__(X6Synthesis<NCB>::NT) __attribute__((amdgpu_waves_p
   const int p = w & 1, q = w >> 1;
   const int li = lane & 15, lg = lane >> 4;
   const bool active = jt * 128 + 32 * q < L.Jh;
-  const float* arun = static_cast<const float*>(g.table) + g.tab_off[L.m_base + m] +
-                      (long long)jt * nkb32 * S::CHUNK + w * (S::CHUNK / 8) + lane * 4;
+  const float* arun = GEN ? nullptr
+                          : static_cast<const float*>(g.table) + g.tab_off[L.m_base + m] +
+                                (long long)jt * nkb32 * S::CHUNK + w * (S::CHUNK / 8) + lane * 4;
+  float* Ps = reinterpret_cast<float*>(Bs + 2 * S::STAGE);  // GEN: [64 rows][GP]
+  // wave w generates group w >> 1 of each block (uniform across the wave)
+  // at latitude 64 (w & 1) + lane of the tile
+  const int gsub = w >> 1, glat = 64 * (w & 1) + lane;
+  const int gj = jt * 128 + glat;
+  const bool gjin = GEN && gj < L.Kp;
+  const double* gseeds = GEN ? g.seeds + g.seed_off[L.m_base + m] : nullptr;
+  const double* grec = GEN ? g.rec + g.rec_off[L.m_base + m] : nullptr;
+  const double gmu = gjin ? L.murow[gj] : 0.0;
+  double gx0[2] = {0.0, 0.0}, gx1[2] = {0.0, 0.0};
+  auto gen_fetch = [&](int kb, int set) __attribute__((always_inline)) {
+    if constexpr (GEN) {
+      const int gi = 4 * kb + gsub;
+      if (gjin && 16 * gi < nm) {
+        gx0[set] = gseeds[2LL * gi * L.Kp + gj];
+        gx1[set] = 16 * gi + 1 < nm ? gseeds[(2LL * gi + 1) * L.Kp + gj] : 0.0;
+      }
+    }
+  };
+  auto gen_store = [&](int kb, int set) __attribute__((always_inline)) {
+    if constexpr (GEN) {
+      const int gi = 4 * kb + gsub;
+      gen_rows16(grec, 16 * gi, gjin ? nm : 0, gmu, gx0[set], gx1[set],
+                 [&](int s2, double x) { Ps[(16 * gsub + s2) * S::GP + glat] = (float)x; });
+    }
+  };
 
   // The tile's spectra as a buffer starting at its first field and wave
   // number: reads past the end of the level's spectra return zero (fields
@@ -420,12 +520,14 @@ __global__ __launch_bounds__(X6Synthesis<NCB>::NT) __attribute__((amdgpu_waves_p
   bf16x8 acur[2][3];
 
   auto gload = [&](int kb, int set) __attribute__((always_inline)) {
+    if constexpr (!GEN) {
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      const int k32 = 2 * kb + s < nkb32 ? 2 * kb + s : nkb32 - 1;  // clamped: those rows are masked
+      for (int s = 0; s < 2; ++s) {
+        const int k32 = 2 * kb + s < nkb32 ? 2 * kb + s : nkb32 - 1;  // clamped: those rows are masked
 #pragma unroll
-      for (int jb = 0; jb < 2; ++jb)
-        araw[set][s][jb] = *reinterpret_cast<const f4*>(arun + (long long)k32 * S::CHUNK + jb * 256);
+        for (int jb = 0; jb < 2; ++jb)
+          araw[set][s][jb] = *reinterpret_cast<const f4*>(arun + (long long)k32 * S::CHUNK + jb * 256);
+      }
     }
 #pragma unroll
     for (int i = 0; i < TR; ++i) {
@@ -440,6 +542,20 @@ __global__ __launch_bounds__(X6Synthesis<NCB>::NT) __attribute__((amdgpu_waves_p
     for (int jb = 0; jb < 2; ++jb) {
       const float x[8] = {araw[set][0][jb][0], araw[set][0][jb][1], araw[set][0][jb][2], araw[set][0][jb][3],
                           araw[set][1][jb][0], araw[set][1][jb][1], araw[set][1][jb][2], araw[set][1][jb][3]};
+      split3(x, acur[jb]);
+    }
+  };
+  // GEN: the wave's values of the generated block, split (slot 8 g + 4 s + u
+  // holds r' = 16 s + 4 g + u, natural row 2 r' + p)
+  auto gen_split_a = [&]() __attribute__((always_inline)) {
+#pragma unroll
+    for (int jb = 0; jb < 2; ++jb) {
+      float x[8];
+#pragma unroll
+      for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          x[4 * s2 + u] = Ps[(32 * s2 + 8 * lg + 2 * u + p) * S::GP + 32 * q + 16 * jb + li];
       split3(x, acur[jb]);
     }
   };
@@ -483,16 +599,22 @@ __global__ __launch_bounds__(X6Synthesis<NCB>::NT) __attribute__((amdgpu_waves_p
     constexpr bool ACT = decltype(act)::value;
     constexpr int H = decltype(hc)::value;
     const int kn = kb + 1 < nkb ? kb + 1 : nkb - 1;
+    gen_fetch(kb + 2 < nkb ? kb + 2 : nkb - 1, H);
     gload(kb + 2 < nkb ? kb + 2 : nkb - 1, H);
     // keep the loads ahead of the block's work (the scheduler would sink
     // them towards their distant uses)
     __builtin_amdgcn_sched_barrier(0);
     if constexpr (ACT) {
       compute(H);
-      split_a(1 - H);
+      if constexpr (!GEN) split_a(1 - H);
     }
+    gen_store(kn, 1 - H);
     split_b(1 - H, 1 - H, kn);
     lds_barrier();
+    if constexpr (GEN) {
+      if constexpr (ACT) gen_split_a();
+      lds_barrier();
+    }
   };
   // pairs of blocks with a branch-free body, then an odd last block
   auto run = [&](auto act) __attribute__((always_inline)) {
@@ -509,9 +631,19 @@ __global__ __launch_bounds__(X6Synthesis<NCB>::NT) __attribute__((amdgpu_waves_p
   if (jt * 128 + 128 > g.jstart[L.m_base + m]) {
     gload(0, 0);
     gload(nkb > 1 ? 1 : 0, 1);
-    split_a(0);
+    if constexpr (GEN) {
+      gen_fetch(0, 0);
+      gen_store(0, 0);
+      gen_fetch(nkb > 1 ? 1 : 0, 1);
+    } else {
+      split_a(0);
+    }
     split_b(0, 0, 0);
     __syncthreads();
+    if constexpr (GEN) {
+      if (active) gen_split_a();
+      __syncthreads();
+    }
     if (active)
       run(std::true_type{});
     else
@@ -536,30 +668,35 @@ __global__ __launch_bounds__(X6Synthesis<NCB>::NT) __attribute__((amdgpu_waves_p
 // ---------------------------------------------------------------------------
 // launcher
 // ---------------------------------------------------------------------------
-template <int NCB>
+template <int NCB, bool GEN>
 static hipError_t launch_bf16_ncb(bool analysis, const GemmArgs& g, hipStream_t st) {
   const dim3 grid(g.ntiles);
   if (analysis) {
-    const size_t lds = X6Analysis<NCB>::lds_bytes();
-    lds_optin<k_legendre_analysis_bf16<NCB>>(lds);
-    hipLaunchKernelGGL((k_legendre_analysis_bf16<NCB>), grid, dim3(X6Analysis<NCB>::NT), lds, st, g);
+    const size_t lds = X6Analysis<NCB>::lds_bytes(GEN);
+    lds_optin<k_legendre_analysis_bf16<NCB, GEN>>(lds);
+    hipLaunchKernelGGL((k_legendre_analysis_bf16<NCB, GEN>), grid, dim3(X6Analysis<NCB>::NT), lds, st, g);
   } else {
-    const size_t lds = X6Synthesis<NCB>::lds_bytes();
-    lds_optin<k_legendre_synthesis_bf16<NCB>>(lds);
-    hipLaunchKernelGGL((k_legendre_synthesis_bf16<NCB>), grid, dim3(X6Synthesis<NCB>::NT), lds, st, g);
+    const size_t lds = X6Synthesis<NCB>::lds_bytes(GEN);
+    lds_optin<k_legendre_synthesis_bf16<NCB, GEN>>(lds);
+    hipLaunchKernelGGL((k_legendre_synthesis_bf16<NCB, GEN>), grid, dim3(X6Synthesis<NCB>::NT), lds, st, g);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_legendre_bf16(bool analysis, const GemmArgs& g, int ncb, hipStream_t st) {
+template <bool GEN>
+static hipError_t launch_bf16_gen(bool analysis, const GemmArgs& g, int ncb, hipStream_t st) {
   switch (ncb) {
-    case 1: return launch_bf16_ncb<1>(analysis, g, st);
-    case 2: return launch_bf16_ncb<2>(analysis, g, st);
-    case 4: return launch_bf16_ncb<4>(analysis, g, st);
-    case 5: return launch_bf16_ncb<5>(analysis, g, st);
-    case 8: return launch_bf16_ncb<8>(analysis, g, st);
+    case 1: return launch_bf16_ncb<1, GEN>(analysis, g, st);
+    case 2: return launch_bf16_ncb<2, GEN>(analysis, g, st);
+    case 4: return launch_bf16_ncb<4, GEN>(analysis, g, st);
+    case 5: return launch_bf16_ncb<5, GEN>(analysis, g, st);
+    case 8: return launch_bf16_ncb<8, GEN>(analysis, g, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_legendre_bf16(bool analysis, const GemmArgs& g, int ncb, bool gen, hipStream_t st) {
+  return gen ? launch_bf16_gen<true>(analysis, g, ncb, st) : launch_bf16_gen<false>(analysis, g, ncb, st);
 }
 
 }  // namespace sht

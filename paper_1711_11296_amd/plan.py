@@ -37,9 +37,9 @@ class Plan:
     buffer, output buffer) triple is captured into a hipGraph on its first
     call and replayed afterwards; at most 16 graphs are kept per plan, so pass
     the same out= buffers on every call (without out= a new output tensor,
-    hence a new capture, may be made each time).  otf (FP64 form only): both
-    Legendre kernels generate P~ from two stored seed rows per 16 degrees
-    instead of reading a table (see sht_options.otf).
+    hence a new capture, may be made each time).  otf: both Legendre kernels
+    generate P~ in FP64 from two stored seed rows per 16 degrees instead of
+    reading a table, in every form (see sht_options.otf).
     """
 
     def __init__(self, N=None, J=None, I=None, nfields=None, *, levels=None, grid="cc_poles",
