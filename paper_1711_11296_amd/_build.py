@@ -18,7 +18,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 HIP_SOURCES = ["sht_fft.hip", "sht_legendre.hip", "sht_legendre_bf16.hip", "sht_transfer.hip", "sht_api.hip"]
-CXX_SOURCES = ["sht_host.cpp"]
+CXX_SOURCES = ["sht_host.cpp", "sht_plan.cpp"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-I" + CSRC, "-I" + os.path.join(os.path.dirname(HERE), "include")]
 HIP_FLAGS = COMMON + ["--offload-arch=" + ARCH, "-mcode-object-version=5",

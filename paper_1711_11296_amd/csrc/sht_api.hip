@@ -10,12 +10,14 @@
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
+#include <numeric>
 #include <set>
 #include <string>
 #include <thread>
 #include <vector>
 
 #include "sht_internal.h"
+#include "sht_plan.h"
 
 using namespace sht;
 
@@ -45,7 +47,6 @@ bool is_live(const void* p) {
   return g_live.count(p) != 0;
 }
 
-long long roundup(long long a, long long b) { return (a + b - 1) / b * b; }
 
 }  // namespace
 
@@ -186,188 +187,6 @@ int check_level_args(int N, int J, int I, int F, int grid) {
   return SHT_OK;
 }
 
-// Column blocking shared by all levels: the one that pads the least
-// (weighted by the Legendre work), preferring wider tiles on ties.
-int choose_ncb(int form, int nlev, const int* N, const int* J, const int* F) {
-  const int cand64[] = {8, 4, 2, 1};
-  const int cand32[] = {10, 8, 5, 4, 2, 1};
-  const int* cand = form == SHT_FORM_FP64 ? cand64 : cand32;
-  const int nc = form == SHT_FORM_FP64 ? 4 : 6;
-  int best = 1;
-  double bestc = 1e300;
-  for (int k = 0; k < nc; ++k) {
-    double c = 0;
-    for (int l = 0; l < nlev; ++l) {
-      double work = (double)(N[l] + 1) * (N[l] + 2) * ((J[l] + 1) / 2);
-      c += work * (double)roundup(2LL * F[l], 16LL * cand[k]);
-    }
-    if (c < bestc * (1 - 1e-12)) {
-      bestc = c;
-      best = cand[k];
-    }
-  }
-  return best;
-}
-
-// Split a tile list (in locality order) into 8 contiguous chunks of equal
-// cost and deal them so that chunk x runs on XCD x (block id % 8 == x).
-std::vector<Tile> xcd_schedule(const std::vector<Tile>& tiles, const std::vector<double>& cost) {
-  const int X = 8;
-  double total = 0;
-  for (double c : cost) total += c;
-  std::vector<std::vector<Tile>> chunk(X);
-  double acc = 0;
-  int x = 0;
-  for (size_t i = 0; i < tiles.size(); ++i) {
-    chunk[x].push_back(tiles[i]);
-    acc += cost[i];
-    while (x < X - 1 && acc >= total * (x + 1) / X) ++x;
-  }
-  size_t len = 0;
-  for (auto& c : chunk) len = std::max(len, c.size());
-  std::vector<Tile> out(len * X, Tile{-1, 0, 0, 0});
-  for (int xx = 0; xx < X; ++xx)
-    for (size_t i = 0; i < chunk[xx].size(); ++i) out[i * X + xx] = chunk[xx][i];
-  return out;
-}
-
-// Fill both copies of one level's table from FP64 columns of P~:
-//  analysis copy: per m, rows r = n - m padded to 128, blocked in the order
-//  the analysis kernel streams it: per (128-row tile, KB-column block) one
-//  contiguous chunk (KB = 32 for float, 16 for double), inside it one run
-//  per wave (16 rows r = 32 q + 2 i + p), inside that one 64-lane vector
-//  after the other: vector v of lane (i, g) holds columns 4 (v E + e) + g,
-//  e < E = 16 bytes / element size;
-//  synthesis copy: per m, one chunk per (128-latitude tile, K block of 32
-//  natural rows), blocked per wave and lane vector like the analysis copy
-//  (see the loop below).
-// Tile list of one Legendre kernel for column blocking ncb (16*ncb columns
-// per tile; the workspace row length Cp must be a multiple of it).
-// sched 0: the list in locality order (m, column block, row block) cut into
-// 8 chunks of equal cost, chunk x dealt to block ids == x (mod 8), i.e. to
-// XCD x; sched 1: the same order dealt round robin.
-std::vector<Tile> build_tiles(const sht_plan_s* P, bool analysis, int ncb, int sched) {
-  const int BN = 16 * ncb;
-  std::vector<Tile> t;
-  std::vector<double> c;
-  for (int l = 0; l < P->nlev; ++l) {
-    const LevelDesc& L = P->lev[l];
-    // column tiles that hold at least one field (the row length may be
-    // padded past the last field by more than a tile)
-    const int ncol = std::min(L.Cp / BN, (2 * L.F + BN - 1) / BN);
-    for (int m = 0; m <= L.N; ++m) {
-      const int nm = L.N - m + 1;
-      const int j0 = P->jst[L.m_base + m];  // reduced transform: latitudes below are left out
-      for (int cb = 0; cb < ncol; ++cb) {
-        if (analysis) {
-          // 128-row tiles; 256 in the split form; K blocks of 32 latitudes
-          // (16 in the FP64 form)
-          const int rows = P->form == SHT_FORM_BF16X6 ? 256 : 128;
-          const int kb = P->form == SHT_FORM_FP64 ? 16 : 32;
-          for (int rb = 0; rb < (nm + rows - 1) / rows; ++rb) {
-            t.push_back(Tile{l, m, rb, cb});
-            c.push_back((double)(L.Kp - j0 / kb * kb) * BN);
-          }
-        } else {
-          // 128-latitude tiles; K blocks of 32 natural rows (64 in the
-          // split form); tiles wholly below j0 are left out (the zonal
-          // synthesis reads those workspace rows as zero)
-          const int kr2 = P->form == SHT_FORM_BF16X6 ? 64 : 32;
-          for (int jt = j0 / 128; jt < (L.Jh + 127) / 128; ++jt) {
-            t.push_back(Tile{l, m, jt, cb});
-            c.push_back(((double)roundup(nm, kr2) + kr2) * 2 * BN);
-          }
-        }
-      }
-    }
-  }
-  if (sched == 1) return t;
-  return xcd_schedule(t, c);
-}
-
-template <typename T>
-void fill_table_level(const LevelDesc& L, const double* mu, const double* sint,
-                      T* dst, const long long* off_a, T* dsyn, const long long* off_s, int* j0,
-                      double* seeds, const long long* off_seed) {
-  const int N = L.N, Jh = L.Jh, Kp = L.Kp;
-  int nth = (int)std::thread::hardware_concurrency();
-  nth = std::max(1, std::min(nth, 64));
-  std::vector<std::thread> pool;
-  for (int t = 0; t < nth; ++t) {
-    pool.emplace_back([=]() {
-      std::vector<double> col;
-      for (int k = t; k <= N; k += nth) {
-        const int m = (k % 2 == 0) ? k / 2 : N - k / 2;
-        const int nm = N - m + 1;
-        col.assign((size_t)nm * Jh, 0.0);
-        alf_column(N, m, Jh, mu, sint, col.data(), Jh);
-        if (j0) {
-          // reduced transform (Sec. 4.1): first latitude (from the pole) at
-          // which some |P~_n^m| reaches 1e-16
-          int first = Jh;
-          for (int r = 0; r < nm; ++r)
-            for (int j = 0; j < first; ++j)
-              if (std::fabs(col[(size_t)r * Jh + j]) >= 1e-16) {
-                first = j;
-                break;
-              }
-          j0[m] = first;
-        }
-        if (seeds) {
-          // generated analysis: rows 16 g and 16 g + 1 of every 16-degree group
-          double* sd = seeds + off_seed[m];
-          for (int g = 0; g < (nm + 15) / 16; ++g)
-            for (int t2 = 0; t2 < 2; ++t2) {
-              const int r = 16 * g + t2;
-              for (int j = 0; j < Kp; ++j)
-                sd[(size_t)(2 * g + t2) * Kp + j] = (r < nm && j < Jh) ? col[(size_t)r * Jh + j] : 0.0;
-            }
-        }
-        if (!dst) continue;  // generated P~: seed rows only
-        T* blk = dst + off_a[m];
-        const int R = (int)roundup(nm, 128);
-        constexpr int KB = sizeof(T) == 4 ? 32 : 16, E = 16 / (int)sizeof(T);
-        const int nkbk = Kp / KB;
-        for (int r = 0; r < R; ++r)
-          for (int j = 0; j < Kp; ++j) {
-            const int rt = r / 128, rr = r % 128;
-            const int q = rr / 32, i = (rr % 32) / 2, p = rr % 2;
-            const int kb = j / KB, jj = j % KB;
-            const int g = jj % 4, kk = jj / 4;
-            const int v = kk / E, e = kk % E;
-            const size_t d = ((size_t)rt * nkbk + kb) * 128 * KB + (size_t)(2 * q + p) * 16 * KB +
-                             (size_t)((v * 4 + g) * 16 + i) * E + e;
-            blk[d] = (r < nm && j < Jh) ? (T)col[(size_t)r * Jh + j] : (T)0;
-          }
-        // synthesis copy: per (128-latitude tile, K block of 2 KR natural
-        // rows) one chunk; inside it one run per wave (parity p, quarter q)
-        // of 64-lane vectors: vector v of lane (i, g) holds latitude
-        // 32 q + 16 (v / (KQ/E)) + i and r' = g KQ + E (v % (KQ/E)) + e
-        constexpr int KR = 16, KQs = KR / 4, NVs = 2 * KQs / E;
-        const int nkbs = (nm + 2 * KR - 1) / (2 * KR);
-        const int JT = (Jh + 127) / 128;
-        const size_t chunk = (size_t)128 * 2 * KR;
-        T* sb = dsyn + off_s[m];
-        for (int jt = 0; jt < JT; ++jt)
-          for (int kb = 0; kb < nkbs; ++kb)
-            for (int w = 0; w < 8; ++w)
-              for (int v = 0; v < NVs; ++v)
-                for (int ln = 0; ln < 64; ++ln)
-                  for (int e = 0; e < E; ++e) {
-                    const int p = w & 1, q = w >> 1, i = ln & 15, g = ln >> 4;
-                    const int jb = v / (KQs / E), kk = (v % (KQs / E)) * E + e;
-                    const int r = kb * 2 * KR + 2 * (g * KQs + kk) + p;
-                    const int j = jt * 128 + 32 * q + 16 * jb + i;
-                    const size_t d = ((size_t)jt * nkbs + kb) * chunk + (size_t)w * (chunk / 8) +
-                                     (size_t)(v * 64 + ln) * E + e;
-                    sb[d] = (r < nm && j < Jh) ? (T)col[(size_t)r * Jh + j] : (T)0;
-                  }
-      }
-    });
-  }
-  for (auto& th : pool) th.join();
-}
-
 int autotune(sht_plan_s* P);
 
 int build_plan(int nlev, const int* Nv, const int* Jv, const int* Iv, const int* Fv,
@@ -406,55 +225,21 @@ int build_plan(int nlev, const int* Nv, const int* Jv, const int* Iv, const int*
   if (FB > 8) {
     // the wide blocking runs only in the fixed-length kernel, whose
     // workspace offsets are 32-bit
-    const long long Cp = roundup(2LL * Fv[0], std::max(BN, 2 * FB));
+    const long long Cp = roundup(2LL * Fv[0], std::lcm(BN, 2 * FB));
     const long long Kp = roundup((Jv[0] + 1) / 2, SHT_K_PAD);
     if ((double)(Nv[0] + 1) * 2.0 * Kp * Cp * P->elem >= 4294967296.0) FB = 8;
   }
   P->fb = FB;
 
   // ---- level descriptors and sizes ----
-  long long goff = 0, soff = 0, woff = 0, moff = 0, item = 0;
-  std::vector<long long> taboff, taboff_syn, seedoff, recoff;
-  long long tab = 0, tabs = 0, seeds_total = 0, rec_total = 0;
+  Layout Y;
+  layout_levels(nlev, Nv, Jv, Iv, Fv, BN, FB, P->lev, &Y);
+  const long long item = Y.items, goff = Y.grid, soff = Y.spec, woff = Y.ws, moff = Y.nm_total;
+  const std::vector<long long>&taboff = Y.taboff, &taboff_syn = Y.taboff_syn, &seedoff = Y.seedoff,
+                           &recoff = Y.recoff;
+  const long long tab = Y.tab, tabs = Y.tabs, seeds_total = Y.seeds, rec_total = Y.rec;
   for (int l = 0; l < nlev; ++l) {
-    LevelDesc& L = P->lev[l];
-    std::memset(&L, 0, sizeof(L));
-    L.N = Nv[l];
-    L.J = Jv[l];
-    L.I = Iv[l];
-    L.F = Fv[l];
-    L.Jh = (L.J + 1) / 2;
-    L.Kp = (int)roundup(L.Jh, SHT_K_PAD);
-    L.Cp = (int)roundup(2LL * L.F, std::max(BN, 2 * FB));
-    factor_radices(L.I, L.rad, &L.nrad);
-    for (int q = 0, ns = 1; q < L.nrad; ns *= L.rad[q], ++q) {
-      L.pns[q] = ns;
-      L.ptw[q] = L.I / (ns * L.rad[q]);
-      L.pmag[q] = ns > 1 ? 0xFFFFFFFFu / (unsigned)ns + 1u : 0u;
-    }
-    L.nfb = (L.F + FB - 1) / FB;
-    L.fft_item0 = (int)item;
-    item += (long long)L.Jh * L.nfb;
-    L.m_base = (int)moff;
-    moff += L.N + 1;
-    L.grid_off = goff;
-    goff += (long long)L.F * L.J * L.I;
-    L.spec_off = soff;
-    soff += (long long)L.F * (L.N + 1) * (L.N + 2);
-    L.ws_off = woff;
-    woff += roundup((long long)(L.N + 1) * 2 * L.Kp * L.Cp, 64);
-    for (int m = 0; m <= L.N; ++m) {
-      taboff.push_back(tab);
-      // analysis copy: rows padded to the row tile of 128
-      tab += roundup(L.N - m + 1, 128) * L.Kp;
-      taboff_syn.push_back(tabs);
-      const int kr2 = 32;  // natural rows per K block
-      tabs += (long long)((L.Jh + 127) / 128) * ((L.N - m + kr2) / kr2) * 128 * kr2;
-      seedoff.push_back(seeds_total);
-      seeds_total += 2LL * ((L.N - m + 16) / 16) * L.Kp;
-      recoff.push_back(rec_total);
-      rec_total += 2LL * (L.N - m + 1);
-    }
+    const LevelDesc& L = P->lev[l];
     P->maxN = std::max(P->maxN, L.N);
     P->flops += 2.0 * L.Jh * (double)(L.N + 1) * (L.N + 2) * L.F;
     // Gauss-Legendre on J nodes is exact to degree 2J-1, the CC rules to J-1
@@ -567,7 +352,8 @@ int build_plan(int nlev, const int* Nv, const int* Jv, const int* Iv, const int*
     for (int m = 0; m <= L.N; ++m)
       P->flops_kept += 4.0 * (L.N - m + 1) * L.F * (double)(L.Jh - P->jst[L.m_base + m] / kb * kb);
   }
-  std::vector<Tile> sf = build_tiles(P, true, P->ncb_fwd, 0), si = build_tiles(P, false, P->ncb_inv, 0);
+  std::vector<Tile> sf = build_tiles(P->form, P->nlev, P->lev, P->jst.data(), true, P->ncb_fwd, 0),
+                    si = build_tiles(P->form, P->nlev, P->lev, P->jst.data(), false, P->ncb_inv, 0);
   P->ntiles_fwd = (int)sf.size();
   P->ntiles_inv = (int)si.size();
 
@@ -982,7 +768,7 @@ int autotune(sht_plan_s* P) {
         for (int sched = 0; sched < 2 && !rc; ++sched) {
           const int c = all[k];
           if (!blocking_ok(P, analysis, c)) continue;
-          std::vector<Tile> t = build_tiles(P, analysis, c, sched);
+          std::vector<Tile> t = build_tiles(P->form, P->nlev, P->lev, P->jst.data(), analysis, c, sched);
           Tile* dt = nullptr;
           if ((rc = hip_check(hipMalloc(reinterpret_cast<void**>(&dt), t.size() * sizeof(Tile)), "tune alloc"))) break;
           (void)hipMemcpy(dt, t.data(), t.size() * sizeof(Tile), hipMemcpyHostToDevice);
@@ -1022,8 +808,10 @@ int autotune(sht_plan_s* P) {
   P->sched_fwd = v[1];
   P->ncb_inv = v[2];
   P->sched_inv = v[3];
-  int rc = upload_tiles(P, true, build_tiles(P, true, P->ncb_fwd, P->sched_fwd));
-  if (!rc) rc = upload_tiles(P, false, build_tiles(P, false, P->ncb_inv, P->sched_inv));
+  int rc = upload_tiles(P, true, build_tiles(P->form, P->nlev, P->lev, P->jst.data(), true, P->ncb_fwd, P->sched_fwd));
+  if (!rc)
+    rc = upload_tiles(P, false,
+                      build_tiles(P->form, P->nlev, P->lev, P->jst.data(), false, P->ncb_inv, P->sched_inv));
   return rc;
 }
 

@@ -111,21 +111,52 @@ static void lds_optin(size_t bytes) {
   }
 }
 
-// Generated P~ (plan option otf), shared by both directions and all forms: the rows
-// r = n - m of a block are produced by the three-term recurrence of
+// Generated P~ (plan option otf), shared by both directions and all forms:
+// the rows r = n - m of a block are produced by the three-term recurrence of
 // Sec. 4.1, P~_r = A_r mu P~_{r-1} - B_r P~_{r-2}, in FP64 from the two
 // stored seed rows of each 16-degree group (rows 16 gi and 16 gi + 1 of
-// every latitude), one latitude per thread, and rounded once to the element
-// type; st(s, value) receives row r0 + s.  Rows at or beyond n_m are zero.
-template <class Store>
-__device__ __forceinline__ void gen_rows16(const double* rec, int r0, int nm, double mu, double x0, double x1,
+// every latitude), one latitude per lane, and rounded once to the element
+// type.  The coefficients of a group sit in lanes (gen_coef) and are
+// broadcast per step (v_readlane), so the recurrence waits on no memory; a
+// row at or beyond n_m has zero coefficients and therefore comes out zero,
+// and so does every later row of the group.
+
+// Lane l of a wave holds (A_r, B_r) of row r = r0 + 2 + (l % 32) of its
+// group, for l % 32 < 14 and r < nm (zero otherwise); with TWO the lanes
+// 32..63 belong to a second group (r0 is the lane's own group's first row).
+__device__ __forceinline__ void gen_coef(const double* rec, int r0, int nm, int lane, double& cA, double& cB) {
+  const int r = r0 + 2 + (lane & 31);
+  const bool ok = (lane & 31) < 14 && r < nm;
+  cA = ok ? rec[2 * r] : 0.0;
+  cB = ok ? rec[2 * r + 1] : 0.0;
+}
+
+template <bool TWO>
+__device__ __forceinline__ double gen_bcast(double v, int l) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const int lo = (int)(unsigned)b, hi = (int)(unsigned)(b >> 32);
+  const unsigned long long b0 = ((unsigned long long)(unsigned)__builtin_amdgcn_readlane(hi, l) << 32) |
+                                (unsigned)__builtin_amdgcn_readlane(lo, l);
+  if constexpr (!TWO) {
+    return __builtin_bit_cast(double, b0);
+  } else {
+    const unsigned long long b1 = ((unsigned long long)(unsigned)__builtin_amdgcn_readlane(hi, l + 32) << 32) |
+                                  (unsigned)__builtin_amdgcn_readlane(lo, l + 32);
+    return __builtin_bit_cast(double, (__lane_id() < 32) ? b0 : b1);
+  }
+}
+
+// The 16 rows r0 .. r0 + 15 at one latitude: st(s, value) receives row r0 + s.
+template <bool TWO, class Store>
+__device__ __forceinline__ void gen_rows16(double cA, double cB, int r0, int nm, double mu, double x0, double x1,
                                            Store st) {
-  st(0, r0 < nm ? x0 : 0.0);
-  st(1, r0 + 1 < nm ? x1 : 0.0);
+  x0 = r0 < nm ? x0 : 0.0;
+  x1 = r0 + 1 < nm ? x1 : 0.0;
+  st(0, x0);
+  st(1, x1);
 #pragma unroll
   for (int s = 2; s < 16; ++s) {
-    const int r = r0 + s;
-    const double x2 = r < nm ? rec[2 * r] * mu * x1 - rec[2 * r + 1] * x0 : 0.0;
+    const double x2 = gen_bcast<TWO>(cA, s - 2) * mu * x1 - gen_bcast<TWO>(cB, s - 2) * x0;
     st(s, x2);
     x0 = x1;
     x1 = x2;

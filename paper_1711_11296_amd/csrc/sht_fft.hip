@@ -1200,7 +1200,9 @@ static bool launch_fixed(bool analysis, const FftArgs& a, int maxN, hipStream_t 
     case 2880:
       if constexpr (FB > 8) return false;  // several wavenumbers per thread: 8 fields at most
       else {
-        // two fields per round (four spill registers and ~5 % more time with four)
+        // two fields per round (four spill registers and ~5 % more time with
+        // four); 512 threads: 768- and 1024-thread workgroups (one per CU,
+        // more waves) spill and measured 10-50 % slower at T959
         *err = launch_p3<T, Plan3<2880, 12, 15>, 512, FB, 2>(analysis, a, maxN, st);
         return true;
       }

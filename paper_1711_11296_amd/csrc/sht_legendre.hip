@@ -128,14 +128,15 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
                             w * 16 * KB + lane * E;
   T* Ps = Bs + 2 * S::STAGE;  // GEN: [128 rows][KB latitudes], swizzled (gen_swz)
   // GEN: wave w generates group w (rows 16 w .. 16 w + 15 of the tile), lane
-  // l < KB latitude l of each block; the group is uniform across the wave,
-  // so the recurrence coefficients come through scalar loads
-  const int ggrp = w, glat = lane;
+  // l at latitude l % KB of each block (lanes l and l + KB compute and
+  // store the same values, which keeps the code free of branches); the
+  // group's recurrence coefficients are held in lanes for the whole tile
+  const int ggrp = w, glat = lane & (KB - 1);
   const int gi = t.rb * 8 + ggrp;
-  const bool gthr = GEN && lane < KB;
-  const bool gon = gthr && 16 * gi < nm;
+  const bool gon = GEN && 16 * gi < nm;  // uniform across the wave
   const double* gseed = GEN ? g.seeds + g.seed_off[L.m_base + m] + (gon ? 2LL * gi * Kp : 0LL) : nullptr;
-  const double* grec = GEN ? g.rec + g.rec_off[L.m_base + m] : nullptr;
+  double gcA = 0.0, gcB = 0.0;
+  if constexpr (GEN) gen_coef(g.rec + g.rec_off[L.m_base + m], 16 * gi, nm, lane, gcA, gcB);
   double gmu[2] = {0.0, 0.0}, gx0[2] = {0.0, 0.0}, gx1[2] = {0.0, 0.0};
   auto gen_fetch = [&](int kb, int set) __attribute__((always_inline)) {
     if constexpr (GEN) {
@@ -143,18 +144,16 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
         const int j = kb * KB + glat;
         gmu[set] = L.murow[j];
         gx0[set] = gseed[j];
-        gx1[set] = 16 * gi + 1 < nm ? gseed[Kp + j] : 0.0;
+        gx1[set] = gseed[Kp + j];  // (a zero row when 16 gi + 1 = n_m: the seed rows are padded)
       }
     }
   };
   auto gen_store = [&](int set) __attribute__((always_inline)) {
     if constexpr (GEN) {
-      if (gthr) {
-        gen_rows16(grec, 16 * gi, 16 * gi < nm ? nm : 0, gmu[set], gx0[set], gx1[set], [&](int s2, double x) {
-          const int row = 16 * ggrp + s2;
-          Ps[row * KB + (glat ^ gen_swz<KB>(row))] = (T)x;
-        });
-      }
+      gen_rows16<false>(gcA, gcB, 16 * gi, nm, gmu[set], gx0[set], gx1[set], [&](int s2, double x) {
+        const int row = 16 * ggrp + s2;
+        Ps[row * KB + (glat ^ gen_swz<KB>(row))] = (T)x;
+      });
     }
   };
   T areg[KQ];
@@ -423,21 +422,23 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
   T* Ps = Bs + 2 * S::STAGE;  // GEN: [2 KR rows][GP]
   // GEN: waves 0..3 generate; wave w takes group gsub = w >> 1 of each block
   // (rows 16 gsub .. + 15 of the block, uniform across the wave) at
-  // latitude glat = 64 (w & 1) + lane of the tile
+  // latitude glat = 64 (w & 1) + lane of the tile; the group's recurrence
+  // coefficients are fetched into lanes with its seed values
   const int gsub = w >> 1, glat = 64 * (w & 1) + lane;
   const int gj = jt * 128 + glat;
-  const bool gthr = GEN && tid < 256;
+  const bool gthr = GEN && w < 4;  // uniform across the wave
   const bool gjin = gthr && gj < L.Kp;
   const double* gseeds = GEN ? g.seeds + g.seed_off[L.m_base + m] : nullptr;
   const double* grec = GEN ? g.rec + g.rec_off[L.m_base + m] : nullptr;
   const double gmu = (GEN && gjin) ? L.murow[gj] : 0.0;
-  double gx0[2] = {0.0, 0.0}, gx1[2] = {0.0, 0.0};
+  double gx0[2] = {0.0, 0.0}, gx1[2] = {0.0, 0.0}, gcA[2] = {0.0, 0.0}, gcB[2] = {0.0, 0.0};
   auto gen_fetch = [&](int kb, int set) __attribute__((always_inline)) {
     if constexpr (GEN) {
       const int gi = 2 * kb + gsub;
+      if (gthr) gen_coef(grec, 16 * gi, nm, lane, gcA[set], gcB[set]);
       if (gjin && 16 * gi < nm) {
         gx0[set] = gseeds[2LL * gi * L.Kp + gj];
-        gx1[set] = 16 * gi + 1 < nm ? gseeds[(2LL * gi + 1) * L.Kp + gj] : 0.0;
+        gx1[set] = gseeds[(2LL * gi + 1) * L.Kp + gj];  // zero row when 16 gi + 1 = n_m
       }
     }
   };
@@ -445,8 +446,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
     if constexpr (GEN) {
       if (gthr) {
         const int gi = 2 * kb + gsub;
-        gen_rows16(grec, 16 * gi, gjin ? nm : 0, gmu, gx0[set], gx1[set],
-                   [&](int s2, double x) { Ps[(16 * gsub + s2) * S::GP + glat] = (T)x; });
+        gen_rows16<false>(gcA[set], gcB[set], 16 * gi, gjin ? nm : 0, gmu, gx0[set], gx1[set],
+                          [&](int s2, double x) { Ps[(16 * gsub + s2) * S::GP + glat] = (T)x; });
       }
     }
   };

@@ -195,11 +195,15 @@ __global__ __launch_bounds__(X6Analysis<NCB>::NT) __attribute__((amdgpu_waves_pe
                           : static_cast<const float*>(g.table) + g.tab_off[L.m_base + m] +
                                 (long long)rbt * Kp * 128 + (4 * q + p) * 16 * KB + lane * 4;
   float* Ps = reinterpret_cast<float*>(Bs + 2 * S::STAGE);  // GEN: [256 rows][32 latitudes], swizzled
+  // lanes 0..31 of wave w generate group 2 w, lanes 32..63 group 2 w + 1
+  // (rows 16 ggrp .. + 15 of the tile) at latitude glat; the coefficients of
+  // both groups are held in their half of the wave for the whole tile
   const int ggrp = tid >> 5, glat = tid & 31;
   const int gi = t.rb * 16 + ggrp;
   const bool gon = GEN && 16 * gi < nm;
   const double* gseed = GEN ? g.seeds + g.seed_off[L.m_base + m] + (gon ? 2LL * gi * Kp : 0LL) : nullptr;
-  const double* grec = GEN ? g.rec + g.rec_off[L.m_base + m] : nullptr;
+  double gcA = 0.0, gcB = 0.0;
+  if constexpr (GEN) gen_coef(g.rec + g.rec_off[L.m_base + m], 16 * gi, nm, lane, gcA, gcB);
   double gmu[2] = {0.0, 0.0}, gx0[2] = {0.0, 0.0}, gx1[2] = {0.0, 0.0};
   auto gen_fetch = [&](int kb, int set) __attribute__((always_inline)) {
     if constexpr (GEN) {
@@ -207,19 +211,18 @@ __global__ __launch_bounds__(X6Analysis<NCB>::NT) __attribute__((amdgpu_waves_pe
         const int j = kb * KB + glat;
         gmu[set] = L.murow[j];
         gx0[set] = gseed[j];
-        gx1[set] = 16 * gi + 1 < nm ? gseed[Kp + j] : 0.0;
+        gx1[set] = gseed[Kp + j];  // zero row when 16 gi + 1 = n_m
       }
     }
   };
   auto gen_store = [&](int set) __attribute__((always_inline)) {
     if constexpr (GEN) {
-      gen_rows16(grec, 16 * gi, gon ? nm : 0, gmu[set], gx0[set], gx1[set], [&](int s2, double x) {
+      gen_rows16<true>(gcA, gcB, 16 * gi, nm, gmu[set], gx0[set], gx1[set], [&](int s2, double x) {
         const int row = 16 * ggrp + s2;
         Ps[row * 32 + (glat ^ x6_swz(row))] = (float)x;
       });
     }
   };
-
   // right-hand tasks: source offset (latitude 0 of the block) and LDS offset
   const float* bsrc[TR];
   int boff[TR];
@@ -459,28 +462,30 @@ __global__ __launch_bounds__(X6Synthesis<NCB>::NT) __attribute__((amdgpu_waves_p
                                 (long long)jt * nkb32 * S::CHUNK + w * (S::CHUNK / 8) + lane * 4;
   float* Ps = reinterpret_cast<float*>(Bs + 2 * S::STAGE);  // GEN: [64 rows][GP]
   // wave w generates group w >> 1 of each block (uniform across the wave)
-  // at latitude 64 (w & 1) + lane of the tile
+  // at latitude 64 (w & 1) + lane of the tile; the group's recurrence
+  // coefficients are fetched into lanes with its seed values
   const int gsub = w >> 1, glat = 64 * (w & 1) + lane;
   const int gj = jt * 128 + glat;
   const bool gjin = GEN && gj < L.Kp;
   const double* gseeds = GEN ? g.seeds + g.seed_off[L.m_base + m] : nullptr;
   const double* grec = GEN ? g.rec + g.rec_off[L.m_base + m] : nullptr;
   const double gmu = gjin ? L.murow[gj] : 0.0;
-  double gx0[2] = {0.0, 0.0}, gx1[2] = {0.0, 0.0};
+  double gx0[2] = {0.0, 0.0}, gx1[2] = {0.0, 0.0}, gcA[2] = {0.0, 0.0}, gcB[2] = {0.0, 0.0};
   auto gen_fetch = [&](int kb, int set) __attribute__((always_inline)) {
     if constexpr (GEN) {
       const int gi = 4 * kb + gsub;
+      gen_coef(grec, 16 * gi, nm, lane, gcA[set], gcB[set]);
       if (gjin && 16 * gi < nm) {
         gx0[set] = gseeds[2LL * gi * L.Kp + gj];
-        gx1[set] = 16 * gi + 1 < nm ? gseeds[(2LL * gi + 1) * L.Kp + gj] : 0.0;
+        gx1[set] = gseeds[(2LL * gi + 1) * L.Kp + gj];  // zero row when 16 gi + 1 = n_m
       }
     }
   };
   auto gen_store = [&](int kb, int set) __attribute__((always_inline)) {
     if constexpr (GEN) {
       const int gi = 4 * kb + gsub;
-      gen_rows16(grec, 16 * gi, gjin ? nm : 0, gmu, gx0[set], gx1[set],
-                 [&](int s2, double x) { Ps[(16 * gsub + s2) * S::GP + glat] = (float)x; });
+      gen_rows16<false>(gcA[set], gcB[set], 16 * gi, gjin ? nm : 0, gmu, gx0[set], gx1[set],
+                        [&](int s2, double x) { Ps[(16 * gsub + s2) * S::GP + glat] = (float)x; });
     }
   };
 

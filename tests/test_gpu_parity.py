@@ -233,6 +233,30 @@ def test_wide_items_first_launch_in_fresh_process(form):
     assert err < 10 * TOL[form], err
 
 
+@pytest.mark.parametrize("form", ["fp32", "bf16x6"])
+def test_wide_items_with_80_column_tiles(form):
+    """360 fields at I = 480: the zonal stage uses 16-field items (32
+    workspace columns each) and the Legendre kernels 80-column tiles, so the
+    workspace row must hold a whole number of both (800 columns, not 720):
+    with 720 the last item of a row wrote 16 columns into the next row.  The
+    fields of the last item and of the first items are compared with the
+    oracle in both directions."""
+    N, J, I, F = 200, 401, 480, 360
+    sel = [0, 7, 8, 15, 351, 352, 359]
+    p = _plan(N, J, I, F, "cc_poles", form)
+    g = _to_dev(inputs.random_grid(F, J, I, seed=31), form)
+    s = _host(p.forward(g))[sel]
+    ref = O.forward(_host(g[sel]), N, "cc_poles")
+    errs = [rel(s[k], ref[k]) for k in range(len(sel))]
+    assert max(errs) < TOL[form], errs
+    a = _to_dev(inputs.random_spectra(N, F, seed=32, profile="k3"), form)
+    x = _host(p.inverse(a))[sel]
+    ref = O.inverse(_host(a[sel]), N, J, I, "cc_poles")
+    errs = [rel(x[k], ref[k]) for k in range(len(sel))]
+    assert max(errs) < TOL[form], errs
+    p.close()
+
+
 def _kept_flops_from_oracle(N, J, F, kind, kb):
     """Legendre flops left after dropping, per m, the whole kb-latitude
     blocks at the pole where every |P~_n^m| < 1e-16 (scan of the oracle's P~)."""
