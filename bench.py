@@ -51,6 +51,10 @@ def parse():
                     help="reduced transform (Sec. 4.1): leave out the polar latitudes where every "
                          "|P~_n^m| < 1e-16; reported in config, never the default")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--graph", action="store_true",
+                    help="time replays of one captured hipGraph per direction instead of eager launches "
+                         "(measured slightly slower on this path: 3.55 vs 3.53 ms at T959, 0.102 vs 0.083 ms at "
+                         "T159)")
     ap.add_argument("--aliasing", action="store_true",
                     help="time the Sec. 4.2 aliasing experiment at N_trunc=479 instead (own JSON line)")
     ap.add_argument("--two-grid", action="store_true",
@@ -391,12 +395,20 @@ def main():
 
     # ---- workload: grids synthesised from k^-3 band-limited spectra ----
     spec0 = inputs.random_spectra(N, F, seed=0, profile="k3")
-    plan = Plan(N, J, I, F, grid=args.grid, form=args.form, reduced=args.reduced, otf=args.otf)
+    # with --graph the timed plan replays one captured hipGraph per
+    # direction, and per-kernel times come from a second, eager plan of the
+    # same batch (graph replays record no per-launch events)
+    plan = Plan(N, J, I, F, grid=args.grid, form=args.form, reduced=args.reduced, otf=args.otf,
+                use_graph=args.graph)
     a = torch.from_numpy(spec0).to("cuda:0", dt)
     g = plan.inverse(a)
     torch.cuda.synchronize()
 
     secs, per_step, s_out, g_out = time_pairs(plan, g, args.steps, args.warmup, torch)
+    if args.graph:
+        pe = Plan(N, J, I, F, grid=args.grid, form=args.form, reduced=args.reduced, otf=args.otf)
+        _, per_step, _, _ = time_pairs(pe, g, args.steps, 1, torch)
+        pe.close()
     value = F * args.steps / secs
     ms_step = secs / args.steps * 1e3
     flops_dir = plan.legendre_flops
@@ -449,10 +461,15 @@ def main():
     fp64 = None
     if not args.no_fp64 and args.form != "fp64":
         del s_out, g_out
-        p64 = Plan(N, J, I, F, grid=args.grid, form="fp64", reduced=args.reduced, otf=args.otf)
+        p64 = Plan(N, J, I, F, grid=args.grid, form="fp64", reduced=args.reduced, otf=args.otf,
+                   use_graph=args.graph)
         g64 = g.double()
         st = max(2, args.steps // 4)
         secs64, per64, _, _ = time_pairs(p64, g64, st, 1, torch)
+        if args.graph:
+            pe64 = Plan(N, J, I, F, grid=args.grid, form="fp64", reduced=args.reduced, otf=args.otf)
+            _, per64, _, _ = time_pairs(pe64, g64, st, 1, torch)
+            pe64.close()
         v64 = F * st / secs64
         s64 = stage_summary(per64)
         la64, ls64 = s64["legendre_analysis"][0], s64["legendre_synthesis"][0]
@@ -480,15 +497,17 @@ def main():
                                   ", reduced transform" if args.reduced else "",
                                   ", P~ generated in the kernels (no table)" if args.otf else ""),
                    "N": N, "J": J, "I": I, "fields": F, "grid": args.grid, "form": args.form,
-                   "reduced": bool(args.reduced), "otf": bool(args.otf)},
+                   "reduced": bool(args.reduced), "otf": bool(args.otf), "graph_replay": bool(args.graph)},
         "table_bytes": plan.table_bytes,
         "legendre_tflops": leg_tflops,
         "legendre_mfma_frac": leg_tflops / peak,
         "end_to_end_mfma_frac": 2 * flops_dir / (ms_step * 1e-3) / 1e12 / peak,
         "stage_ms": stage_avg,
         "stage_ms_median": stage_med,
-        "timing": "value and ms_per_step: wall clock of the steps with no per-launch events; stage_ms and "
-                  "roofline: a second pass of the same steps with HIP events around every launch",
+        "timing": ("value and ms_per_step: wall clock of the steps (%s) with no per-launch events; stage_ms and "
+                   "roofline: a second pass of the same steps%s with HIP events around every launch"
+                   % ("replays of one captured hipGraph per direction" if args.graph else "eager launches",
+                      " on an eager plan of the same batch" if args.graph else "")),
         "rel_err_vs_oracle": err,
         "fp64_form": fp64,
         "roofline": {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",

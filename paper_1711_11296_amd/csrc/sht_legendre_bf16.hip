@@ -295,17 +295,28 @@ __global__ __launch_bounds__(X6Analysis<NCB>::NT) __attribute__((amdgpu_waves_pe
   };
   auto compute = [&](int stage) __attribute__((always_inline)) {
     const __bf16* Bp = Bs + stage * S::STAGE + (p * BN + li) * P + 8 * lg;
+    // column blocks in pairs: the six piece products of each term go to one
+    // accumulator smallest first, and the four accumulators of a pair (two
+    // row blocks by two column blocks) take turns, so that four independent
+    // chains keep the bfloat16 matrix pipe busy
 #pragma unroll
-    for (int c = 0; c < NCB; ++c) {
-      bf16x8 bb[3];
+    for (int c = 0; c < NCB; c += 2) {
+      constexpr int CC = 2;
+      bf16x8 bb[CC][3];
 #pragma unroll
-      for (int k = 0; k < 3; ++k) bb[k] = *reinterpret_cast<const bf16x8*>(Bp + k * S::PLANE + c * 16 * P);
-      // six piece products, smallest first, the two row blocks alternating
+      for (int cc = 0; cc < CC; ++cc)
+        if (c + cc < NCB)
+#pragma unroll
+          for (int k = 0; k < 3; ++k)
+            bb[cc][k] = *reinterpret_cast<const bf16x8*>(Bp + k * S::PLANE + (c + cc) * 16 * P);
 #pragma unroll
       for (int pr = 0; pr < 6; ++pr) {
         constexpr int ia[6] = {2, 1, 0, 1, 0, 0}, ib[6] = {0, 1, 2, 0, 1, 0};
 #pragma unroll
-        for (int h = 0; h < 2; ++h) acc[h][c] = mfma_bf16(acur[h][ia[pr]], bb[ib[pr]], acc[h][c]);
+        for (int cc = 0; cc < CC; ++cc)
+          if (c + cc < NCB)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) acc[h][c + cc] = mfma_bf16(acur[h][ia[pr]], bb[cc][ib[pr]], acc[h][c + cc]);
       }
     }
   };
@@ -587,16 +598,27 @@ __global__ __launch_bounds__(X6Synthesis<NCB>::NT) __attribute__((amdgpu_waves_p
   };
   auto compute = [&](int stage) __attribute__((always_inline)) {
     const __bf16* Bp = Bs + stage * S::STAGE + (p * BN + li) * P + 8 * lg;
+    // column blocks in pairs, four independent accumulator chains (as in
+    // the analysis)
 #pragma unroll
-    for (int c = 0; c < NCB; ++c) {
-      bf16x8 bb[3];
+    for (int c = 0; c < NCB; c += 2) {
+      constexpr int CC = 2;
+      bf16x8 bb[CC][3];
 #pragma unroll
-      for (int k = 0; k < 3; ++k) bb[k] = *reinterpret_cast<const bf16x8*>(Bp + k * S::PLANE + c * 16 * P);
+      for (int cc = 0; cc < CC; ++cc)
+        if (c + cc < NCB)
+#pragma unroll
+          for (int k = 0; k < 3; ++k)
+            bb[cc][k] = *reinterpret_cast<const bf16x8*>(Bp + k * S::PLANE + (c + cc) * 16 * P);
 #pragma unroll
       for (int pr = 0; pr < 6; ++pr) {
         constexpr int ia[6] = {2, 1, 0, 1, 0, 0}, ib[6] = {0, 1, 2, 0, 1, 0};
 #pragma unroll
-        for (int jb = 0; jb < 2; ++jb) acc[jb][c] = mfma_bf16(acur[jb][ia[pr]], bb[ib[pr]], acc[jb][c]);
+        for (int cc = 0; cc < CC; ++cc)
+          if (c + cc < NCB)
+#pragma unroll
+            for (int jb = 0; jb < 2; ++jb)
+              acc[jb][c + cc] = mfma_bf16(acur[jb][ia[pr]], bb[cc][ib[pr]], acc[jb][c + cc]);
       }
     }
   };
