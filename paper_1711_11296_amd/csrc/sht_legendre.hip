@@ -482,6 +482,20 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
   const __amdgpu_buffer_rsrc_t srs = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<T*>(spec + sfirst), (short)0, (int)(unsigned)(sbytes > 0xFFFFFFFFLL ? 0xFFFFFFFFLL : sbytes),
       0x00020000);
+  // Quad task qq: field fl, quad rp (natural rows 4 rp .. 4 rp + 3 of the
+  // block).  In the FP32 form the lanes of a half-wave take 4 quads of 8
+  // fields, so that the 8-byte stores of one instruction (column 2 fl + ri,
+  // pitch 20 words) cover all 64 LDS banks once; otherwise quads vary
+  // fastest.
+  auto quad_of = [&](int qq, int& fl, int& rp) __attribute__((always_inline)) {
+    if constexpr (sizeof(T) == 4 && KR / 2 == 8) {
+      rp = (qq & 3) | (((qq >> 5) & 1) << 2);
+      fl = ((qq >> 2) & 7) | ((qq >> 6) << 3);
+    } else {
+      fl = qq / (KR / 2);
+      rp = qq % (KR / 2);
+    }
+  };
   // (issued unconditionally, also by waves without latitudes in this tile
   // and for blocks past the end, clamped: with straight-line loads the
   // compiler's wait counts cover exactly the block that is consumed)
@@ -494,7 +508,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
 #pragma unroll
     for (int i = 0; i < S::NQ; ++i) {
       const int qq = tid + i * 512;
-      const int fl = qq / (KR / 2), rp = qq % (KR / 2);
+      int fl, rp;
+      quad_of(qq, fl, rp);
       const int r = kb * 2 * KR + 4 * rp;  // first natural row of the quad
       const unsigned off = ((unsigned)fl * (unsigned)nc + (unsigned)r) * 2u * (unsigned)sizeof(T);
       // vector u holds natural rows r + u E/2 .. r + (u+1) E/2 - 1; rows
@@ -510,7 +525,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
     for (int i = 0; i < S::NQ; ++i) {
       const int qq = tid + i * 512;
       if (S::NQ * 512 == S::QUADS || qq < S::QUADS) {
-        const int fl = qq / (KR / 2), rp = qq % (KR / 2);
+        int fl, rp;
+        quad_of(qq, fl, rp);
         const int r = kb * 2 * KR + 4 * rp;
         T x[8];
 #pragma unroll
