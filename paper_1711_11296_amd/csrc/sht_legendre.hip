@@ -49,10 +49,13 @@ namespace sht {
 // cores work on block kb and stored into the other stage afterwards, so one
 // barrier per block suffices.
 // ---------------------------------------------------------------------------
-template <typename T, int NCB>
+template <typename T, int NCB, bool GEN = false>
 struct AnalysisShape {
   static constexpr int E = 16 / (int)sizeof(T);        // scalars per 16 bytes
-  static constexpr int KB = sizeof(T) == 4 ? 32 : 16;  // contraction block
+  // contraction block; generated P~ in FP64 also takes 32 latitudes (there
+  // is no table layout to match, and a block's recurrence and two barriers
+  // then serve twice the products)
+  static constexpr int KB = (sizeof(T) == 4 || GEN) ? 32 : 16;
   static constexpr int KQ = KB / 4;                    // k values per lane and block
   static constexpr int BN = 16 * NCB;
   // With an even number of column blocks the right-hand operand goes from
@@ -95,10 +98,12 @@ __device__ __forceinline__ int gen_swz(int row) {
 // were read into registers before the last barrier), read after the next
 // barrier, and a second barrier guards it against the next block's writes.
 template <typename T, int NCB, bool GEN>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_legendre_analysis(const GemmArgs g) {
+// (The FP64 generated kernel with 8 column blocks fills the LDS, one
+// workgroup per compute unit: it takes the registers of two waves per SIMD.)
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 && GEN && NCB > 4 ? 2 : 4))) void k_legendre_analysis(const GemmArgs g) {
   typedef typename Acc<T>::type AccT;
   typedef typename V16<T>::type V;
-  using S = AnalysisShape<T, NCB>;
+  using S = AnalysisShape<T, NCB, GEN>;
   constexpr int E = S::E, KB = S::KB, KQ = S::KQ, BN = S::BN, BS = S::BS;
 
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -229,7 +234,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
   // operations of a wave complete in issue order).
   auto wait_fills = [&]() {
     if constexpr (S::DMA) {
-      static_assert(KQ / E == 2, "two table loads per block");
+      static_assert(GEN || KQ / E == 2, "two table loads per block");
       if constexpr (GEN)
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // nothing else is worth keeping in flight
       else
@@ -646,12 +651,12 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
 template <typename T>
 static size_t lds_analysis(int ncb, bool gen) {
   switch (ncb) {
-    case 1: return AnalysisShape<T, 1>::lds_bytes(gen);
-    case 2: return AnalysisShape<T, 2>::lds_bytes(gen);
-    case 4: return AnalysisShape<T, 4>::lds_bytes(gen);
-    case 5: return AnalysisShape<T, 5>::lds_bytes(gen);
-    case 8: return AnalysisShape<T, 8>::lds_bytes(gen);
-    default: return AnalysisShape<T, 10>::lds_bytes(gen);
+    case 1: return gen ? AnalysisShape<T, 1, true>::lds_bytes(true) : AnalysisShape<T, 1>::lds_bytes(false);
+    case 2: return gen ? AnalysisShape<T, 2, true>::lds_bytes(true) : AnalysisShape<T, 2>::lds_bytes(false);
+    case 4: return gen ? AnalysisShape<T, 4, true>::lds_bytes(true) : AnalysisShape<T, 4>::lds_bytes(false);
+    case 5: return gen ? AnalysisShape<T, 5, true>::lds_bytes(true) : AnalysisShape<T, 5>::lds_bytes(false);
+    case 8: return gen ? AnalysisShape<T, 8, true>::lds_bytes(true) : AnalysisShape<T, 8>::lds_bytes(false);
+    default: return gen ? AnalysisShape<T, 10, true>::lds_bytes(true) : AnalysisShape<T, 10>::lds_bytes(false);
   }
 }
 
