@@ -99,7 +99,21 @@ typedef struct {
                      and round it once to the form's element type; the plan
                      keeps no table (seed rows: 1/8 of the table's entries,
                      in FP64). */
+  int zonal;      /* sht_zonal_t: how a multi-level plan launches its zonal
+                     stage (Sec. 3.2: a hierarchy of truncations batched in
+                     one plan).  Single-level plans ignore it. */
 } sht_options;
+
+typedef enum {
+  SHT_ZONAL_AUTO = 0,        /* one launch where the levels allow it; with
+                                autotune, whichever of the two below timed
+                                faster at plan time, per direction */
+  SHT_ZONAL_ONE_LAUNCH = 1,  /* one persistent launch over every level's
+                                work items where every level has I = 400,
+                                800 or 1600 or I <= 1024 (else as below) */
+  SHT_ZONAL_PER_LENGTH = 2   /* one launch per compile-time FFT length and
+                                one for the other levels */
+} sht_zonal_t;
 
 enum {
   SHT_OK = 0,

@@ -37,7 +37,10 @@ class SHTError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("grid", ctypes.c_int), ("form", ctypes.c_int),
                 ("autotune", ctypes.c_int), ("use_graph", ctypes.c_int),
-                ("reduced", ctypes.c_int), ("otf", ctypes.c_int)]
+                ("reduced", ctypes.c_int), ("otf", ctypes.c_int), ("zonal", ctypes.c_int)]
+
+
+ZONAL = {"auto": 0, "one_launch": 1, "per_length": 2}
 
 
 _lib = None

@@ -71,6 +71,8 @@ struct sht_plan_s {
   int ncb_fwd = 1, ncb_inv = 1;   // column blocking used by each Legendre kernel
   int fb = 8;                  // fields per zonal work item
   int sched_fwd = 0, sched_inv = 0;
+  int zonal = SHT_ZONAL_AUTO;  // sht_zonal_t option
+  int one_fwd = 1, one_inv = 1;   // multi-level zonal stage in one launch, per direction
   int maxN = 0;
   int nitems = 0;
   int ntiles_fwd = 0, ntiles_inv = 0;
@@ -195,9 +197,10 @@ int build_plan(int nlev, const int* Nv, const int* Jv, const int* Iv, const int*
   *out = nullptr;
   if (nlev < 1 || nlev > SHT_MAX_LEVELS) return fail(SHT_EINVAL, "nlevels must be 1..8");
   if (!Nv || !Jv || !Iv || !Fv) return fail(SHT_EINVAL, "level arrays must not be NULL");
-  sht_options o{SHT_GRID_CC_POLES, SHT_FORM_FP64, 0, 0, 0, 0};
+  sht_options o{SHT_GRID_CC_POLES, SHT_FORM_FP64, 0, 0, 0, 0, SHT_ZONAL_AUTO};
   if (opts) o = *opts;
   if (o.form < SHT_FORM_FP64 || o.form > SHT_FORM_BF16X6) return fail(SHT_EINVAL, "unknown form");
+  if (o.zonal < SHT_ZONAL_AUTO || o.zonal > SHT_ZONAL_PER_LENGTH) return fail(SHT_EINVAL, "unknown zonal launch mode");
   if (o.otf && (o.reduced || o.autotune)) return fail(SHT_EINVAL, "otf cannot be combined with reduced or autotune");
   for (int l = 0; l < nlev; ++l) {
     int rc = check_level_args(Nv[l], Jv[l], Iv[l], Fv[l], o.grid);
@@ -212,6 +215,8 @@ int build_plan(int nlev, const int* Nv, const int* Jv, const int* Iv, const int*
   P->use_graph = o.use_graph;
   P->reduced = o.reduced != 0;
   P->otf = o.otf != 0;
+  P->zonal = o.zonal;
+  P->one_fwd = P->one_inv = o.zonal != SHT_ZONAL_PER_LENGTH;
   P->nlev = nlev;
   P->elem = o.form == SHT_FORM_FP64 ? 8 : 4;
   int rc = hip_check(hipGetDevice(&P->device), "hipGetDevice");
@@ -522,6 +527,7 @@ void prof_mark(sht_plan_s* P, void* stream, int stage, bool start) {
 int run_analysis(sht_plan_s* P, const void* grid, void* spec, void* stream, int use_w, int use_inv_I,
                  double mscale, void* ws) {
   FftArgs a = fft_args(P, grid, ws, use_w, use_inv_I, mscale);
+  a.one_launch = P->one_fwd;
   prof_mark(P, stream, ST_ZONAL_A, true);
   int e = launch_zonal(P->form, true, a, P->maxN, stream);
   prof_mark(P, stream, ST_ZONAL_A, false);
@@ -543,6 +549,7 @@ int run_synthesis(sht_plan_s* P, const void* spec, void* grid, void* stream, int
   prof_mark(P, stream, ST_LEG_S, false);
   if (e) return hip_check((hipError_t)e, "Legendre synthesis launch");
   FftArgs a = fft_args(P, P->d_ws, grid, use_w, use_inv_I, mscale);
+  a.one_launch = P->one_inv;
   prof_mark(P, stream, ST_ZONAL_S, true);
   e = launch_zonal(P->form, false, a, P->maxN, stream);
   prof_mark(P, stream, ST_ZONAL_S, false);
@@ -680,7 +687,7 @@ std::string tune_key(const sht_plan_s* P) {
     if (ch == ' ') ch = '_';
   int rt = 0;
   (void)hipRuntimeGetVersion(&rt);
-  std::string k = arch + " hip" + std::to_string(rt) + " v2 form" + std::to_string(P->form) + " fb" +
+  std::string k = arch + " hip" + std::to_string(rt) + " v3 form" + std::to_string(P->form) + " fb" +
                   std::to_string(P->fb) + " lev" + std::to_string(P->nlev);
   for (int l = 0; l < P->nlev; ++l)
     k += " " + std::to_string(P->lev[l].N) + "," + std::to_string(P->lev[l].J) + "," + std::to_string(P->lev[l].I) +
@@ -698,7 +705,7 @@ bool blocking_ok(const sht_plan_s* P, bool analysis, int c) {
   return true;
 }
 
-bool tune_lookup(const std::string& key, int v[4]) {
+bool tune_lookup(const std::string& key, int v[6]) {
   FILE* f = std::fopen(tune_path().c_str(), "r");
   if (!f) return false;
   char line[4096];
@@ -707,16 +714,16 @@ bool tune_lookup(const std::string& key, int v[4]) {
     std::string l(line);
     size_t bar = l.find('|');
     if (bar == std::string::npos || l.substr(0, bar) != key) continue;
-    found = std::sscanf(l.c_str() + bar + 1, "%d %d %d %d", &v[0], &v[1], &v[2], &v[3]) == 4;
+    found = std::sscanf(l.c_str() + bar + 1, "%d %d %d %d %d %d", &v[0], &v[1], &v[2], &v[3], &v[4], &v[5]) == 6;
   }
   std::fclose(f);
   return found;
 }
 
-void tune_store(const std::string& key, const int v[4]) {
+void tune_store(const std::string& key, const int v[6]) {
   FILE* f = std::fopen(tune_path().c_str(), "a");
   if (!f) return;  // the cache is optional
-  std::fprintf(f, "%s|%d %d %d %d\n", key.c_str(), v[0], v[1], v[2], v[3]);
+  std::fprintf(f, "%s|%d %d %d %d %d %d\n", key.c_str(), v[0], v[1], v[2], v[3], v[4], v[5]);
   std::fclose(f);
 }
 
@@ -734,17 +741,20 @@ int upload_tiles(sht_plan_s* P, bool analysis, const std::vector<Tile>& t) {
 }
 
 // Time the Legendre kernels for every column blocking that keeps the
-// workspace layout and both tile orders; keep the fastest per direction.
+// workspace layout and both tile orders, and (multi-level plans) the zonal
+// stage in one launch and per FFT length; keep the fastest per direction.
+// Cache line: ncb and order of the analysis, the same of the synthesis,
+// one-launch zonal analysis and synthesis (0/1).
 int autotune(sht_plan_s* P) {
   const std::string key = tune_key(P);
-  int v[4];
+  int v[6];
   // a cached entry is used only if it passes the same filter as the search
   // (a stale or foreign line could otherwise leave columns uncomputed)
   // (the plan's default blocking, which the search keeps when no candidate
   // passes, is also accepted)
   const bool cached = tune_lookup(key, v) && (v[0] == P->ncb_fwd || blocking_ok(P, true, v[0])) &&
                       (v[2] == P->ncb_inv || blocking_ok(P, false, v[2])) && (v[1] == 0 || v[1] == 1) &&
-                      (v[3] == 0 || v[3] == 1);
+                      (v[3] == 0 || v[3] == 1) && (v[4] == 0 || v[4] == 1) && (v[5] == 0 || v[5] == 1);
   if (!cached) {
     const int all64[] = {1, 2, 4, 8}, all32[] = {1, 2, 4, 5, 8, 10};
     const int* all = P->form == SHT_FORM_FP64 ? all64 : all32;
@@ -796,6 +806,39 @@ int autotune(sht_plan_s* P) {
       v[2 * dir] = bc;
       v[2 * dir + 1] = bs;
     }
+    // zonal stage of a multi-level plan: one launch over all levels against
+    // one per FFT length (the same when the levels do not allow one launch;
+    // ties keep one launch)
+    v[4] = v[5] = 1;
+    if (!rc && P->nlev > 1) {
+      void* grid = nullptr;
+      rc = hip_check(hipMalloc(&grid, P->grid_elems * P->elem + 16), "tune alloc");
+      if (!rc) rc = hip_check(hipMemset(grid, 0, P->grid_elems * P->elem), "tune clear");
+      for (int dir = 0; dir < 2 && !rc; ++dir) {
+        const bool analysis = dir == 0;
+        float best = 1e30f;
+        for (int one = 1; one >= 0 && !rc; --one) {
+          FftArgs a = analysis ? fft_args(P, grid, P->d_ws, 1, 1, 1.0) : fft_args(P, P->d_ws, grid, 0, 0, 1.0);
+          a.one_launch = one;
+          int e = launch_zonal(P->form, analysis, a, P->maxN, st);
+          (void)hipEventRecord(e0, st);
+          for (int r = 0; r < 3 && !e; ++r) e = launch_zonal(P->form, analysis, a, P->maxN, st);
+          (void)hipEventRecord(e1, st);
+          (void)hipEventSynchronize(e1);
+          float ms = 0.f;
+          (void)hipEventElapsedTime(&ms, e0, e1);
+          if (e) {
+            rc = hip_check((hipError_t)e, "tune zonal launch");
+            break;
+          }
+          if (ms < best) {
+            best = ms;
+            v[4 + dir] = one;
+          }
+        }
+      }
+      if (grid) (void)hipFree(grid);
+    }
     P->profile = saved_profile;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -808,6 +851,10 @@ int autotune(sht_plan_s* P) {
   P->sched_fwd = v[1];
   P->ncb_inv = v[2];
   P->sched_inv = v[3];
+  if (P->zonal == SHT_ZONAL_AUTO) {
+    P->one_fwd = v[4];
+    P->one_inv = v[5];
+  }
   int rc = upload_tiles(P, true, build_tiles(P->form, P->nlev, P->lev, P->jst.data(), true, P->ncb_fwd, P->sched_fwd));
   if (!rc)
     rc = upload_tiles(P, false,

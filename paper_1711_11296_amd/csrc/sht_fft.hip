@@ -312,7 +312,7 @@ __device__ __forceinline__ void stockham_pass(cx<T>* buf, int I, int Ns, int tws
 // Forward complex FFTs (sign -) of the FC sequences in buf, natural order in
 // and out.  Every thread of the block must call it.
 template <typename T, int NT, int FC, int MAXI>
-__device__ void fft_lds(cx<T>* buf, const LevelDesc& L, const cx<T>* tw) {
+__device__ __forceinline__ void fft_lds(cx<T>* buf, const LevelDesc& L, const cx<T>* tw) {
   for (int p = 0; p < L.nrad; ++p) {
     const int R = L.rad[p], Ns = L.pns[p], tws = L.ptw[p];
     const unsigned mg = L.pmag[p];
@@ -333,6 +333,11 @@ __device__ __forceinline__ int level_of(const FftArgs& a, int item) {
   int l = 0;
   while (l + 1 < a.nlev && item >= a.lev[l + 1].fft_item0) ++l;
   return l;
+}
+
+// One past the last work item (slot) of level l.
+__device__ __forceinline__ int level_end(const FftArgs& a, int l) {
+  return l + 1 < a.nlev ? a.lev[l + 1].fft_item0 : a.nitems;
 }
 
 // Store/load FB complex values (2*FB scalars, 64 bytes) starting at a
@@ -460,12 +465,14 @@ struct Item {
   bool eq;
 };
 
-// Workgroup b runs on XCD b mod 8 and walks the items b, b + G, ...
-// (G = gridDim.x, a multiple of 8 on a full device).  Item index i is
-// mapped to list position x R' + k (x = i mod 8, k = i / 8, R' the length
-// of the x-th eighth of the list): every XCD works through one contiguous
-// eighth, so the field blocks of one latitude pair run on one XCD at about
-// the same time and fill whole workspace lines in its L2.  The map is a
+// Workgroup b runs on XCD b mod 8 and walks the slots b, b + G, ...
+// (G = gridDim.x, a multiple of 8 on a full device).  The slots of a level
+// are a contiguous range; within it, local slot i is mapped to the level's
+// list position x R' + k (x = i mod 8, k = i / 8, R' the length of the
+// x-th eighth of the level's list): the workgroups of one XCD work through
+// one contiguous eighth of every level, so the field blocks of one latitude
+// pair run on one XCD at about the same time and fill whole workspace lines
+// in its L2, and every XCD gets the same share of each level.  The map is a
 // permutation of [0, n).
 __device__ __forceinline__ int xcd_map(int i, int n) {
   const int x = i & 7, k = i >> 3;
@@ -475,10 +482,9 @@ __device__ __forceinline__ int xcd_map(int i, int n) {
 
 __device__ __forceinline__ Item decode_item(const FftArgs& a, int slot) {
   Item it;
-  const int item = xcd_map(slot, a.nitems);
-  it.l = level_of(a, item);
+  it.l = level_of(a, slot);
   const LevelDesc& L = a.lev[it.l];
-  const int local = item - L.fft_item0;
+  const int local = xcd_map(slot - L.fft_item0, level_end(a, it.l) - L.fft_item0);
   it.jp = local / L.nfb;
   it.fb = local - it.jp * L.nfb;
   it.eq = (L.J & 1) && (it.jp == (L.J >> 1));
@@ -503,9 +509,10 @@ __device__ __forceinline__ T row_scale(const FftArgs& a, const LevelDesc& L, int
 // the stores of the previous item overlap.  Twiddles are staged in LDS when
 // TWL is set (reloaded when the level changes).
 // ---------------------------------------------------------------------------
+// The slots item, item + G, ... below `end` (any levels); returns the first
+// slot past them.  Every thread of the workgroup calls it alike.
 template <typename T, int NT, int FB, int FC, int MS, int MAXI, bool TWL>
-__global__ __launch_bounds__(NT) void k_zonal_analysis(const FftArgs a) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
+__device__ __forceinline__ int zonal_analysis_run(const FftArgs& a, int item, int end, unsigned char* smem_raw) {
   constexpr int NRD = FB / FC;
   constexpr int LPT = (MAXI + NT - 1) / NT;
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
@@ -514,7 +521,7 @@ __global__ __launch_bounds__(NT) void k_zonal_analysis(const FftArgs a) {
   const T msc = (T)a.mscale;
 
   T pn[FC][LPT], ps[FC][LPT];
-  auto load_rows = [&](int item, int rd) {
+  auto load_rows = [&](int item, int rd) __attribute__((always_inline)) {
     const Item it = decode_item(a, item);
     const LevelDesc& L = a.lev[it.l];
     const T* grid = grid0 + L.grid_off;
@@ -533,12 +540,11 @@ __global__ __launch_bounds__(NT) void k_zonal_analysis(const FftArgs a) {
     }
   };
 
-  int item = blockIdx.x;
-  if (item >= a.nitems) return;
+  if (item >= end) return item;
   int lcur = -1;
   const cx<T>* tw = nullptr;
   load_rows(item, 0);
-  for (; item < a.nitems; item += gridDim.x) {
+  for (; item < end; item += gridDim.x) {
     const Item it = decode_item(a, item);
     const LevelDesc& L = a.lev[it.l];
     const int I = L.I, N = L.N;
@@ -570,7 +576,7 @@ __global__ __launch_bounds__(NT) void k_zonal_analysis(const FftArgs a) {
       __syncthreads();
       if (rd + 1 < NRD)
         load_rows(item, rd + 1);
-      else if (next < a.nitems)
+      else if (next < end)
         load_rows(next, 0);
       fft_lds<T, NT, FC, MAXI>(buf, L, tw);
 #pragma unroll
@@ -615,6 +621,13 @@ __global__ __launch_bounds__(NT) void k_zonal_analysis(const FftArgs a) {
       }
     }
   }
+  return item;
+}
+
+template <typename T, int NT, int FB, int FC, int MS, int MAXI, bool TWL>
+__global__ __launch_bounds__(NT) void k_zonal_analysis(const FftArgs a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  zonal_analysis_run<T, NT, FB, FC, MS, MAXI, TWL>(a, blockIdx.x, a.nitems, smem_raw);
 }
 
 // ---------------------------------------------------------------------------
@@ -624,8 +637,7 @@ __global__ __launch_bounds__(NT) void k_zonal_analysis(const FftArgs a) {
 // buffers, so they overlap that round's FFT and row stores.
 // ---------------------------------------------------------------------------
 template <typename T, int NT, int FB, int FC, int MS, int MAXI, bool TWL>
-__global__ __launch_bounds__(NT) void k_zonal_synthesis(const FftArgs a) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
+__device__ __forceinline__ int zonal_synthesis_run(const FftArgs& a, int item, int end, unsigned char* smem_raw) {
   constexpr int NRD = FB / FC;
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
   const T* ws0 = static_cast<const T*>(a.src);
@@ -633,7 +645,7 @@ __global__ __launch_bounds__(NT) void k_zonal_synthesis(const FftArgs a) {
   const T msc = (T)a.mscale;
 
   cx<T> stS[MS][FB], stA[MS][FB];
-  auto load_ws = [&](int item) {
+  auto load_ws = [&](int item) __attribute__((always_inline)) {
     const Item it = decode_item(a, item);
     const LevelDesc& L = a.lev[it.l];
     const T* ws = ws0 + L.ws_off;
@@ -655,12 +667,11 @@ __global__ __launch_bounds__(NT) void k_zonal_synthesis(const FftArgs a) {
     }
   };
 
-  int item = blockIdx.x;
-  if (item >= a.nitems) return;
+  if (item >= end) return item;
   int lcur = -1;
   const cx<T>* tw = nullptr;
   load_ws(item);
-  for (; item < a.nitems; item += gridDim.x) {
+  for (; item < end; item += gridDim.x) {
     const Item it = decode_item(a, item);
     const LevelDesc& L = a.lev[it.l];
     const int I = L.I, J = L.J, N = L.N;
@@ -708,7 +719,7 @@ __global__ __launch_bounds__(NT) void k_zonal_synthesis(const FftArgs a) {
         }
       }
       __syncthreads();
-      if (rd + 1 == NRD && next < a.nitems) load_ws(next);
+      if (rd + 1 == NRD && next < end) load_ws(next);
       fft_lds<T, NT, FC, MAXI>(buf, L, tw);
 #pragma unroll
       for (int fc = 0; fc < FC; ++fc) {
@@ -727,6 +738,13 @@ __global__ __launch_bounds__(NT) void k_zonal_synthesis(const FftArgs a) {
       __syncthreads();
     }
   }
+  return item;
+}
+
+template <typename T, int NT, int FB, int FC, int MS, int MAXI, bool TWL>
+__global__ __launch_bounds__(NT) void k_zonal_synthesis(const FftArgs a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  zonal_synthesis_run<T, NT, FB, FC, MS, MAXI, TWL>(a, blockIdx.x, a.nitems, smem_raw);
 }
 
 // ---------------------------------------------------------------------------
@@ -872,26 +890,28 @@ struct Fft3 {
   }
 };
 
+// The slots item, item + G, ... of level l (item is one of them); returns
+// the first slot past the level.  Every thread of the workgroup calls it
+// alike.
 template <typename T, class P, int NT, int FB, int FC, int MS>
-__global__ __launch_bounds__(NT) void k_zonal_analysis_p3(const FftArgs a) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
+__device__ __forceinline__ int zonal_analysis_run_p3(const FftArgs& a, int l, int item, unsigned char* smem_raw) {
   using F3 = Fft3<T, P, NT, FC>;
   constexpr int NRD = FB / FC, I = P::I;
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
   cx<T>* twl = buf + FC * P::IP;
-  const LevelDesc& L = a.lev[0];
+  const LevelDesc& L = a.lev[l];
+  const int s0 = L.fft_item0, end = level_end(a, l), n = end - s0;
   const T* grid = static_cast<const T*>(a.src) + L.grid_off;
   T* ws = static_cast<T*>(a.dst) + L.ws_off;
   const T msc = (T)a.mscale;
   const int N = L.N, J = L.J;
 
-  int item = blockIdx.x;
-  if (item >= a.nitems) return;
+  if (item >= end) return item;
   F3::stage_twiddles(twl, static_cast<const cx<T>*>(L.tw));
 
   cx<T> v1[F3::S1][16];
-  auto load_rows = [&](int slot, int rd) {
-    const int itm = xcd_map(slot, a.nitems);
+  auto load_rows = [&](int slot, int rd) __attribute__((always_inline)) {
+    const int itm = xcd_map(slot - s0, n);
     const int jp = itm / L.nfb, fb = itm - jp * L.nfb;
     const bool eq = (J & 1) && (jp == (J >> 1));
 #pragma unroll
@@ -913,8 +933,8 @@ __global__ __launch_bounds__(NT) void k_zonal_analysis_p3(const FftArgs a) {
   };
 
   load_rows(item, 0);
-  for (; item < a.nitems; item += gridDim.x) {
-    const int itm = xcd_map(item, a.nitems);
+  for (; item < end; item += gridDim.x) {
+    const int itm = xcd_map(item - s0, n);
     const int jp = itm / L.nfb, fb = itm - jp * L.nfb;
     const bool eq = (J & 1) && (jp == (J >> 1));
     const T rscale = row_scale<T>(a, L, jp);
@@ -927,7 +947,7 @@ __global__ __launch_bounds__(NT) void k_zonal_analysis_p3(const FftArgs a) {
       __syncthreads();
       if (rd + 1 < NRD)
         load_rows(item, rd + 1);
-      else if (next < a.nitems)
+      else if (next < end)
         load_rows(next, 0);
       F3::pass2(buf, twl);
       {
@@ -989,16 +1009,23 @@ __global__ __launch_bounds__(NT) void k_zonal_analysis_p3(const FftArgs a) {
       store_runs_quad<T, FB>(wrow + plane, plane, m, N, stA[s]);
     }
   }
+  return item;
 }
 
 template <typename T, class P, int NT, int FB, int FC, int MS>
-__global__ __launch_bounds__(NT) void k_zonal_synthesis_p3(const FftArgs a) {
+__global__ __launch_bounds__(NT) void k_zonal_analysis_p3(const FftArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  zonal_analysis_run_p3<T, P, NT, FB, FC, MS>(a, 0, blockIdx.x, smem_raw);
+}
+
+template <typename T, class P, int NT, int FB, int FC, int MS>
+__device__ __forceinline__ int zonal_synthesis_run_p3(const FftArgs& a, int l, int item, unsigned char* smem_raw) {
   using F3 = Fft3<T, P, NT, FC>;
   constexpr int NRD = FB / FC, I = P::I;
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
   cx<T>* twl = buf + FC * P::IP;
-  const LevelDesc& L = a.lev[0];
+  const LevelDesc& L = a.lev[l];
+  const int s0 = L.fft_item0, end = level_end(a, l), n = end - s0;
   const T* ws = static_cast<const T*>(a.src) + L.ws_off;
   T* grid = static_cast<T*>(a.dst) + L.grid_off;
   const T msc = (T)a.mscale;
@@ -1007,8 +1034,8 @@ __global__ __launch_bounds__(NT) void k_zonal_synthesis_p3(const FftArgs a) {
   const long long plane = (long long)L.Kp * Cp;
 
   cx<T> stS[MS][FB], stA[MS][FB];
-  auto load_ws = [&](int slot) {
-    const int itm = xcd_map(slot, a.nitems);
+  auto load_ws = [&](int slot) __attribute__((always_inline)) {
+    const int itm = xcd_map(slot - s0, n);
     const int jp = itm / L.nfb, fb = itm - jp * L.nfb;
 #pragma unroll
     for (int s = 0; s < MS; ++s) {
@@ -1026,12 +1053,11 @@ __global__ __launch_bounds__(NT) void k_zonal_synthesis_p3(const FftArgs a) {
     }
   };
 
-  int item = blockIdx.x;
-  if (item >= a.nitems) return;
+  if (item >= end) return item;
   F3::stage_twiddles(twl, static_cast<const cx<T>*>(L.tw));
   load_ws(item);
-  for (; item < a.nitems; item += gridDim.x) {
-    const int itm = xcd_map(item, a.nitems);
+  for (; item < end; item += gridDim.x) {
+    const int itm = xcd_map(item - s0, n);
     const int jp = itm / L.nfb, fb = itm - jp * L.nfb;
     const bool eq = (J & 1) && (jp == (J >> 1));
     const T rscale = row_scale<T>(a, L, jp);
@@ -1064,7 +1090,7 @@ __global__ __launch_bounds__(NT) void k_zonal_synthesis_p3(const FftArgs a) {
         }
       }
       __syncthreads();
-      if (rd + 1 == NRD && next < a.nitems) load_ws(next);
+      if (rd + 1 == NRD && next < end) load_ws(next);
       F3::pass1_lds(buf);
       F3::pass2(buf, twl);
       cx<T> v3[F3::S3][P::R3];
@@ -1089,6 +1115,72 @@ __global__ __launch_bounds__(NT) void k_zonal_synthesis_p3(const FftArgs a) {
       }
       __syncthreads();  // the next round refills the buffer
     }
+  }
+  return item;
+}
+
+template <typename T, class P, int NT, int FB, int FC, int MS>
+__global__ __launch_bounds__(NT) void k_zonal_synthesis_p3(const FftArgs a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  zonal_synthesis_run_p3<T, P, NT, FB, FC, MS>(a, 0, blockIdx.x, smem_raw);
+}
+
+
+// ---------------------------------------------------------------------------
+// Multi-level plans in one launch.  A configuration says how a level runs:
+// with a compile-time three-pass plan (ZP3) or with runtime radices (ZRt).
+// The persistent workgroups of k_zonal_levels walk their slots in increasing
+// order, which visits the levels one after the other, each as a contiguous
+// run of slots (every level's items are spread over all XCDs, see xcd_map);
+// a run is handed to the level's configuration (LevelDesc::zk), and the LDS
+// is reused by the next run after a barrier.  One launch therefore covers
+// every level, with no idle tail between levels.
+// ---------------------------------------------------------------------------
+template <class P, int FC, int MS>
+struct ZP3 {
+  template <typename T>
+  static constexpr size_t lds() {
+    return (size_t)(FC * P::IP + P::ntw) * sizeof(cx<T>);
+  }
+  template <typename T, int NT, int FB, bool ANA>
+  static __device__ __forceinline__ int run(const FftArgs& a, int l, int item, unsigned char* smem) {
+    if constexpr (ANA)
+      return zonal_analysis_run_p3<T, P, NT, FB, FC, MS>(a, l, item, smem);
+    else
+      return zonal_synthesis_run_p3<T, P, NT, FB, FC, MS>(a, l, item, smem);
+  }
+};
+
+// runtime radices, twiddles staged in LDS at FftArgs::tw_lds
+template <int FC, int MS, int MAXI>
+struct ZRt {
+  static constexpr int fc = FC, maxi = MAXI, ms = MS;
+  template <typename T, int NT, int FB, bool ANA>
+  static __device__ __forceinline__ int run(const FftArgs& a, int l, int item, unsigned char* smem) {
+    if constexpr (ANA)
+      return zonal_analysis_run<T, NT, FB, FC, MS, MAXI, true>(a, item, level_end(a, l), smem);
+    else
+      return zonal_synthesis_run<T, NT, FB, FC, MS, MAXI, true>(a, item, level_end(a, l), smem);
+  }
+};
+
+template <typename T, int NT, int FB, bool ANA, class C, class... Cs>
+__device__ __forceinline__ int zonal_run_cfg(const FftArgs& a, int k, int l, int item, unsigned char* smem) {
+  if (k == 0) return C::template run<T, NT, FB, ANA>(a, l, item, smem);
+  if constexpr (sizeof...(Cs) > 0)
+    return zonal_run_cfg<T, NT, FB, ANA, Cs...>(a, k - 1, l, item, smem);
+  else
+    return level_end(a, l);  // (not reached: the launcher gives every level a configuration)
+}
+
+template <typename T, int NT, int FB, bool ANA, class... Cs>
+__global__ __launch_bounds__(NT) void k_zonal_levels(const FftArgs a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  int item = blockIdx.x;
+  while (item < a.nitems) {
+    const int l = level_of(a, item);
+    item = zonal_run_cfg<T, NT, FB, ANA, Cs...>(a, a.lev[l].zk, l, item, smem_raw);
+    __syncthreads();  // the next level's run refills the LDS
   }
 }
 
@@ -1278,13 +1370,75 @@ static hipError_t launch_generic(bool analysis, const FftArgs& a, int maxN, hipS
   return launch_cfg<T, 512, FB, FC, 4, 4096>(analysis, a, maxI, st);
 }
 
-// Multi-level plans: each level whose I has a compile-time three-pass plan
-// gets a launch of its own (one level per argument block, its items
-// renumbered from 0); the other levels share one launch of the
-// runtime-radix kernel.  All launches go to the same stream, and the levels
+// Multi-level plans whose levels all have I = 1600, 800 or 400 (three-pass
+// plans) or I <= 1024 (runtime radices), and at least two launches' worth of
+// lengths: one launch of k_zonal_levels.  Returns false (nothing launched)
+// for other plans.
+template <typename T, int FB>
+static bool launch_levels_one(bool analysis, const FftArgs& a, hipStream_t st, hipError_t* err) {
+  constexpr bool dbl = sizeof(T) == 8;
+  constexpr int NT = 512;
+  using C1600 = ZP3<Plan3<1600, 10, 10>, dbl ? 2 : 4, 2>;
+  using C800 = ZP3<Plan3<800, 5, 10>, 4, 1>;
+  using C400 = ZP3<Plan3<400, 5, 5>, dbl ? 4 : 8, 1>;
+  using CRt = ZRt<dbl ? 1 : 4, 1, 1024>;
+  if (a.nlev < 2 || a.fb != FB) return false;
+  FftArgs b = a;
+  size_t lds = 0;
+  int maxIrt = 0, kinds = 0;
+  for (int l = 0; l < a.nlev; ++l) {
+    const LevelDesc& L = a.lev[l];
+    int k;
+    size_t need = 0;
+    if (L.I == 1600 || L.I == 800 || L.I == 400) {
+      // the three-pass kernels address the workspace with 32-bit offsets
+      if ((double)(L.N + 1) * 2.0 * L.Kp * L.Cp * sizeof(T) >= 4294967296.0) return false;
+      k = L.I == 1600 ? 0 : L.I == 800 ? 1 : 2;
+      need = k == 0 ? C1600::template lds<T>() : k == 1 ? C800::template lds<T>() : C400::template lds<T>();
+    } else {
+      if (L.I > CRt::maxi || L.N + 1 > CRt::ms * NT) return false;
+      k = 3;
+      maxIrt = L.I > maxIrt ? L.I : maxIrt;
+    }
+    kinds |= 1 << k;
+    b.lev[l].zk = k;
+    lds = need > lds ? need : lds;
+  }
+  // one runtime-radix launch or one length alone gains nothing
+  if (__builtin_popcount(kinds) < 2) return false;
+  if (maxIrt) {
+    b.tw_lds = (CRt::fc * maxIrt + 1) & ~1;
+    const size_t rt = (size_t)(b.tw_lds + maxIrt) * sizeof(cx<T>);
+    lds = rt > lds ? rt : lds;
+  }
+  int per_cu = (int)(kMaxLds / lds);
+  const int by_waves = 2048 / NT;
+  per_cu = per_cu < by_waves ? per_cu : by_waves;
+  per_cu = per_cu < 1 ? 1 : per_cu;
+  int nwg = g_num_cu * per_cu;
+  nwg = nwg < a.nitems ? nwg : a.nitems;
+  const dim3 grid(nwg), block(NT);
+  if (analysis) {
+    lds_optin<k_zonal_levels<T, NT, FB, true, C1600, C800, C400, CRt>>(lds);
+    hipLaunchKernelGGL((k_zonal_levels<T, NT, FB, true, C1600, C800, C400, CRt>), grid, block, lds, st, b);
+  } else {
+    lds_optin<k_zonal_levels<T, NT, FB, false, C1600, C800, C400, CRt>>(lds);
+    hipLaunchKernelGGL((k_zonal_levels<T, NT, FB, false, C1600, C800, C400, CRt>), grid, block, lds, st, b);
+  }
+  *err = hipGetLastError();
+  return true;
+}
+
+// Multi-level plans: one launch of k_zonal_levels where every level fits
+// it (and FftArgs::one_launch asks for it); otherwise each level whose I has a compile-time three-pass plan gets
+// a launch of its own (one level per argument block, its items renumbered
+// from 0), and the other levels share one launch of the runtime-radix
+// kernel.  All launches go to the same stream, and the levels
 // write disjoint parts of the output.
 template <typename T, int FB, int FC>
 static hipError_t launch_levels(bool analysis, const FftArgs& a, hipStream_t st) {
+  hipError_t e1 = hipSuccess;
+  if (a.one_launch && launch_levels_one<T, FB>(analysis, a, st, &e1)) return e1;
   FftArgs rest = a;
   rest.nlev = 0;
   rest.nitems = 0;

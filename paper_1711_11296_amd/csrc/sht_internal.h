@@ -43,7 +43,7 @@ struct LevelDesc {
   int fft_item0;   // first FFT work item of this level
   int nfb;         // field blocks of the FFT kernels
   int m_base;      // index of (level, m=0) in the per-m offset arrays
-  int pad_;
+  int zk;          // zonal stage, one-launch multi-level kernel: configuration of this level (set at launch)
   long long grid_off;  // element offset of this level in the grid buffer
   long long spec_off;  // element offset of this level in the spec buffer
   long long ws_off;    // element offset in the workspace
@@ -64,6 +64,7 @@ struct FftArgs {
   double mscale;
   int tw_lds;        // element offset of the LDS twiddle table (set at launch)
   int fb;            // fields per work item (zonal_fields_per_block)
+  int one_launch;    // multi-level plans: one launch over all levels where they allow it
   // per (level, m): first latitude of the Legendre sums (reduced transform;
   // else 0); the synthesis leaves whole 128-latitude tiles below it out of
   // the workspace, and the zonal synthesis reads them as zero

@@ -30,7 +30,8 @@ class Plan:
     """A transform plan on the current GPU.
 
     levels: one (N, J, I, nfields) tuple, or a list of them for a batched
-    hierarchy run together (one Legendre launch per direction for all levels).  grid: "cc_poles", "fejer2" or "fejer1";
+    hierarchy run together (one Legendre launch per direction for all
+    levels).  grid: "cc_poles", "fejer2", "fejer1" or "gauss";
     form: "fp64", "fp32" or "bf16x6".  reduced: leave out, per m, the polar
     latitudes where every |P~_n^m| < 1e-16 (the reduced transform of
     Sec. 4.1; see sht_options.reduced).  use_graph: each (direction, input
@@ -39,11 +40,13 @@ class Plan:
     the same out= buffers on every call (without out= a new output tensor,
     hence a new capture, may be made each time).  otf: both Legendre kernels
     generate P~ in FP64 from two stored seed rows per 16 degrees instead of
-    reading a table, in every form (see sht_options.otf).
+    reading a table, in every form (see sht_options.otf).  zonal (several
+    levels): "auto", "one_launch" or "per_length", how the zonal stage is
+    launched (see sht_zonal_t; with autotune, "auto" takes the faster).
     """
 
     def __init__(self, N=None, J=None, I=None, nfields=None, *, levels=None, grid="cc_poles",
-                 form="fp64", autotune=False, use_graph=False, reduced=False, otf=False):
+                 form="fp64", autotune=False, use_graph=False, reduced=False, otf=False, zonal="auto"):
         import torch
         lib = _lib.load()
         if levels is None:
@@ -52,7 +55,8 @@ class Plan:
         self.grid_kind = grid
         self.form = form
         self.dtype = torch.float64 if form == "fp64" else torch.float32
-        opts = _lib.Options(_lib.GRID[grid], _lib.FORM[form], int(autotune), int(use_graph), int(reduced), int(otf))
+        opts = _lib.Options(_lib.GRID[grid], _lib.FORM[form], int(autotune), int(use_graph), int(reduced), int(otf),
+                            _lib.ZONAL[zonal])
         h = ctypes.c_void_p()
         n = len(self.levels)
         arr = lambda k: (ctypes.c_int * n)(*[lv[k] for lv in self.levels])  # noqa: E731

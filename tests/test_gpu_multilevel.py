@@ -125,15 +125,19 @@ def test_autotune_cache_written(plan):
     path = os.environ["SHT_TUNE_CACHE"]
     txt = open(path).read()
     line = [ln for ln in txt.splitlines() if " lev5 " in ln][-1]
-    assert " form1 " in line and " v2 " in line and "|" in line
+    assert " form1 " in line and " v3 " in line and "|" in line
+    vals = [int(x) for x in line.split("|")[1].split()]
+    # Legendre blocking and order per direction, then the zonal launch
+    # choice per direction (one launch or per FFT length)
+    assert len(vals) == 6 and vals[4] in (0, 1) and vals[5] in (0, 1)
 
 
 @pytest.mark.parametrize("form", ["fp64", "bf16x6"])
 def test_mixed_length_levels_other_forms(form):
     """A multi-level plan whose levels mix lengths with a compile-time FFT
     plan (I = 400, 800) and without one (I = 200, 300), in the FP64 and
-    split forms: the per-length zonal launches and the shared runtime-radix
-    launch together cover every level, each against the oracle."""
+    split forms (one zonal launch per direction covers every level): each
+    level against the oracle."""
     from paper_1711_11296_amd import Plan
     levels = [(64, 129, 200, 3), (128, 257, 400, 2), (149, 150, 300, 5), (399, 97, 800, 2)]
     dt = torch.float64 if form == "fp64" else torch.float32
@@ -148,6 +152,53 @@ def test_mixed_length_levels_other_forms(form):
         assert rel(gl[k], O.inverse(al[k], N, J, I, "cc_poles")) < tol, ("inverse", levels[k])
         assert rel(sl[k], O.forward(gl[k], N, "cc_poles")) < tol, ("forward", levels[k])
     p.close()
+
+
+@pytest.mark.parametrize("zonal", ["one_launch", "per_length"])
+@pytest.mark.parametrize("form", ["fp64", "fp32", "bf16x6"])
+def test_levels_ragged(form, zonal):
+    """Both launch modes of a multi-level zonal stage (one launch over all
+    levels; one per FFT length) with every kind of level the one-launch
+    kernel takes (I = 1600, 800 and 400 with compile-time plans, I = 100 and
+    128 with runtime radices), in plan order unlike their sizes, odd and even
+    J, field counts that leave partial field blocks, all three forms: each
+    level of both directions against the oracle."""
+    from paper_1711_11296_amd import Plan
+    levels = [(500, 1001, 1600, 11), (40, 81, 100, 9), (130, 262, 400, 13), (200, 401, 800, 3),
+              (60, 121, 128, 17)]
+    dt = torch.float64 if form == "fp64" else torch.float32
+    tol = 1e-12 if form == "fp64" else 1e-6
+    p = Plan(levels=levels, grid="cc_poles", form=form, zonal=zonal)
+    specs = [inputs.random_spectra(N, F, seed=40 + k, profile="inv1") for k, (N, J, I, F) in enumerate(levels)]
+    a = torch.from_numpy(np.concatenate([s.ravel() for s in specs])).to(_dev(), dt)
+    g = p.inverse(a)
+    s = p.forward(g)
+    al, gl, sl = _split(p, _np(a), "spec"), _split(p, _np(g), "grid"), _split(p, _np(s), "spec")
+    p.close()
+    for k, (N, J, I, F) in enumerate(levels):
+        assert rel(gl[k], O.inverse(al[k], N, J, I, "cc_poles")) < tol, ("inverse", levels[k])
+        assert rel(sl[k], O.forward(gl[k], N, "cc_poles")) < tol, ("forward", levels[k])
+
+
+@pytest.mark.parametrize("form", ["fp64", "fp32"])
+def test_per_length_levels(form):
+    """A multi-level plan with a length outside the one-launch kernel (I =
+    480) takes one zonal launch per compile-time length plus one for the
+    runtime-radix levels: each level against the oracle."""
+    from paper_1711_11296_amd import Plan
+    levels = [(159, 319, 480, 5), (64, 129, 200, 3), (100, 201, 400, 10), (30, 40, 90, 2)]
+    dt = torch.float64 if form == "fp64" else torch.float32
+    tol = 1e-12 if form == "fp64" else 1e-6
+    p = Plan(levels=levels, grid="cc_poles", form=form)
+    specs = [inputs.random_spectra(N, F, seed=50 + k, profile="inv1") for k, (N, J, I, F) in enumerate(levels)]
+    a = torch.from_numpy(np.concatenate([s.ravel() for s in specs])).to(_dev(), dt)
+    g = p.inverse(a)
+    s = p.forward(g)
+    al, gl, sl = _split(p, _np(a), "spec"), _split(p, _np(g), "grid"), _split(p, _np(s), "spec")
+    p.close()
+    for k, (N, J, I, F) in enumerate(levels):
+        assert rel(gl[k], O.inverse(al[k], N, J, I, "cc_poles")) < tol, ("inverse", levels[k])
+        assert rel(sl[k], O.forward(gl[k], N, "cc_poles")) < tol, ("forward", levels[k])
 
 
 def test_concurrent_levels_keep_stream_order():

@@ -55,6 +55,9 @@ def test_invalid_arguments_are_rejected_without_a_gpu():
     assert lib.sht_plan_ex(4, 9, 14, 1, ctypes.byref(opts), ctypes.byref(h)) == _lib.SHT_EINVAL  # 7 | I
     assert lib.sht_plan_ex(4, 9, 9, 0, ctypes.byref(opts), ctypes.byref(h)) == _lib.SHT_EINVAL  # F < 1
     assert lib.sht_plan_ex(4, 9, 9, 1, ctypes.byref(opts), None) == _lib.SHT_EINVAL
+    bad = _lib.Options(0, 0, 0, 0, 0, 0, 3)     # no such zonal launch mode
+    assert lib.sht_plan_ex(4, 9, 9, 1, ctypes.byref(bad), ctypes.byref(h)) == _lib.SHT_EINVAL
+    assert "zonal" in _lib.last_error()
     assert not h.value
     del dp
 
