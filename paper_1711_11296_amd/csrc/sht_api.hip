@@ -190,6 +190,7 @@ int check_level_args(int N, int J, int I, int F, int grid) {
 }
 
 int autotune(sht_plan_s* P);
+bool blocking_ok(const sht_plan_s* P, bool analysis, int c);
 
 int build_plan(int nlev, const int* Nv, const int* Jv, const int* Iv, const int* Fv,
                const sht_options* opts, sht_plan_t* out) {
@@ -346,6 +347,27 @@ int build_plan(int nlev, const int* Nv, const int* Jv, const int* Iv, const int*
       if (ok) {
         ncb = c;
         break;
+      }
+    }
+  }
+  // small plans: where a direction's tiles would not give every compute
+  // unit two workgroups, narrower column tiles (more of them) are taken, as
+  // long as a narrower blocking is admissible (blocking_ok)
+  {
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, P->device) != hipSuccess || ncu <= 0)
+      ncu = 256;
+    for (int dir = 0; dir < 2; ++dir) {
+      int& ncb = dir == 0 ? P->ncb_fwd : P->ncb_inv;
+      while (build_tiles(P->form, nlev, P->lev, P->jst.data(), dir == 0, ncb, 0).size() < 2 * (size_t)ncu) {
+        int next = 0;
+        for (int c : {8, 5, 4, 2, 1})
+          if (c < ncb && blocking_ok(P, dir == 0, c)) {
+            next = c;
+            break;
+          }
+        if (!next) break;
+        ncb = next;
       }
     }
   }
