@@ -276,7 +276,9 @@ int sht_device_bytes(size_t* out);
  *   SHT_GRID_CC_POLES: (J_fine-1) = s (J_coarse-1), coarse row j = fine row
  *   s j; SHT_GRID_FEJER2: (J_fine+1) = s (J_coarse+1), coarse row j = fine
  *   row s (j+1) - 1; columns: I_fine = t I_coarse, coarse column i = fine
- *   column t i.  SHT_GRID_FEJER1 does not nest (SHT_EINVAL).
+ *   column t i.  SHT_GRID_FEJER1 does not nest (SHT_EINVAL).  fine and
+ *   coarse need only be element-aligned (one level's slice of a multi-level
+ *   plan's concatenated grids).
  * Both return SHT_EINVAL on bad sizes or pointers, SHT_EHIP on a launch
  * failure.
  */
@@ -308,6 +310,10 @@ int sht_grid_product(long long n, int dbl, const void* a, const void* b,
  * sht_grid_residual: r[i] = x[i] - alpha * kappa[i mod n_per] * y[i] - f[i]
  *   for i < n (n a multiple of n_per: kappa is one grid of n_per values
  *   shared by all fields).  r may equal x, y or f.
+ * Unlike the calls above, these two take element-aligned buffers (one
+ * level's slice of a multi-level plan's concatenated grids or spectra):
+ * sht_spec_laplacian needs in and out aligned to a complex pair (8 bytes
+ * for float, 16 for double), sht_grid_residual to one element.
  * SHT_EINVAL on bad sizes, a non-finite scale or alpha, or bad pointers;
  * SHT_EHIP on a launch failure.
  */

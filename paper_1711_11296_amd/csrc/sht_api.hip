@@ -482,9 +482,10 @@ int check_plan(sht_plan_t p) {
   return SHT_OK;
 }
 
-int check_ptr(const void* p, const char* name) {
+int check_ptr(const void* p, const char* name, int align = 16) {
   if (!p) return fail(SHT_EINVAL, std::string(name) + " must not be NULL");
-  if (reinterpret_cast<uintptr_t>(p) % 16) return fail(SHT_EINVAL, std::string(name) + " must be 16-byte aligned");
+  if (reinterpret_cast<uintptr_t>(p) % align)
+    return fail(SHT_EINVAL, std::string(name) + " must be " + std::to_string(align) + "-byte aligned");
   return SHT_OK;
 }
 
@@ -921,8 +922,10 @@ int sht_spec_laplacian(int N, int nfields, int dbl, double scale, const void* in
   if (N < 0 || N > 65534 || nfields < 1 || nfields > 65535)
     return fail(SHT_EINVAL, "need 0 <= N <= 65534 and 1 <= nfields <= 65535");
   if (!std::isfinite(scale)) return fail(SHT_EINVAL, "scale must be finite");
-  int rc = check_ptr(in, "in");
-  if (!rc) rc = check_ptr(out, "out");
+  // complex pairs: aligned to two elements
+  const int al = dbl ? 16 : 8;
+  int rc = check_ptr(in, "in", al);
+  if (!rc) rc = check_ptr(out, "out", al);
   if (rc) return rc;
   return hip_check((hipError_t)launch_laplacian(N, nfields, scale, dbl != 0, in, out, stream), "laplacian launch");
 }
@@ -931,11 +934,12 @@ int sht_grid_residual(long long n, long long n_per, int dbl, double alpha, const
                       const void* y, const void* f, void* r, void* stream) {
   if (n < 1 || n_per < 1 || n % n_per) return fail(SHT_EINVAL, "need n >= 1 a multiple of n_per >= 1");
   if (!std::isfinite(alpha)) return fail(SHT_EINVAL, "alpha must be finite");
-  int rc = check_ptr(x, "x");
-  if (!rc) rc = check_ptr(kappa, "kappa");
-  if (!rc) rc = check_ptr(y, "y");
-  if (!rc) rc = check_ptr(f, "f");
-  if (!rc) rc = check_ptr(r, "r");
+  const int al = dbl ? 8 : 4;  // element-aligned (16-byte vectors where all are)
+  int rc = check_ptr(x, "x", al);
+  if (!rc) rc = check_ptr(kappa, "kappa", al);
+  if (!rc) rc = check_ptr(y, "y", al);
+  if (!rc) rc = check_ptr(f, "f", al);
+  if (!rc) rc = check_ptr(r, "r", al);
   if (rc) return rc;
   return hip_check((hipError_t)launch_residual(n, n_per, alpha, dbl != 0, x, kappa, y, f, r, stream),
                    "residual launch");
@@ -960,8 +964,9 @@ int sht_grid_inject(int J_fine, int I_fine, int J_coarse, int I_coarse, int nfie
     return fail(SHT_EINVAL, "grid kind does not nest");
   }
   if (J_coarse > 65535) return fail(SHT_EINVAL, "J_coarse too large");
-  int rc = check_ptr(fine, "fine");
-  if (!rc) rc = check_ptr(coarse, "coarse");
+  const int al = dbl ? 8 : 4;  // element-aligned: scalar accesses
+  int rc = check_ptr(fine, "fine", al);
+  if (!rc) rc = check_ptr(coarse, "coarse", al);
   if (rc) return rc;
   if (fine == coarse) return fail(SHT_EINVAL, "fine and coarse must not overlap");
   return hip_check((hipError_t)launch_inject(J_fine, I_fine, J_coarse, I_coarse, nfields, rs, r0, I_fine / I_coarse,

@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdint>
 
 #include "sht_internal.h"
 
@@ -126,7 +127,11 @@ int launch_residual(long long n, long long n_per, double alpha, bool dbl, const 
   hipStream_t st = static_cast<hipStream_t>(stream);
   const long long nf = n / n_per;
   const int E = dbl ? 2 : 4;
-  const bool vec = n_per % E == 0;
+  // 16-byte vectors where every field starts 16-byte aligned; else scalars
+  // (element-aligned slices of a larger buffer, e.g. one level of a
+  // multi-level plan's grids)
+  auto a16 = [](const void* p) { return reinterpret_cast<uintptr_t>(p) % 16 == 0; };
+  const bool vec = n_per % E == 0 && a16(x) && a16(kappa) && a16(y) && a16(f) && a16(r);
   long long bx = (n_per / (vec ? E : 1) + 255) / 256;
   bx = bx < 1 ? 1 : (bx > 4096 ? 4096 : bx);
   const long long by = nf > 65535 ? 65535 : nf;

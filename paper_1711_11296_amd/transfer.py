@@ -38,14 +38,26 @@ def spec_retruncate(spec, N_in, N_out):
     return out
 
 
-def grid_inject(grid, J_coarse, I_coarse, kind="cc_poles"):
+def _check_out(out, shape, like):
+    if tuple(out.shape) != tuple(shape) or out.dtype != like.dtype or out.device != like.device:
+        raise ValueError("out must be %s of %s on %s" % (tuple(shape), like.dtype, like.device))
+    if not out.is_contiguous():
+        raise ValueError("out must be contiguous")
+    return out
+
+
+def grid_inject(grid, J_coarse, I_coarse, kind="cc_poles", out=None):
     """Grids [F, J_fine, I_fine] -> [F, J_coarse, I_coarse]: the nested rows
-    and columns of the finer grid (see sht_grid_inject)."""
+    and columns of the finer grid (see sht_grid_inject); into `out` when
+    given (contiguous, not overlapping grid)."""
     import torch
     lib = _lib.load()
     grid = grid.contiguous()
     F, J, I = grid.shape
-    out = torch.empty((F, J_coarse, I_coarse), dtype=grid.dtype, device=grid.device)
+    if out is None:
+        out = torch.empty((F, J_coarse, I_coarse), dtype=grid.dtype, device=grid.device)
+    else:
+        _check_out(out, (F, J_coarse, I_coarse), grid)
     stream = torch.cuda.current_stream(grid.device).cuda_stream
     _lib.check(lib.sht_grid_inject(J, I, J_coarse, I_coarse, F, _GRID[kind], _dbl(grid),
                                    ctypes.c_void_p(grid.data_ptr()), ctypes.c_void_p(out.data_ptr()),
@@ -69,26 +81,27 @@ def grid_product(a, b):
 
 
 
-def spec_laplacian(spec, N, scale=1.0):
+def spec_laplacian(spec, N, scale=1.0, out=None):
     """Spectra [F, (N+1)(N+2)/2, 2] -> c_n * spec with c_n = -scale n (n+1):
-    the Laplacian on a sphere of radius 1/sqrt(scale)."""
+    the Laplacian on a sphere of radius 1/sqrt(scale); into `out` when given
+    (contiguous; may be spec)."""
     import torch
     lib = _lib.load()
     spec = spec.contiguous()
     F = spec.shape[0]
     if tuple(spec.shape) != (F, (N + 1) * (N + 2) // 2, 2):
         raise ValueError("spec must be [F, %d, 2]" % ((N + 1) * (N + 2) // 2))
-    out = torch.empty_like(spec)
+    out = torch.empty_like(spec) if out is None else _check_out(out, spec.shape, spec)
     stream = torch.cuda.current_stream(spec.device).cuda_stream
     _lib.check(lib.sht_spec_laplacian(N, F, _dbl(spec), float(scale), ctypes.c_void_p(spec.data_ptr()),
                                       ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(stream)))
     return out
 
 
-def grid_residual(x, kappa, y, f, alpha):
+def grid_residual(x, kappa, y, f, alpha, out=None):
     """r = x - alpha * kappa * y - f; x, y, f [F, J, I] (or any shape whose
     trailing elements form whole copies of kappa), kappa [J, I] shared by
-    all fields."""
+    all fields; into `out` when given (contiguous; may be x, y or f)."""
     import torch
     lib = _lib.load()
     ts = [x.contiguous(), kappa.contiguous(), y.contiguous(), f.contiguous()]
@@ -99,7 +112,7 @@ def grid_residual(x, kappa, y, f, alpha):
     n, n_per = ts[0].numel(), ts[1].numel()
     if n_per < 1 or n % n_per:
         raise ValueError("kappa must tile x")
-    r = torch.empty_like(ts[0])
+    r = torch.empty_like(ts[0]) if out is None else _check_out(out, ts[0].shape, ts[0])
     stream = torch.cuda.current_stream(x.device).cuda_stream
     _lib.check(lib.sht_grid_residual(n, n_per, _dbl(ts[0]), float(alpha), *[ctypes.c_void_p(t.data_ptr()) for t in ts],
                                      ctypes.c_void_p(r.data_ptr()), ctypes.c_void_p(stream)))

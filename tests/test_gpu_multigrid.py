@@ -1,8 +1,8 @@
 """The residual and restriction steps of the App. C two-grid cycle on the
 GPU, through the C ABI: the spectral Laplacian and the residual update
-against the oracle, and the composed residual on two nested levels of the
+against the oracle, the composed residual on two nested levels of the
 hierarchy (N = 32 and 64 on the grid with poles; N = 79 and 159 on the
-paper's grid) in every form."""
+paper's grid) in every form, and both steps on multi-level plans."""
 
 import numpy as np
 import pytest
@@ -89,3 +89,61 @@ def test_two_level_residual_and_restriction(form, kind, Nc, Jc, Ic, Nf, Jf, If):
     assert np.linalg.norm(Rcg - Rcg_ref) / np.linalg.norm(Xc) < TOL[form]
     fine.close()
     coarse.close()
+
+
+@pytest.mark.parametrize("form", ["fp64", "fp32", "bf16x6"])
+def test_multilevel_residual_and_restriction(form):
+    """The residual on a multi-level plan (three nested levels of the grid
+    with poles in one plan: one batched analysis and synthesis, a scale per
+    level) against the oracle level by level, and the batched restriction
+    of the two finer levels' residuals onto a two-level coarse plan against
+    the oracle's injection and analysis.  The sizes leave some levels'
+    slices of the concatenated buffers 8 bytes off a 16-byte boundary."""
+    kind = "cc_poles"
+    levels = [(32, 65, 90, 3), (64, 129, 180, 1), (128, 257, 360, 3)]
+    dt = torch.float64 if form == "fp64" else torch.float32
+    alpha, scales = 0.2, [1e-4, 2e-4, 5e-5]
+    rng = np.random.default_rng(7)
+    p = Plan(levels=levels, grid=kind, form=form)
+
+    def concat(seed):
+        return torch.from_numpy(np.concatenate([inputs.random_spectra(N, F, seed=seed + k, profile="inv1").ravel()
+                                                for k, (N, J, I, F) in enumerate(levels)])).to("cuda:0", dt)
+
+    X, Fr = p.inverse(concat(1)), p.inverse(concat(11))
+    kap = [torch.from_numpy(1.0 + 0.5 * rng.random((J, I))).to("cuda:0", dt) for (N, J, I, F) in levels]
+    R = helmholtz_residual(p, X, kap, Fr, alpha, scales)
+    assert R.shape == X.shape
+    Xh, Fh, Rh = _host(X), _host(Fr), _host(R)
+    Rk = []
+    for k, (N, J, I, F) in enumerate(levels):
+        o, n = p.grid_offsets[k], F * J * I
+        xk, fk, rk = (v[o:o + n].reshape(F, J, I) for v in (Xh, Fh, Rh))
+        ref = O.helmholtz_residual(xk, _host(kap[k]), fk, alpha, N, kind, scales[k])
+        assert np.linalg.norm(rk - ref) / np.linalg.norm(xk) < TOL[form], levels[k]
+        Rk.append(rk)
+    p.close()
+    coarse = [(32, 65, 90, 1), (64, 129, 180, 3)]
+    c = Plan(levels=coarse, grid=kind, form=form)
+    Rc = _host(restrict_to_coarse_spectra([torch.from_numpy(Rk[k + 1]).to("cuda:0", dt) for k in range(2)], c, kind))
+    for k, (N, J, I, F) in enumerate(coarse):
+        o, n = c.spec_offsets[k], F * (N + 1) * (N + 2)
+        ref = O.forward(O.inject(Rk[k + 1], J, I, kind), N, kind)
+        assert _rel(Rc[o:o + n].reshape(ref.shape), ref) < TOL[form], coarse[k]
+    c.close()
+
+
+def test_multilevel_helpers_check_arguments():
+    p = Plan(levels=[(8, 17, 32, 1), (16, 33, 64, 1)], grid="cc_poles", form="fp64")
+    x = torch.zeros(p.grid_elems, dtype=torch.float64, device="cuda:0")
+    k1, k2 = torch.ones(17, 32, dtype=torch.float64, device="cuda:0"), torch.ones(33, 64, dtype=torch.float64,
+                                                                                    device="cuda:0")
+    with pytest.raises(ValueError):
+        helmholtz_residual(p, x, k1, x, 0.1)              # one kappa per level
+    with pytest.raises(ValueError):
+        helmholtz_residual(p, x, [k2, k1], x, 0.1)        # kappa shapes per level
+    with pytest.raises(ValueError):
+        helmholtz_residual(p, x[:-1], [k1, k2], x[:-1], 0.1)
+    with pytest.raises(ValueError):
+        restrict_to_coarse_spectra(x, p, "cc_poles")       # one fine grid per level
+    p.close()
