@@ -274,9 +274,10 @@ def bench_two_grid(args, torch):
 def bench_hierarchy(args, torch):
     """One step = one analysis + one synthesis of all five levels of the
     nested hierarchy (one Legendre launch per direction for all levels; the
-    zonal stage launches once per level with a compile-time FFT length and
-    once for the rest), replayed as a hipGraph, FP32 form, autotuned tiles.  Stage times come from a second, eager plan of
-    the same levels (graph replays record no per-stage events)."""
+    zonal stage in one launch over all levels or one per FFT length, as the
+    autotuner chose per direction), replayed as a hipGraph, FP32 form,
+    autotuned tiles.  Stage times come from a second, eager plan of the same
+    levels (graph replays record no per-stage events)."""
     import numpy as np
     from paper_1711_11296_amd import Plan, inputs
     torch.cuda.set_device(0)
@@ -352,8 +353,9 @@ def bench_hierarchy(args, torch):
            "dtype": "f32" if form == "fp32" else ("f64" if form == "fp64" else "bf16x6/f32"),
            "data": "synthetic: grids synthesised from k^-3 random spectra (seed = level index)",
            "config": {"workload": "nested hierarchy N=32,64,128,256,512 (J=2N+1, I=100..1600, grid with poles), "
-                                  "32 fields per level, one Legendre launch per direction, zonal launches per "
-                                  "FFT length, graph replay, %s form" % form,
+                                  "32 fields per level, one Legendre launch per direction, the zonal stage in "
+                                  "one launch or one per FFT length (autotuned per direction), graph replay, "
+                                  "%s form" % form,
                       "levels": [list(lv) for lv in HIER_LEVELS], "fields": Ftot, "form": form},
            "legendre_tflops": 2 * flops_dir / ((la + ls) * 1e-3) / 1e12,
            "stage_ms_eager": st, "rel_err_vs_oracle_field0": err,
