@@ -53,8 +53,9 @@ def test_graph_cache_cycles_past_its_capacity():
 
 def test_autotune_cache_with_an_inadmissible_entry(tmp_path, monkeypatch):
     """A cache line whose blocking does not fit the plan's workspace layout
-    (here 64 column blocks, wider than any kernel takes) is not used: the
-    plan re-tunes, stores an admissible line and still matches the oracle."""
+    (here 64 column blocks, wider than any kernel takes), or whose zonal
+    launch choice is neither 0 nor 1, is not used: the plan re-tunes, stores
+    an admissible line and still matches the oracle."""
     from paper_1711_11296_amd import Plan
     cache = tmp_path / "tune.txt"
     monkeypatch.setenv("SHT_TUNE_CACHE", str(cache))
@@ -64,9 +65,15 @@ def test_autotune_cache_with_an_inadmissible_entry(tmp_path, monkeypatch):
     lines = cache.read_text().splitlines()
     assert len(lines) == 1 and "|" in lines[0]
     key, vals = lines[0].split("|")
-    assert "hip" in key and " v2 " in key
+    assert "hip" in key and " v3 " in key
     good = [int(v) for v in vals.split()]
-    cache.write_text("%s|64 0 64 1\n" % key)
+    assert len(good) == 6
+    # a zonal launch choice outside {0, 1} with an otherwise good line
+    cache.write_text("%s|%d %d %d %d 2 1\n" % (key, *good[:4]))
+    Plan(N, J, I, F, grid="fejer2", form="fp32", autotune=True).close()
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 2 and [int(v) for v in lines[1].split("|")[1].split()][4:] == [1, 1]
+    cache.write_text("%s|64 0 64 1 1 1\n" % key)
     p = Plan(N, J, I, F, grid="fejer2", form="fp32", autotune=True)
     g = torch.from_numpy(inputs.random_grid(F, J, I, seed=21)).to(_dev(), torch.float32)
     s = p.forward(g)
@@ -81,6 +88,7 @@ def test_autotune_cache_with_an_inadmissible_entry(tmp_path, monkeypatch):
     assert len(lines) == 2 and lines[1].startswith(key + "|")
     redo = [int(v) for v in lines[1].split("|")[1].split()]
     assert redo[0] in (1, 2, 4, 8, 10) and redo[2] in (1, 2, 4, 8) and redo[1] in (0, 1) and redo[3] in (0, 1)
+    assert redo[4] == 1 and redo[5] == 1   # single-level plan: the zonal choice stays "one launch"
     del good
 
 
