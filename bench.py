@@ -124,6 +124,28 @@ def counted_traffic(stage, form, config):
     return None
 
 
+def host_description():
+    """CPU model, logical CPUs, numpy and its BLAS (for the oracle's timing)."""
+    import numpy as np
+    model = "unknown CPU"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    blas = ""
+    try:
+        from threadpoolctl import threadpool_info
+        blas = ", ".join("%s %s (%s threads)" % (i.get("internal_api", "?"), i.get("version", "?"),
+                                                 i.get("num_threads", "?")) for i in threadpool_info())
+    except Exception:
+        pass
+    return "host %s, %d logical CPUs, numpy %s%s" % (model, os.cpu_count() or 0, np.__version__,
+                                                     ", BLAS " + blas if blas else "")
+
+
 def time_pairs(plan, g, steps, warmup, torch):
     """Warm up, then time `steps` analysis+synthesis pairs with nothing but
     the transforms on the stream (wall clock between two synchronisations).
@@ -346,7 +368,7 @@ def bench_hierarchy(args, torch):
         cpu = {"value": len(HIER_LEVELS) / t_cpu, "unit": "fields*SHT-pairs/s", "cores": int(os.cpu_count()),
                "kind": "oracle",
                "sample": "field 0 of each of the 5 levels (the workload's mix, 1/32 of it), one analysis + one "
-                         "synthesis each, FP64 numpy oracle, %.1f s" % t_cpu}
+                         "synthesis each, FP64 numpy oracle, %.1f s; %s" % (t_cpu, host_description())}
     out = {"metric": "fields*SHT-pairs/s", "value": value, "unit": "fields*SHT-pairs/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": secs / args.steps * 1e3,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -457,8 +479,8 @@ def main():
         cpu = {"value": len(sel) / t_cpu, "unit": "fields*SHT-pairs/s", "cores": int(nthreads or os.cpu_count()),
                "kind": "oracle",
                "sample": "%d of %d fields (fields %s), one analysis + one synthesis at N=%d J=%d I=%d, FP64 "
-                         "numpy oracle (DFT matrix, unfolded Legendre sums), %.1f s"
-                         % (len(sel), F, sel, N, J, I, t_cpu)}
+                         "numpy oracle (DFT matrix, unfolded Legendre sums), %.1f s; %s"
+                         % (len(sel), F, sel, N, J, I, t_cpu, host_description())}
 
     # ---- FP64 form on the same batch (speedup of the chosen form) ----
     fp64 = None
