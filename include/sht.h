@@ -105,9 +105,11 @@ typedef struct {
 } sht_options;
 
 typedef enum {
-  SHT_ZONAL_AUTO = 0,        /* one launch where the levels allow it; with
-                                autotune, whichever of the two below timed
-                                faster at plan time, per direction */
+  SHT_ZONAL_AUTO = 0,        /* per direction: with autotune, whichever of
+                                the two below timed faster at plan time;
+                                without, one launch where the levels allow
+                                it and the one-launch kernel of the form and
+                                direction runs without register spills */
   SHT_ZONAL_ONE_LAUNCH = 1,  /* one persistent launch over every level's
                                 work items where every level has I = 400,
                                 800 or 1600 or I <= 1024 (else as below) */
@@ -144,6 +146,10 @@ enum {
                                left out, a whole number of the kernel's
                                blocks (32; 16 in the FP64 form); equal to
                                SHT_Q_LEGENDRE_FLOPS otherwise */
+  SHT_Q_ZONAL_ONE_LAUNCH = 11, /* int, multi-level plans: bit 0 set if the
+                               zonal analysis runs as one launch over all
+                               levels, bit 1 the zonal synthesis (see
+                               sht_zonal_t); 0 for single-level plans */
   SHT_Q_GRID_OFFSET = 100,  /* size_t: element offset of level (key-100) */
   SHT_Q_SPEC_OFFSET = 200   /* size_t: element offset of level (key-200) */
 };

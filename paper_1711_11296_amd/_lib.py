@@ -18,6 +18,7 @@ SHT_OK, SHT_EINVAL, SHT_ENOMEM, SHT_EHIP, SHT_ESTATE = 0, -1, -2, -3, -4
 Q_NLEVELS, Q_NCOEF, Q_EXACT, Q_WORKSPACE_BYTES, Q_TABLE_BYTES = 0, 1, 2, 3, 4
 Q_GRID_ELEMS, Q_SPEC_ELEMS, Q_FORM, Q_GRID_KIND, Q_LEGENDRE_FLOPS = 5, 6, 7, 8, 9
 Q_LEGENDRE_FLOPS_KEPT = 10
+Q_ZONAL_ONE_LAUNCH = 11
 Q_GRID_OFFSET, Q_SPEC_OFFSET = 100, 200
 
 EXPORTS = ["sht_plan", "sht_plan_ex", "sht_plan_multi", "sht_forward", "sht_inverse",

@@ -218,6 +218,12 @@ int build_plan(int nlev, const int* Nv, const int* Jv, const int* Iv, const int*
   P->otf = o.otf != 0;
   P->zonal = o.zonal;
   P->one_fwd = P->one_inv = o.zonal != SHT_ZONAL_PER_LENGTH;
+  if (o.zonal == SHT_ZONAL_AUTO && nlev > 1) {
+    // without a timing, one launch only where its kernel keeps everything in
+    // registers (the autotuner, if asked for, times both and decides)
+    P->one_fwd = !zonal_one_launch_spills(o.form, true);
+    P->one_inv = !zonal_one_launch_spills(o.form, false);
+  }
   P->nlev = nlev;
   P->elem = o.form == SHT_FORM_FP64 ? 8 : 4;
   int rc = hip_check(hipGetDevice(&P->device), "hipGetDevice");
@@ -1038,6 +1044,9 @@ int sht_plan_query(sht_plan_t plan, int key, void* out) {
     case SHT_Q_GRID_KIND: *(int*)out = P->grid; return SHT_OK;
     case SHT_Q_LEGENDRE_FLOPS: *(double*)out = P->flops; return SHT_OK;
     case SHT_Q_LEGENDRE_FLOPS_KEPT: *(double*)out = P->flops_kept; return SHT_OK;
+    case SHT_Q_ZONAL_ONE_LAUNCH:
+      *(int*)out = P->nlev > 1 ? (P->one_fwd ? 1 : 0) | (P->one_inv ? 2 : 0) : 0;
+      return SHT_OK;
     default: break;
   }
   if (key >= SHT_Q_GRID_OFFSET && key < SHT_Q_GRID_OFFSET + P->nlev) {

@@ -1374,14 +1374,27 @@ static hipError_t launch_generic(bool analysis, const FftArgs& a, int maxN, hipS
 // plans) or I <= 1024 (runtime radices), and at least two launches' worth of
 // lengths: one launch of k_zonal_levels.  Returns false (nothing launched)
 // for other plans.
-template <typename T, int FB>
-static bool launch_levels_one(bool analysis, const FftArgs& a, hipStream_t st, hipError_t* err) {
-  constexpr bool dbl = sizeof(T) == 8;
-  constexpr int NT = 512;
+template <typename T>
+struct ZLevels {
+  static constexpr bool dbl = sizeof(T) == 8;
+  static constexpr int NT = 512;
   using C1600 = ZP3<Plan3<1600, 10, 10>, dbl ? 2 : 4, 2>;
   using C800 = ZP3<Plan3<800, 5, 10>, 4, 1>;
   using C400 = ZP3<Plan3<400, 5, 5>, dbl ? 4 : 8, 1>;
   using CRt = ZRt<dbl ? 1 : 4, 1, 1024>;
+  template <int FB, bool ANA>
+  static constexpr auto kernel() {
+    return &k_zonal_levels<T, NT, FB, ANA, C1600, C800, C400, CRt>;
+  }
+};
+
+template <typename T, int FB>
+static bool launch_levels_one(bool analysis, const FftArgs& a, hipStream_t st, hipError_t* err) {
+  constexpr int NT = ZLevels<T>::NT;
+  using C1600 = typename ZLevels<T>::C1600;
+  using C800 = typename ZLevels<T>::C800;
+  using C400 = typename ZLevels<T>::C400;
+  using CRt = typename ZLevels<T>::CRt;
   if (a.nlev < 2 || a.fb != FB) return false;
   FftArgs b = a;
   size_t lds = 0;
@@ -1419,11 +1432,13 @@ static bool launch_levels_one(bool analysis, const FftArgs& a, hipStream_t st, h
   nwg = nwg < a.nitems ? nwg : a.nitems;
   const dim3 grid(nwg), block(NT);
   if (analysis) {
-    lds_optin<k_zonal_levels<T, NT, FB, true, C1600, C800, C400, CRt>>(lds);
-    hipLaunchKernelGGL((k_zonal_levels<T, NT, FB, true, C1600, C800, C400, CRt>), grid, block, lds, st, b);
+    constexpr auto K = ZLevels<T>::template kernel<FB, true>();
+    lds_optin<K>(lds);
+    hipLaunchKernelGGL(K, grid, block, lds, st, b);
   } else {
-    lds_optin<k_zonal_levels<T, NT, FB, false, C1600, C800, C400, CRt>>(lds);
-    hipLaunchKernelGGL((k_zonal_levels<T, NT, FB, false, C1600, C800, C400, CRt>), grid, block, lds, st, b);
+    constexpr auto K = ZLevels<T>::template kernel<FB, false>();
+    lds_optin<K>(lds);
+    hipLaunchKernelGGL(K, grid, block, lds, st, b);
   }
   *err = hipGetLastError();
   return true;
@@ -1471,6 +1486,19 @@ static hipError_t launch_zonal_t(bool analysis, const FftArgs& a, int maxN, hipS
   hipError_t err = hipSuccess;
   if (launch_fixed<T, FB>(analysis, a, maxN, st, &err)) return err;
   return launch_generic<T, FB, FC>(analysis, a, maxN, st);
+}
+
+int zonal_one_launch_spills(int form, bool analysis) {
+  const void* k = nullptr;
+  if (form == SHT_FORM_FP64)
+    k = analysis ? reinterpret_cast<const void*>(ZLevels<double>::kernel<4, true>())
+                 : reinterpret_cast<const void*>(ZLevels<double>::kernel<4, false>());
+  else
+    k = analysis ? reinterpret_cast<const void*>(ZLevels<float>::kernel<8, true>())
+                 : reinterpret_cast<const void*>(ZLevels<float>::kernel<8, false>());
+  hipFuncAttributes fa;
+  if (hipFuncGetAttributes(&fa, k) != hipSuccess) return 1;
+  return fa.localSizeBytes > 0 ? 1 : 0;
 }
 
 int zonal_fields_per_block(int form, int nlev, int N, int J, int I, int F) {

@@ -105,6 +105,9 @@ struct GemmArgs {
 // The level's workspace size with that blocking must be below 4 GiB (the
 // planner checks and falls back to 8).
 int zonal_fields_per_block(int form, int nlev, int N, int J, int I, int F);
+// 1 if the one-launch multi-level zonal kernel of this form and direction
+// keeps values in scratch memory (register spills), else 0
+int zonal_one_launch_spills(int form, bool analysis);
 int launch_zonal(int form, bool analysis, const FftArgs& a, int maxN, void* stream);
 // gen: generate P~ in the kernels from the plan's seed rows instead of
 // reading a table (plan option otf)

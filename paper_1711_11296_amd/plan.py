@@ -68,6 +68,9 @@ class Plan:
         self.spec_elems = self._query(_lib.Q_SPEC_ELEMS, ctypes.c_size_t)
         self.legendre_flops = self._query(_lib.Q_LEGENDRE_FLOPS, ctypes.c_double)
         self.legendre_flops_kept = self._query(_lib.Q_LEGENDRE_FLOPS_KEPT, ctypes.c_double)
+        # multi-level plans: (analysis, synthesis) zonal stage in one launch
+        zo = self._query(_lib.Q_ZONAL_ONE_LAUNCH, ctypes.c_int)
+        self.zonal_one_launch = (bool(zo & 1), bool(zo & 2))
         self.exact = bool(self._query(_lib.Q_EXACT, ctypes.c_int))
         self.workspace_bytes = self._query(_lib.Q_WORKSPACE_BYTES, ctypes.c_size_t)
         self.table_bytes = self._query(_lib.Q_TABLE_BYTES, ctypes.c_size_t)

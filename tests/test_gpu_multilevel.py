@@ -125,6 +125,8 @@ def test_autotune_cache_written(plan):
     path = os.environ["SHT_TUNE_CACHE"]
     txt = open(path).read()
     line = [ln for ln in txt.splitlines() if " lev5 " in ln][-1]
+    # the plan runs the zonal launch modes the tuner stored
+    assert plan.zonal_one_launch == tuple(bool(int(v)) for v in line.split("|")[1].split()[4:6])
     assert " form1 " in line and " v3 " in line and "|" in line
     vals = [int(x) for x in line.split("|")[1].split()]
     # Legendre blocking and order per direction, then the zonal launch
@@ -169,6 +171,7 @@ def test_levels_ragged(form, zonal):
     dt = torch.float64 if form == "fp64" else torch.float32
     tol = 1e-12 if form == "fp64" else 1e-6
     p = Plan(levels=levels, grid="cc_poles", form=form, zonal=zonal)
+    assert p.zonal_one_launch == ((True, True) if zonal == "one_launch" else (False, False))
     specs = [inputs.random_spectra(N, F, seed=40 + k, profile="inv1") for k, (N, J, I, F) in enumerate(levels)]
     a = torch.from_numpy(np.concatenate([s.ravel() for s in specs])).to(_dev(), dt)
     g = p.inverse(a)
