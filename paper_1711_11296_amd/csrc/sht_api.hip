@@ -358,14 +358,20 @@ int build_plan(int nlev, const int* Nv, const int* Jv, const int* Iv, const int*
   }
   // small plans: where a direction's tiles would not give every compute
   // unit two workgroups, narrower column tiles (more of them) are taken, as
-  // long as a narrower blocking is admissible (blocking_ok)
+  // long as a narrower blocking is admissible (blocking_ok); the idle slots
+  // that even out the XCD chunks of a tile list do not count
   {
     int ncu = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, P->device) != hipSuccess || ncu <= 0)
       ncu = 256;
+    auto real_tiles = [&](bool analysis, int c) {
+      size_t n = 0;
+      for (const Tile& t : build_tiles(P->form, nlev, P->lev, P->jst.data(), analysis, c, 0)) n += t.level >= 0;
+      return n;
+    };
     for (int dir = 0; dir < 2; ++dir) {
       int& ncb = dir == 0 ? P->ncb_fwd : P->ncb_inv;
-      while (build_tiles(P->form, nlev, P->lev, P->jst.data(), dir == 0, ncb, 0).size() < 2 * (size_t)ncu) {
+      while (real_tiles(dir == 0, ncb) < 2 * (size_t)ncu) {
         int next = 0;
         for (int c : {8, 5, 4, 2, 1})
           if (c < ncb && blocking_ok(P, dir == 0, c)) {
