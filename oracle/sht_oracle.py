@@ -228,23 +228,42 @@ def alf_m(N, m, mu, sint):
       P~_{m+1}^m = sqrt(2m+3) mu P~_m^m
       P~_n^m = a_n^m (mu P~_{n-1}^m - P~_{n-2}^m / a_{n-1}^m),
       a_n^m = sqrt((4n^2-1)/(n^2-m^2)).
+    The paper runs it in quadruple precision, whose exponent range holds
+    the sectoral start sin^m(theta) at any order used here; in float64 that
+    start falls below the double range at high order (e.g. m = 747 at
+    sin(theta) = 0.37), while P~_n^m grows back to O(1) before n = 2047.  So
+    each latitude's values are carried as a float64 significand times 2^e
+    with one integer exponent e per latitude (the recurrence is linear in
+    the two values it carries, so both are rescaled together), and stored
+    as significand * 2^e, which is 0 where the value is below the double
+    range.
     """
     mu = np.asarray(mu, dtype=np.float64)
     sint = np.asarray(sint, dtype=np.float64)
     out = np.zeros((N - m + 1, mu.size))
+    e = np.zeros(mu.size, dtype=np.int64)
     pmm = np.full(mu.size, 1.0 / math.sqrt(2.0))
     for k in range(1, m + 1):
-        pmm = math.sqrt((2.0 * k + 1.0) / (2.0 * k)) * sint * pmm
-    out[0] = pmm
+        pmm, ex = np.frexp(math.sqrt((2.0 * k + 1.0) / (2.0 * k)) * sint * pmm)
+        e += ex
+    out[0] = np.ldexp(pmm, e)
     if N == m:
         return out
-    out[1] = math.sqrt(2.0 * m + 3.0) * mu * pmm
+    p0, p1 = pmm, math.sqrt(2.0 * m + 3.0) * mu * pmm
+    out[1] = np.ldexp(p1, e)
 
     def a(n):
         return math.sqrt((4.0 * n * n - 1.0) / (n * n - m * m))
 
+    big = 2.0 ** 500
     for n in range(m + 2, N + 1):
-        out[n - m] = a(n) * (mu * out[n - m - 1] - out[n - m - 2] / a(n - 1))
+        p0, p1 = p1, a(n) * (mu * p1 - p0 / a(n - 1))
+        grow = np.abs(p1) > big
+        if grow.any():
+            p0 = np.where(grow, p0 / big, p0)
+            p1 = np.where(grow, p1 / big, p1)
+            e += np.where(grow, 500, 0)
+        out[n - m] = np.ldexp(p1, e)
     return out
 
 

@@ -64,6 +64,26 @@ def test_alf_vs_mpmath_high_degree(n, m, th):
     assert abs(P - float(ref)) <= 1e-9 + 1e-10 * abs(float(ref))
 
 
+@pytest.mark.parametrize("n,m,th,below", [(2047, 747, 12 * math.pi / 100, True), (2047, 760, 0.39, True),
+                                          (2047, 900, 0.5 * math.pi, False)])
+def test_alf_sectoral_start_below_double_range(n, m, th, below):
+    """Orders whose sectoral start sin^m(theta) lies below the double range
+    (0.368^747 ~ 1e-324) while P~_n^m grows back to O(1) by degree n: the
+    values still match mpmath (the recurrence carries its exponent, as the
+    paper's quadruple precision does)."""
+    mpmath.mp.dps = 60
+    mu = math.cos(th)
+    s = math.sin(th)
+    assert (m * math.log10(1.0 / s) > 308) == below
+    ref = mpmath.legenp(n, m, mpmath.mpf(mu)) * (-1) ** m
+    ref *= mpmath.sqrt((2 * n + 1) / mpmath.mpf(2) * mpmath.factorial(n - m) / mpmath.factorial(n + m))
+    P = O.alf_m(n, m, np.array([mu]), np.array([s]))
+    assert abs(P[n - m, 0] - float(ref)) <= 1e-9 + 1e-10 * abs(float(ref)), (P[n - m, 0], float(ref))
+    # the same degrees at the same latitude: every entry finite, the sectoral
+    # one rounded to 0 where it is below the double range
+    assert np.all(np.isfinite(P))
+
+
 def test_alf_orthonormal_under_gauss_rule():
     N = 30
     x, w = npleg.leggauss(40)
