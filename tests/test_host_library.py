@@ -55,6 +55,13 @@ def test_invalid_arguments_are_rejected_without_a_gpu():
     assert lib.sht_plan_ex(4, 9, 14, 1, ctypes.byref(opts), ctypes.byref(h)) == _lib.SHT_EINVAL  # 7 | I
     assert lib.sht_plan_ex(4, 9, 9, 0, ctypes.byref(opts), ctypes.byref(h)) == _lib.SHT_EINVAL  # F < 1
     assert lib.sht_plan_ex(4, 9, 9, 1, ctypes.byref(opts), None) == _lib.SHT_EINVAL
+    n9 = (ctypes.c_int * 9)(*([8] * 9))
+    i9 = (ctypes.c_int * 9)(*([32] * 9))
+    j9 = (ctypes.c_int * 9)(*([17] * 9))
+    f9 = (ctypes.c_int * 9)(*([1] * 9))
+    assert lib.sht_plan_multi(9, n9, j9, i9, f9, ctypes.byref(opts), ctypes.byref(h)) == _lib.SHT_EINVAL
+    assert "nlevels" in _lib.last_error()                                                  # at most 8 levels
+    assert lib.sht_plan_ex(4, 9, 4800, 1, ctypes.byref(opts), ctypes.byref(h)) == _lib.SHT_EINVAL  # I > 4096
     bad = _lib.Options(0, 0, 0, 0, 0, 0, 3)     # no such zonal launch mode
     assert lib.sht_plan_ex(4, 9, 9, 1, ctypes.byref(bad), ctypes.byref(h)) == _lib.SHT_EINVAL
     assert "zonal" in _lib.last_error()
