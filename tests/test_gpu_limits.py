@@ -14,7 +14,7 @@ from paper_1711_11296_amd import Plan, inputs
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp64": 1e-12, "fp32": 1e-6}
+TOL = {"fp64": 1e-12, "fp32": 1e-6, "bf16x6": 1e-6}
 
 
 def _host(t):
@@ -27,28 +27,35 @@ def _rel(x, y):
 
 
 def test_longest_fft_and_largest_truncation():
+    """Every form, with the table and with generated P~ (whose seed rows at
+    this order include values below the double range)."""
     N, J, I, F, kind = 2047, 101, 4096, 2, "cc_poles"
     a = inputs.random_spectra(N, F, seed=3, profile="inv1")
-    g_ref = O.inverse(a, N, J, I, kind)
-    s_ref = O.forward(g_ref, N, kind)
-    for form in ("fp64", "fp32"):
+    g64 = O.inverse(a, N, J, I, kind)
+    refs = {torch.float64: (g64, O.forward(g64, N, kind))}
+    for form in ("fp64", "fp32", "bf16x6"):
         dt = torch.float64 if form == "fp64" else torch.float32
-        p = Plan(N, J, I, F, grid=kind, form=form)
         ad = torch.from_numpy(a).to("cuda:0", dt)
-        g = p.inverse(ad)
-        # the forward map is applied to the oracle's grid (rounded to the
-        # form's type), so that both directions are checked on their own
-        s = p.forward(torch.from_numpy(g_ref).to("cuda:0", dt))
-        if form == "fp64":
-            gi_ref, sf_ref = g_ref, s_ref
-        else:  # the oracle on the FP32-rounded inputs the GPU received
-            gi_ref = O.inverse(_host(ad), N, J, I, kind)
-            sf_ref = O.forward(_host(torch.from_numpy(g_ref).to(dt)), N, kind)
-        ei = [_rel(x, r) for x, r in zip(_host(g), gi_ref)]
-        ef = [_rel(x, r) for x, r in zip(_host(s), sf_ref)]
-        print("N=2047 I=4096 %s: inverse %s forward %s" % (form, ["%.2e" % e for e in ei], ["%.2e" % e for e in ef]))
-        assert max(ei) < TOL[form] and max(ef) < TOL[form]
-        p.close()
+        gd = torch.from_numpy(g64).to("cuda:0", dt)
+        if dt not in refs:  # the oracle on the FP32-rounded inputs the GPU receives
+            refs[dt] = (O.inverse(_host(ad), N, J, I, kind), O.forward(_host(gd), N, kind))
+        gi_ref, sf_ref = refs[dt]
+        out = {}
+        for otf in (False, True):
+            p = Plan(N, J, I, F, grid=kind, form=form, otf=otf)
+            # the forward map is applied to the oracle's grid, so that both
+            # directions are checked on their own
+            g, s = _host(p.inverse(ad)), _host(p.forward(gd))
+            p.close()
+            ei = [_rel(x, r) for x, r in zip(g, gi_ref)]
+            ef = [_rel(x, r) for x, r in zip(s, sf_ref)]
+            print("N=2047 I=4096 %s%s: inverse %s forward %s" % (form, " otf" if otf else "",
+                                                                ["%.2e" % e for e in ei], ["%.2e" % e for e in ef]))
+            assert max(ei) < TOL[form] and max(ef) < TOL[form]
+            out[otf] = (g, s)
+        # generated and stored P~ agree to a few roundings of the element type
+        close = 1e-13 if form == "fp64" else 1e-7
+        assert _rel(out[True][0], out[False][0]) < close and _rel(out[True][1], out[False][1]) < close
 
 
 @pytest.mark.parametrize("zonal", ["one_launch", "per_length"])
