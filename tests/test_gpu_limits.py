@@ -79,3 +79,27 @@ def test_eight_levels(form, zonal):
         sk = sh[so:so + F * (N + 1) * (N + 2)].reshape(F, -1, 2)
         assert _rel(sk, O.forward(gk, N, "cc_poles")) < TOL[form], ("forward", levels[k])
     p.close()
+
+
+def test_workspace_beyond_4_gib():
+    """T959 with 600 fields: the workspace (8.8 GB) is past the 32-bit
+    offsets of the fixed-length zonal kernels, so the zonal stage falls back
+    to the runtime-radix kernels (I = 2880 there); the first, a middle and
+    the last field of both directions against the oracle."""
+    N, J, I, F, kind = 959, 1919, 2880, 600, "cc_poles"
+    p = Plan(N, J, I, F, grid=kind, form="fp32")
+    assert p.workspace_bytes > 2 ** 32
+    gen = torch.Generator(device="cuda:0")
+    gen.manual_seed(11)
+    a = torch.randn(p.spec_shape, generator=gen, device="cuda:0", dtype=torch.float32)
+    g = p.inverse(a)
+    s = p.forward(g)
+    sel = [0, 299, F - 1]
+    ah, gh, sh = _host(a[sel]), _host(g[sel]), _host(s[sel])
+    del a, g, s
+    p.close()
+    torch.cuda.empty_cache()
+    ei = [_rel(x, r) for x, r in zip(gh, O.inverse(ah, N, J, I, kind))]
+    ef = [_rel(x, r) for x, r in zip(sh, O.forward(gh, N, kind))]
+    print("T959 600 fields: inverse %s forward %s" % (["%.2e" % e for e in ei], ["%.2e" % e for e in ef]))
+    assert max(ei) < 1e-6 and max(ef) < 1e-6
