@@ -1370,10 +1370,8 @@ static hipError_t launch_generic(bool analysis, const FftArgs& a, int maxN, hipS
   return launch_cfg<T, 512, FB, FC, 4, 4096>(analysis, a, maxI, st);
 }
 
-// Multi-level plans whose levels all have I = 1600, 800 or 400 (three-pass
-// plans) or I <= 1024 (runtime radices), and at least two launches' worth of
-// lengths: one launch of k_zonal_levels.  Returns false (nothing launched)
-// for other plans.
+// The configurations of the one-launch kernel for one element type (zk =
+// index into C1600, C800, C400, CRt) and its two instantiations.
 template <typename T>
 struct ZLevels {
   static constexpr bool dbl = sizeof(T) == 8;
@@ -1388,6 +1386,10 @@ struct ZLevels {
   }
 };
 
+// Multi-level plans whose levels all have I = 1600, 800 or 400 (three-pass
+// plans) or I <= 1024 (runtime radices), and at least two launches' worth of
+// lengths: one launch of k_zonal_levels.  Returns false (nothing launched)
+// for other plans.
 template <typename T, int FB>
 static bool launch_levels_one(bool analysis, const FftArgs& a, hipStream_t st, hipError_t* err) {
   constexpr int NT = ZLevels<T>::NT;
