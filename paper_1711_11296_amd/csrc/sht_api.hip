@@ -239,7 +239,7 @@ int build_plan(int nlev, const int* Nv, const int* Jv, const int* Iv, const int*
     // workspace offsets are 32-bit
     const long long Cp = roundup(2LL * Fv[0], std::lcm(BN, 2 * FB));
     const long long Kp = roundup((Jv[0] + 1) / 2, SHT_K_PAD);
-    if ((double)(Nv[0] + 1) * 2.0 * Kp * Cp * P->elem >= 4294967296.0) FB = 8;
+    if (!zonal_offsets_fit(Kp, Cp, (long long)P->elem)) FB = 8;
   }
   P->fb = FB;
 

@@ -430,23 +430,26 @@ __device__ __forceinline__ void quad_transpose(int (&x)[4][4]) {
 // Store the runs v of the quad's four wavenumbers m - j .. m - j + 3
 // (j = lane in quad) at dst(m') = base + (2 m') * plane; runs with m' > N
 // are skipped.  All lanes of the quad must call it.  base is uniform and the
-// level's workspace is below 4 GiB: the per-lane part of each address is a
-// 32-bit byte offset.  A run of 2 FB values is 64 or 128 bytes; a 128-byte
-// run goes as two 64-byte halves.
+// 64 lanes of a wave hold consecutive wavenumbers: each address is a
+// uniform 64-bit base at the wave's first wavenumber plus a 32-bit per-lane
+// byte offset of fewer than 128 planes (zonal_offsets_fit).  A run of 2 FB
+// values is 64 or 128 bytes; a 128-byte run goes as two 64-byte halves.
 template <typename T, int FB>
 __device__ __forceinline__ void store_runs_quad(T* base, long long plane, int m, int N,
                                                 const cx<T> (&v)[FB]) {
   constexpr int HALVES = 2 * FB * (int)sizeof(T) / 64;
   static_assert(HALVES * 64 == 2 * FB * (int)sizeof(T) && HALVES <= 2, "64- or 128-byte runs");
-  const int j = threadIdx.x & 3;
-  char* b = reinterpret_cast<char*>(base);
-  const unsigned step = (unsigned)(2 * plane * (long long)sizeof(T));
+  const int lane = threadIdx.x & 63, j = lane & 3;
+  const long long step64 = 2 * plane * (long long)sizeof(T);
+  const int mw = __builtin_amdgcn_readfirstlane(m - lane);  // the wave's first wavenumber
+  char* b = reinterpret_cast<char*>(base) + (long long)mw * step64;
+  const unsigned step = (unsigned)step64;
 #pragma unroll
   for (int hf = 0; hf < HALVES; ++hf) {
     int x[4][4];
     __builtin_memcpy(x, reinterpret_cast<const char*>(v) + 64 * hf, 64);
     quad_transpose(x);
-    unsigned off = (unsigned)(m - j) * step + 16u * (unsigned)j + 64u * (unsigned)hf;
+    unsigned off = (unsigned)(lane - j) * step + 16u * (unsigned)j + 64u * (unsigned)hf;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int mr = m - j + r;
@@ -1285,8 +1288,9 @@ template <typename T, int FB>
 static bool launch_fixed(bool analysis, const FftArgs& a, int maxN, hipStream_t st, hipError_t* err) {
   if (a.nlev != 1) return false;
   // the fixed-length kernels address the workspace with 32-bit offsets
+  // from a per-wave base
   const LevelDesc& L = a.lev[0];
-  if ((double)(L.N + 1) * 2.0 * L.Kp * L.Cp * sizeof(T) >= 4294967296.0) return false;
+  if (!zonal_offsets_fit(L.Kp, L.Cp, sizeof(T))) return false;
   constexpr bool dbl = sizeof(T) == 8;
   switch (a.lev[0].I) {
     case 2880:
@@ -1407,7 +1411,8 @@ static bool launch_levels_one(bool analysis, const FftArgs& a, hipStream_t st, h
     size_t need = 0;
     if (L.I == 1600 || L.I == 800 || L.I == 400) {
       // the three-pass kernels address the workspace with 32-bit offsets
-      if ((double)(L.N + 1) * 2.0 * L.Kp * L.Cp * sizeof(T) >= 4294967296.0) return false;
+      // from a per-wave base
+      if (!zonal_offsets_fit(L.Kp, L.Cp, sizeof(T))) return false;
       k = L.I == 1600 ? 0 : L.I == 800 ? 1 : 2;
       need = k == 0 ? C1600::template lds<T>() : k == 1 ? C800::template lds<T>() : C400::template lds<T>();
     } else {

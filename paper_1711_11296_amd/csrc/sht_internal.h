@@ -105,6 +105,12 @@ struct GemmArgs {
 // The level's workspace size with that blocking must be below 4 GiB (the
 // planner checks and falls back to 8).
 int zonal_fields_per_block(int form, int nlev, int N, int J, int I, int F);
+// The fixed-length zonal kernels store the workspace with 32-bit byte
+// offsets from a per-wave base: 64 wavenumbers x 2 planes of Kp x Cp
+// elements must stay below 4 GiB (else the runtime-radix kernels run).
+inline bool zonal_offsets_fit(long long Kp, long long Cp, long long elem) {
+  return 128.0 * (double)Kp * (double)Cp * (double)elem < 4294967296.0;
+}
 // 1 if the one-launch multi-level zonal kernel of this form and direction
 // keeps values in scratch memory (register spills), else 0
 int zonal_one_launch_spills(int form, bool analysis);

@@ -82,10 +82,9 @@ def test_eight_levels(form, zonal):
 
 
 def test_workspace_beyond_4_gib():
-    """T959 with 600 fields: the workspace (8.8 GB) is past the 32-bit
-    offsets of the fixed-length zonal kernels, so the zonal stage falls back
-    to the runtime-radix kernels (I = 2880 there); the first, a middle and
-    the last field of both directions against the oracle."""
+    """T959 with 600 fields: the workspace (8.8 GB) is past 4 GiB, which the
+    fixed-length zonal kernels address from a per-wave base; the first, a
+    middle and the last field of both directions against the oracle."""
     N, J, I, F, kind = 959, 1919, 2880, 600, "cc_poles"
     p = Plan(N, J, I, F, grid=kind, form="fp32")
     assert p.workspace_bytes > 2 ** 32
