@@ -513,7 +513,7 @@ FftArgs fft_args(const sht_plan_s* P, const void* src, void* dst, int use_w, int
   a.use_inv_I = use_inv_I;
   a.mscale = mscale;
   a.fb = P->fb;
-  a.jstart = P->d_jst;
+  a.jstart = P->reduced ? P->d_jst : nullptr;  // null: no latitude left out
   return a;
 }
 

@@ -659,7 +659,7 @@ __device__ __forceinline__ int zonal_synthesis_run(const FftArgs& a, int item, i
       const int m = threadIdx.x + s * NT;
       // rows below the first 128-latitude tile the Legendre synthesis
       // computes for this m (reduced transform) are zero
-      if (m <= L.N && it.jp >= (a.jstart[L.m_base + m] & ~127)) {
+      if (m <= L.N && (!a.jstart || it.jp >= (a.jstart[L.m_base + m] & ~127))) {
         const T* sS = ws + (2LL * m) * plane + (long long)it.jp * Cp + 2 * it.fb * FB;
         load_run<T, FB>(sS, stS[s]);
         load_run<T, FB>(sS + plane, stA[s]);
@@ -1040,13 +1040,19 @@ __device__ __forceinline__ int zonal_synthesis_run_p3(const FftArgs& a, int l, i
   auto load_ws = [&](int slot) __attribute__((always_inline)) {
     const int itm = xcd_map(slot - s0, n);
     const int jp = itm / L.nfb, fb = itm - jp * L.nfb;
+    // the runs of the wave's 64 consecutive wavenumbers: a uniform base at
+    // its first wavenumber plus 32-bit lane offsets (zonal_offsets_fit)
+    const int lane = threadIdx.x & 63;
+    const unsigned lstep = (unsigned)(2 * plane * (long long)sizeof(T));
 #pragma unroll
     for (int s = 0; s < MS; ++s) {
       const int m = threadIdx.x + s * NT;
       // rows below the first 128-latitude tile the Legendre synthesis
       // computes for this m (reduced transform) are zero
-      if (m <= N && jp >= (a.jstart[L.m_base + m] & ~127)) {
-        const T* sS = ws + (2LL * m) * plane + (long long)jp * Cp + 2 * fb * FB;
+      if (m <= N && (!a.jstart || jp >= (a.jstart[L.m_base + m] & ~127))) {
+        const int mw = __builtin_amdgcn_readfirstlane(m - lane);
+        const char* wb = reinterpret_cast<const char*>(ws + (2LL * mw) * plane + (long long)jp * Cp + 2 * fb * FB);
+        const T* sS = reinterpret_cast<const T*>(wb + (unsigned)lane * lstep);
         load_run<T, FB>(sS, stS[s]);
         load_run<T, FB>(sS + plane, stA[s]);
       } else {

@@ -66,8 +66,8 @@ struct FftArgs {
   int fb;            // fields per work item (zonal_fields_per_block)
   int one_launch;    // multi-level plans: one launch over all levels where they allow it
   // per (level, m): first latitude of the Legendre sums (reduced transform;
-  // else 0); the synthesis leaves whole 128-latitude tiles below it out of
-  // the workspace, and the zonal synthesis reads them as zero
+  // null otherwise); the synthesis leaves whole 128-latitude tiles below it
+  // out of the workspace, and the zonal synthesis reads them as zero
   const int* jstart;
 };
 
