@@ -42,6 +42,9 @@ def helmholtz_residual(plan, x, kappa, f, alpha, scale=1.0):
     if not isinstance(kappa, (list, tuple)) or len(kappa) != len(levels):
         raise ValueError("kappa: one [J, I] grid per level (%d)" % len(levels))
     scales = _per_level(scale, len(levels), "scale")
+    for k, (N, J, I, F) in enumerate(levels):
+        if tuple(kappa[k].shape) != (J, I):
+            raise ValueError("kappa[%d] must be [%d, %d]" % (k, J, I))
     xf, ff = x.contiguous().reshape(-1), f.contiguous().reshape(-1)
     if xf.numel() != plan.grid_elems or ff.numel() != plan.grid_elems:
         raise ValueError("x and f must hold the plan's %d grid values" % plan.grid_elems)
@@ -54,8 +57,6 @@ def helmholtz_residual(plan, x, kappa, f, alpha, scale=1.0):
     r = torch.empty_like(xf)
     for k, (N, J, I, F) in enumerate(levels):
         o, n = plan.grid_offsets[k], F * J * I
-        if tuple(kappa[k].shape) != (J, I):
-            raise ValueError("kappa[%d] must be [%d, %d]" % (k, J, I))
         grid_residual(xf[o:o + n].view(F, J, I), kappa[k], y[o:o + n].view(F, J, I), ff[o:o + n].view(F, J, I),
                       alpha, out=r[o:o + n].view(F, J, I))
     return r.view(x.shape)
@@ -77,10 +78,11 @@ def restrict_to_coarse_spectra(r_fine, coarse_plan, kind):
     import torch
     if not isinstance(r_fine, (list, tuple)) or len(r_fine) != len(levels):
         raise ValueError("r_fine: one fine grid per coarse level (%d)" % len(levels))
-    g = torch.empty(coarse_plan.grid_elems, dtype=r_fine[0].dtype, device=r_fine[0].device)
     for k, (N, J, I, F) in enumerate(levels):
         if r_fine[k].dim() != 3 or r_fine[k].shape[0] != F:
             raise ValueError("r_fine[%d] must be [%d, J_fine, I_fine]" % (k, F))
+    g = torch.empty(coarse_plan.grid_elems, dtype=r_fine[0].dtype, device=r_fine[0].device)
+    for k, (N, J, I, F) in enumerate(levels):
         o = coarse_plan.grid_offsets[k]
         grid_inject(r_fine[k], J, I, kind, out=g[o:o + F * J * I].view(F, J, I))
     return coarse_plan.forward(g)
