@@ -239,7 +239,7 @@ int build_plan(int nlev, const int* Nv, const int* Jv, const int* Iv, const int*
     // workspace offsets are 32-bit
     const long long Cp = roundup(2LL * Fv[0], std::lcm(BN, 2 * FB));
     const long long Kp = roundup((Jv[0] + 1) / 2, SHT_K_PAD);
-    if (!zonal_offsets_fit(Kp, Cp, (long long)P->elem)) FB = 8;
+    if (!zonal_offsets_fit(ws_plane(Kp, Cp), (long long)P->elem)) FB = 8;
   }
   P->fb = FB;
 
@@ -692,8 +692,9 @@ int run_forward_noalloc(sht_plan_s* P, const void* grid, void* spec, void* strea
   for (int l = 0; l < P->nlev; ++l) {
     const LevelDesc& L = P->lev[l];
     const long long row16 = (long long)L.Cp * (long long)P->elem / 16;  // Cp is a multiple of 16
+    const long long plane16 = L.wplane * (long long)P->elem / 16;        // so is the plane stride
     const int e = launch_clear_span(static_cast<unsigned char*>(ws) + L.ws_off * (long long)P->elem,
-                                    2LL * (L.N + 1), row16 * L.Kp, row16 * L.Jh, row16 * (L.Kp - L.Jh), stream);
+                                    2LL * (L.N + 1), plane16, row16 * L.Jh, row16 * (L.Kp - L.Jh), stream);
     if (e) return hip_check((hipError_t)e, "workspace clear launch");
   }
   const int saved_profile = P->profile;  // profiling would create events

@@ -613,7 +613,7 @@ __device__ __forceinline__ int zonal_analysis_run(const FftArgs& a, int item, in
 
     T* ws = ws0 + L.ws_off;
     const long long Cp = L.Cp;
-    const long long plane = (long long)L.Kp * Cp;
+    const long long plane = L.wplane;
 #pragma unroll
     for (int s = 0; s < MS; ++s) {
       const int m = threadIdx.x + s * NT;
@@ -653,7 +653,7 @@ __device__ __forceinline__ int zonal_synthesis_run(const FftArgs& a, int item, i
     const LevelDesc& L = a.lev[it.l];
     const T* ws = ws0 + L.ws_off;
     const long long Cp = L.Cp;
-    const long long plane = (long long)L.Kp * Cp;
+    const long long plane = L.wplane;
 #pragma unroll
     for (int s = 0; s < MS; ++s) {
       const int m = threadIdx.x + s * NT;
@@ -1003,7 +1003,7 @@ __device__ __forceinline__ int zonal_analysis_run_p3(const FftArgs& a, int l, in
     }
 
     const long long Cp = L.Cp;
-    const long long plane = (long long)L.Kp * Cp;
+    const long long plane = L.wplane;
     T* wrow = ws + (long long)jp * Cp + 2 * fb * FB;
 #pragma unroll
     for (int s = 0; s < MS; ++s) {
@@ -1034,7 +1034,7 @@ __device__ __forceinline__ int zonal_synthesis_run_p3(const FftArgs& a, int l, i
   const T msc = (T)a.mscale;
   const int N = L.N, J = L.J;
   const long long Cp = L.Cp;
-  const long long plane = (long long)L.Kp * Cp;
+  const long long plane = L.wplane;
 
   cx<T> stS[MS][FB], stA[MS][FB];
   auto load_ws = [&](int slot) __attribute__((always_inline)) {
@@ -1296,7 +1296,7 @@ static bool launch_fixed(bool analysis, const FftArgs& a, int maxN, hipStream_t 
   // the fixed-length kernels address the workspace with 32-bit offsets
   // from a per-wave base
   const LevelDesc& L = a.lev[0];
-  if (!zonal_offsets_fit(L.Kp, L.Cp, sizeof(T))) return false;
+  if (!zonal_offsets_fit(L.wplane, sizeof(T))) return false;
   constexpr bool dbl = sizeof(T) == 8;
   switch (a.lev[0].I) {
     case 2880:
@@ -1418,7 +1418,7 @@ static bool launch_levels_one(bool analysis, const FftArgs& a, hipStream_t st, h
     if (L.I == 1600 || L.I == 800 || L.I == 400) {
       // the three-pass kernels address the workspace with 32-bit offsets
       // from a per-wave base
-      if (!zonal_offsets_fit(L.Kp, L.Cp, sizeof(T))) return false;
+      if (!zonal_offsets_fit(L.wplane, sizeof(T))) return false;
       k = L.I == 1600 ? 0 : L.I == 800 ? 1 : 2;
       need = k == 0 ? C1600::template lds<T>() : k == 1 ? C800::template lds<T>() : C400::template lds<T>();
     } else {

@@ -47,6 +47,7 @@ struct LevelDesc {
   long long grid_off;  // element offset of this level in the grid buffer
   long long spec_off;  // element offset of this level in the spec buffer
   long long ws_off;    // element offset in the workspace
+  long long wplane;    // workspace elements from one (m, parity) plane to the next (ws_plane)
   const void* tw;      // I twiddles exp(-2 pi i k / I), complex, data type
   const double* wrow;  // Jh quadrature weights of the northern rows
   const double* murow; // Kp nodes mu_j of the northern rows, zero past Jh (analysis with generated P~)
@@ -105,11 +106,17 @@ struct GemmArgs {
 // The level's workspace size with that blocking must be below 4 GiB (the
 // planner checks and falls back to 8).
 int zonal_fields_per_block(int form, int nlev, int N, int J, int I, int F);
+// Workspace elements from one (m, parity) plane [Kp][Cp] to the next: the
+// plane plus a pad, so that the planes of consecutive wavenumbers (one
+// wave's 64 lanes in the zonal kernels) do not start at the same offset
+// modulo the large powers of two that HBM channels are interleaved by.
+constexpr long long kWsPlanePad = 32;  // elements (a multiple of 16; chosen by measurement)
+inline long long ws_plane(long long Kp, long long Cp) { return Kp * Cp + kWsPlanePad; }
 // The fixed-length zonal kernels store the workspace with 32-bit byte
-// offsets from a per-wave base: 64 wavenumbers x 2 planes of Kp x Cp
-// elements must stay below 4 GiB (else the runtime-radix kernels run).
-inline bool zonal_offsets_fit(long long Kp, long long Cp, long long elem) {
-  return 128.0 * (double)Kp * (double)Cp * (double)elem < 4294967296.0;
+// offsets from a per-wave base: 64 wavenumbers x 2 planes must stay below
+// 4 GiB (else the runtime-radix kernels run).
+inline bool zonal_offsets_fit(long long wplane, long long elem) {
+  return 128.0 * (double)wplane * (double)elem < 4294967296.0;
 }
 // 1 if the one-launch multi-level zonal kernel of this form and direction
 // keeps values in scratch memory (register spills), else 0

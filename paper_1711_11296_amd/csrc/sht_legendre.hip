@@ -118,7 +118,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
   const int c0 = t.cb * BN;
   const int Kp = L.Kp;
   const long long Cp = L.Cp;
-  const long long plane = (long long)Kp * Cp;
+  const long long plane = L.wplane;
   const T* wsm = static_cast<const T*>(g.ws) + L.ws_off + (2LL * m) * plane + c0;
 
   const int tid = threadIdx.x;
@@ -631,7 +631,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
   }
 
   if (!active) return;
-  const long long plane = (long long)L.Kp * Cp;
+  const long long plane = L.wplane;
   T* ws = static_cast<T*>(g.ws) + L.ws_off + (2LL * m + p) * plane;
 #pragma unroll
   for (int jb = 0; jb < 2; ++jb)

@@ -180,7 +180,7 @@ __global__ __launch_bounds__(X6Analysis<NCB>::NT) __attribute__((amdgpu_waves_pe
   const int c0 = t.cb * BN;
   const int Kp = L.Kp;
   const long long Cp = L.Cp;
-  const long long plane = (long long)Kp * Cp;
+  const long long plane = L.wplane;
   const float* wsm = static_cast<const float*>(g.ws) + L.ws_off + (2LL * m) * plane + c0;
 
   const int tid = threadIdx.x;
@@ -678,7 +678,7 @@ __global__ __launch_bounds__(X6Synthesis<NCB>::NT) __attribute__((amdgpu_waves_p
   }
 
   if (!active) return;
-  const long long plane = (long long)L.Kp * Cp;
+  const long long plane = L.wplane;
   float* ws = static_cast<float*>(g.ws) + L.ws_off + (2LL * m + p) * plane;
 #pragma unroll
   for (int jb = 0; jb < 2; ++jb)

@@ -66,7 +66,8 @@ void layout_levels(int nlev, const int* Nv, const int* Jv, const int* Iv, const 
     L.spec_off = Y.spec;
     Y.spec += (long long)L.F * (L.N + 1) * (L.N + 2);
     L.ws_off = Y.ws;
-    Y.ws += roundup((long long)(L.N + 1) * 2 * L.Kp * L.Cp, 64);
+    L.wplane = ws_plane(L.Kp, L.Cp);
+    Y.ws += roundup((long long)(L.N + 1) * 2 * L.wplane, 64);
     for (int m = 0; m <= L.N; ++m) {
       Y.taboff.push_back(Y.tab);
       // analysis copy: rows padded to the row tile of 128
