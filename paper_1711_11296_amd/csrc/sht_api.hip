@@ -671,11 +671,11 @@ int scratch_ptr(int dev, void** out) {
 }
 
 // The analysis with the workspace in the static array.  The Legendre
-// analysis reads the padding rows ceil(J/2) <= j < Kp of every workspace
-// plane (their table entries are zero), and an earlier call, of this or
-// another plan, may have left any value there (NaN included): they are
-// cleared first by a fill kernel on the same stream.  No events, graphs or
-// allocations.
+// analysis reads the padding rows ceil(J/2) <= j < Kp of every wavenumber's
+// workspace region (their table entries are zero), and an earlier call, of
+// this or another plan, may have left any value there (NaN included): they
+// are cleared first by a fill kernel on the same stream.  No events, graphs
+// or allocations.
 int run_forward_noalloc(sht_plan_s* P, const void* grid, void* spec, void* stream) {
   if (P->ws_bytes > SHT_NOALLOC_WORKSPACE_BYTES)
     return fail(SHT_EINVAL, "the plan's workspace (" + std::to_string(P->ws_bytes) +
@@ -691,10 +691,12 @@ int run_forward_noalloc(sht_plan_s* P, const void* grid, void* spec, void* strea
   if ((rc = scratch_ptr(dev, &ws))) return rc;
   for (int l = 0; l < P->nlev; ++l) {
     const LevelDesc& L = P->lev[l];
-    const long long row16 = (long long)L.Cp * (long long)P->elem / 16;  // Cp is a multiple of 16
-    const long long plane16 = L.wplane * (long long)P->elem / 16;        // so is the plane stride
+    // an analysis row holds 2 Cp elements (both parities), Cp a multiple of
+    // 16; the regions are 2 wplane elements apart, wplane a multiple of 16
+    const long long row16 = 2LL * L.Cp * (long long)P->elem / 16;
+    const long long region16 = 2LL * L.wplane * (long long)P->elem / 16;
     const int e = launch_clear_span(static_cast<unsigned char*>(ws) + L.ws_off * (long long)P->elem,
-                                    2LL * (L.N + 1), plane16, row16 * L.Jh, row16 * (L.Kp - L.Jh), stream);
+                                    (long long)(L.N + 1), region16, row16 * L.Jh, row16 * (L.Kp - L.Jh), stream);
     if (e) return hip_check((hipError_t)e, "workspace clear launch");
   }
   const int saved_profile = P->profile;  // profiling would create events

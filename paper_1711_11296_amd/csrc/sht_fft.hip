@@ -21,10 +21,11 @@
 // fields).  The FB fields go through the LDS buffer one after the other and
 // the wavenumbers m <= N of all FB fields are kept in registers, so that each
 // workspace access is a contiguous run of 2*FB values (64 bytes) per (m,
-// parity, row) instead of one isolated complex value.
+// parity, row) instead of one isolated complex value; the analysis stores
+// both parities of a row as one run of 4*FB values (ws_col).
 //
-// Workspace layout (per level): ws[m][parity][j][c], j < Kp (rows >= ceil(J/2)
-// stay zero), c = 2*field + {re, im} < Cp.
+// Workspace layout (per level): see ws_col and ws_plane; the analysis and
+// the synthesis lay it out differently.
 
 #include <hip/hip_runtime.h>
 
@@ -355,6 +356,7 @@ struct Vec16<double> {
 
 template <typename T, int FB>
 __device__ __forceinline__ void store_run(T* dst, const cx<T> (&v)[FB]) {
+  static_assert(2 * FB <= 16, "one analysis workspace column block");
   typedef typename Vec16<T>::type V;
   constexpr int E = 16 / sizeof(T);  // scalars per vector
   V* d = reinterpret_cast<V*>(dst);
@@ -433,8 +435,9 @@ __device__ __forceinline__ void quad_transpose(int (&x)[4][4]) {
 // 64 lanes of a wave hold consecutive wavenumbers: each address is a
 // uniform 64-bit base at the wave's first wavenumber plus a 32-bit per-lane
 // byte offset of fewer than 128 planes (zonal_offsets_fit).  A run of 2 FB
-// values is 64 or 128 bytes; a 128-byte run goes as two 64-byte halves.
-template <typename T, int FB>
+// values is 64 or 128 bytes; a 128-byte run goes as two 64-byte halves, HS
+// bytes apart.
+template <typename T, int FB, int HS = 64>
 __device__ __forceinline__ void store_runs_quad(T* base, long long plane, int m, int N,
                                                 const cx<T> (&v)[FB]) {
   constexpr int HALVES = 2 * FB * (int)sizeof(T) / 64;
@@ -449,7 +452,7 @@ __device__ __forceinline__ void store_runs_quad(T* base, long long plane, int m,
     int x[4][4];
     __builtin_memcpy(x, reinterpret_cast<const char*>(v) + 64 * hf, 64);
     quad_transpose(x);
-    unsigned off = (unsigned)(lane - j) * step + 16u * (unsigned)j + 64u * (unsigned)hf;
+    unsigned off = (unsigned)(lane - j) * step + 16u * (unsigned)j + (unsigned)HS * (unsigned)hf;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int mr = m - j + r;
@@ -618,9 +621,10 @@ __device__ __forceinline__ int zonal_analysis_run(const FftArgs& a, int item, in
     for (int s = 0; s < MS; ++s) {
       const int m = threadIdx.x + s * NT;
       if (m <= N) {
-        T* dS = ws + (2LL * m) * plane + (long long)it.jp * Cp + 2 * it.fb * FB;
+        // the item's column block (ws_col): even run, then odd run
+        T* dS = ws + (2LL * m) * plane + (long long)it.jp * 2 * Cp + 4 * it.fb * FB;
         store_run<T, FB>(dS, stS[s]);
-        store_run<T, FB>(dS + plane, stA[s]);
+        store_run<T, FB>(dS + 2 * FB, stA[s]);
       }
     }
   }
@@ -662,7 +666,7 @@ __device__ __forceinline__ int zonal_synthesis_run(const FftArgs& a, int item, i
       if (m <= L.N && (!a.jstart || it.jp >= (a.jstart[L.m_base + m] & ~127))) {
         const T* sS = ws + (2LL * m) * plane + (long long)it.jp * Cp + 2 * it.fb * FB;
         load_run<T, FB>(sS, stS[s]);
-        load_run<T, FB>(sS + plane, stA[s]);
+        load_run<T, FB>(sS + L.spoff, stA[s]);
       } else {
 #pragma unroll
         for (int q = 0; q < FB; ++q) stS[s][q] = stA[s][q] = cx<T>{(T)0, (T)0};
@@ -1004,12 +1008,15 @@ __device__ __forceinline__ int zonal_analysis_run_p3(const FftArgs& a, int l, in
 
     const long long Cp = L.Cp;
     const long long plane = L.wplane;
-    T* wrow = ws + (long long)jp * Cp + 2 * fb * FB;
+    // the item's column blocks of W = min(2 FB, 16) columns (ws_col): the
+    // even run at the start of each, the odd one W elements later
+    constexpr int WB = 2 * FB < 16 ? 2 * FB : 16;
+    T* wrow = ws + (long long)jp * 2 * Cp + 4 * fb * FB;
 #pragma unroll
     for (int s = 0; s < MS; ++s) {
       const int m = threadIdx.x + s * NT;
-      store_runs_quad<T, FB>(wrow, plane, m, N, stS[s]);
-      store_runs_quad<T, FB>(wrow + plane, plane, m, N, stA[s]);
+      store_runs_quad<T, FB, 2 * WB * (int)sizeof(T)>(wrow, plane, m, N, stS[s]);
+      store_runs_quad<T, FB, 2 * WB * (int)sizeof(T)>(wrow + WB, plane, m, N, stA[s]);
     }
   }
   return item;
@@ -1054,7 +1061,7 @@ __device__ __forceinline__ int zonal_synthesis_run_p3(const FftArgs& a, int l, i
         const char* wb = reinterpret_cast<const char*>(ws + (2LL * mw) * plane + (long long)jp * Cp + 2 * fb * FB);
         const T* sS = reinterpret_cast<const T*>(wb + (unsigned)lane * lstep);
         load_run<T, FB>(sS, stS[s]);
-        load_run<T, FB>(sS + plane, stA[s]);
+        load_run<T, FB>(sS + L.spoff, stA[s]);
       } else {
 #pragma unroll
         for (int q = 0; q < FB; ++q) stS[s][q] = stA[s][q] = cx<T>{(T)0, (T)0};
@@ -1524,6 +1531,10 @@ int zonal_fields_per_block(int form, int nlev, int N, int J, int I, int F) {
 
 int launch_zonal(int form, bool analysis, const FftArgs& a, int maxN, void* stream) {
   hipStream_t st = static_cast<hipStream_t>(stream);
+  // the kernels' item width must match every level's analysis column block
+  const int fb = form == SHT_FORM_FP64 ? 4 : (a.fb == 16 ? 16 : 8);
+  for (int l = 0; l < a.nlev; ++l)
+    if ((1 << a.lev[l].wsh) != (2 * fb < 16 ? 2 * fb : 16)) return (int)hipErrorInvalidValue;
   if (form == SHT_FORM_FP64) return (int)launch_zonal_t<double, 4, 1>(analysis, a, maxN, st);
   if (a.fb == 16) {
     ensure_num_cu();

@@ -44,10 +44,12 @@ struct LevelDesc {
   int nfb;         // field blocks of the FFT kernels
   int m_base;      // index of (level, m=0) in the per-m offset arrays
   int zk;          // zonal stage, one-launch multi-level kernel: configuration of this level (set at launch)
+  int wsh;         // log2 of the analysis workspace column block W = min(2 FB, 16) (ws_col)
   long long grid_off;  // element offset of this level in the grid buffer
   long long spec_off;  // element offset of this level in the spec buffer
   long long ws_off;    // element offset in the workspace
-  long long wplane;    // workspace elements from one (m, parity) plane to the next (ws_plane)
+  long long wplane;    // half the workspace elements from one wavenumber's region to the next (ws_plane)
+  long long spoff;     // synthesis: offset of the odd-parity plane in a region (wplane, or Jh Cp when Kp > Jh)
   const void* tw;      // I twiddles exp(-2 pi i k / I), complex, data type
   const double* wrow;  // Jh quadrature weights of the northern rows
   const double* murow; // Kp nodes mu_j of the northern rows, zero past Jh (analysis with generated P~)
@@ -106,14 +108,33 @@ struct GemmArgs {
 // The level's workspace size with that blocking must be below 4 GiB (the
 // planner checks and falls back to 8).
 int zonal_fields_per_block(int form, int nlev, int N, int J, int I, int F);
-// Workspace elements from one (m, parity) plane [Kp][Cp] to the next: the
-// plane plus a pad, so that the planes of consecutive wavenumbers (one
-// wave's 64 lanes in the zonal kernels) do not start at the same offset
-// modulo the large powers of two that HBM channels are interleaved by.
+// Workspace layout (per level).  The region of wavenumber m starts
+// 2 wplane elements after that of m - 1 and holds Kp rows j of 2 Cp
+// elements (rows j >= ceil(J/2) stay zero), for the columns
+// c = 2 field + {re, im} < Cp of both parities p.  The two directions use
+// it differently (each writes and reads its own):
+// * synthesis (and forward adjoint): two planes, parity p at p spoff,
+//   row j < ceil(J/2) at j Cp, column c; spoff = wplane, or ceil(J/2) Cp
+//   when Kp > ceil(J/2), so that these planes never overlap the rows the
+//   analysis keeps zero;
+// * analysis (and inverse adjoint): row j at 2 j Cp holds both parities in
+//   blocks of W = 2^wsh = min(2 FB, 16) columns, [column block][parity][W]
+//   (ws_col): the columns of a zonal work item are one block (two for
+//   16-field items), so the item's stores for one m are one contiguous run
+//   of 4 FB elements (128 bytes for 8 FP32 fields), and each latitude row
+//   of a Legendre analysis tile is one run over both parities.
+// Offset of (parity, column c) within an analysis row:
+constexpr int ws_col(int wsh, int par, int c) {
+  return ((c >> wsh) << (wsh + 1)) + (par << wsh) + (c & ((1 << wsh) - 1));
+}
+// wplane is one parity's share of a region, Kp Cp elements, plus a pad, so
+// that the regions of consecutive wavenumbers (one wave's 64 lanes in the
+// zonal kernels) do not start at the same offset modulo the large powers of
+// two that HBM channels are interleaved by.
 constexpr long long kWsPlanePad = 32;  // elements (a multiple of 16; chosen by measurement)
 inline long long ws_plane(long long Kp, long long Cp) { return Kp * Cp + kWsPlanePad; }
-// The fixed-length zonal kernels store the workspace with 32-bit byte
-// offsets from a per-wave base: 64 wavenumbers x 2 planes must stay below
+// The fixed-length zonal kernels address the workspace with 32-bit byte
+// offsets from a per-wave base: 64 wavenumbers x 2 wplane must stay below
 // 4 GiB (else the runtime-radix kernels run).
 inline bool zonal_offsets_fit(long long wplane, long long elem) {
   return 128.0 * (double)wplane * (double)elem < 4294967296.0;

@@ -17,7 +17,9 @@
 // kernel streams it (analysis: rows r = n - m padded to 128 by Kp columns j;
 // synthesis: 128-latitude tiles by blocks of 32 natural rows; zero padding;
 // see the kernels below).  The split-bfloat16 kernels read the same FP32
-// copies.  Workspace layout: ws[m][parity][j][c] (see the zonal stage).
+// copies.  Workspace layouts: see ws_col and ws_plane (the analysis reads
+// rows of both parities interleaved in column blocks, the synthesis writes
+// one plane per parity).
 //
 // Work decomposition: a host-built list gives one tile per workgroup; it is
 // ordered so that the tiles of one m, which share the same right-hand
@@ -60,11 +62,13 @@ struct AnalysisShape {
   static constexpr int BN = 16 * NCB;
   // With an even number of column blocks the right-hand operand goes from
   // memory to LDS directly (global_load_lds, 64 x 16 bytes per instruction,
-  // contiguous in LDS), in rows of BN elements whose 16-column blocks are
-  // swapped in pairs on odd rows (column c sits at c ^ 16 when k is odd):
-  // the lane groups g = 0, 1 that one LDS cycle serves read rows of
-  // different parity and so hit different bank halves.  Otherwise it is
-  // staged through registers into rows padded to a pitch of 16 mod 32 words.
+  // contiguous in LDS), in rows 2 k + parity of BN elements (one
+  // instruction fills both parities of one or more latitudes, contiguous in
+  // the workspace) whose 16-column blocks are swapped in pairs for odd k
+  // (column c sits at c ^ 16): the lane groups g = 0, 1 that one LDS cycle
+  // serves read latitudes k of different parity and so hit different bank
+  // halves.  Otherwise it is staged through registers into rows
+  // parity KB + k padded to a pitch of 16 mod 32 words.
   static constexpr bool DMA = NCB % 2 == 0;
   static constexpr int BS = DMA ? BN : BN + (sizeof(T) == 4 ? 16 : 2);
   static constexpr int STAGE = 2 * KB * BS;            // elements of one stage
@@ -119,7 +123,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
   const int Kp = L.Kp;
   const long long Cp = L.Cp;
   const long long plane = L.wplane;
-  const T* wsm = static_cast<const T*>(g.ws) + L.ws_off + (2LL * m) * plane + c0;
+  const T* wsm = static_cast<const T*>(g.ws) + L.ws_off + (2LL * m) * plane;  // region m
 
   const int tid = threadIdx.x;
   // wave-uniform values live in scalar registers
@@ -193,7 +197,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
         const int par = qq / (KB * BN / E);
         const int rem = qq - par * (KB * BN / E);
         const int row = rem / (BN / E), cv = rem % (BN / E);
-        rb[i] = *reinterpret_cast<const V*>(wsm + par * plane + (long long)(kb * KB + row) * Cp + cv * E);
+        rb[i] = *reinterpret_cast<const V*>(wsm + (long long)(kb * KB + row) * 2 * Cp +
+                                            ws_col(L.wsh, par, c0 + cv * E));
       }
     }
   };
@@ -213,20 +218,26 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
   };
   // memory -> LDS without registers: instruction i of wave w fills the
   // 1 KiB chunk number i*8 + w of the stage; lane l takes its 16-byte piece
-  // (row, physical column) and fetches the logical column under the swizzle
+  // (row 2 k + parity, physical column) and fetches the logical column under
+  // the swizzle.  The lane's byte offsets within a K block are fixed for the
+  // tile (32-bit, from the block's uniform base).
+  unsigned dofs[S::DMA ? S::NB : 1];
+  if constexpr (S::DMA) {
+    static_assert(S::BV % 512 == 0, "whole chunks per wave");
+#pragma unroll
+    for (int i = 0; i < S::NB; ++i) {
+      const int u = (i * 8 + w) * 64 + lane;
+      const int rr = u / (BN / E), col = (u - rr * (BN / E)) * E;
+      const int k = rr >> 1, par = rr & 1;
+      dofs[i] = (unsigned)(k * 2 * (int)Cp + ws_col(L.wsh, par, c0 + (col ^ ((k & 1) << 4)))) * (unsigned)sizeof(T);
+    }
+  }
   auto dma = [&](int kb, int stage) {
     if constexpr (S::DMA) {
-      static_assert(S::BV % 512 == 0, "whole chunks per wave");
       T* dst = Bs + stage * S::STAGE;
+      const char* src = reinterpret_cast<const char*>(wsm + (long long)kb * KB * 2 * Cp);
 #pragma unroll
-      for (int i = 0; i < S::NB; ++i) {
-        const int chunk = i * 8 + w;
-        const int L = chunk * 64 + lane;
-        const int rr = L / (BN / E), col = (L - rr * (BN / E)) * E;
-        const int par = rr / KB, k = rr - par * KB;
-        const T* src = wsm + par * plane + (long long)(kb * KB + k) * Cp + (col ^ ((k & 1) << 4));
-        load_to_lds16(src, dst + chunk * 64 * E);
-      }
+      for (int i = 0; i < S::NB; ++i) load_to_lds16(src + dofs[i], dst + (i * 8 + w) * 64 * E);
     }
   };
   // Wait for this wave's LDS fills: they were issued before the two table
@@ -252,14 +263,16 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
 #pragma unroll
         for (int e = 0; e < E; ++e) a[v * E + e] = ac[v][e];
     }
-    const T* Bp = Bs + stage * S::STAGE + (p * KB + lg) * BS + li;
-    // swizzled column-block offsets (rows g + 4 kk have the parity of g)
+    // LDS row of (parity p, latitude k): 2 k + p (DMA) or p KB + k
+    constexpr int RK = S::DMA ? 2 : 1, RP = S::DMA ? 1 : KB;
+    const T* Bp = Bs + stage * S::STAGE + (p * RP + lg * RK) * BS + li;
+    // swizzled column-block offsets (latitudes g + 4 kk have the parity of g)
     const int sw = (S::DMA && (lg & 1)) ? 16 : 0;
 #pragma unroll
     for (int kk = 0; kk < KQ; ++kk) {
       T bv[NCB];
 #pragma unroll
-      for (int c = 0; c < NCB; ++c) bv[c] = Bp[4 * kk * BS + c * 16 + ((c & 1) ? -sw : sw)];
+      for (int c = 0; c < NCB; ++c) bv[c] = Bp[4 * kk * RK * BS + c * 16 + ((c & 1) ? -sw : sw)];
 #pragma unroll
       for (int c = 0; c < NCB; ++c) acc[c] = mfma16(a[kk], bv[c], acc[c]);
     }
@@ -632,7 +645,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
 
   if (!active) return;
   const long long plane = L.wplane;
-  T* ws = static_cast<T*>(g.ws) + L.ws_off + (2LL * m + p) * plane;
+  T* ws = static_cast<T*>(g.ws) + L.ws_off + (2LL * m) * plane + p * L.spoff;
 #pragma unroll
   for (int jb = 0; jb < 2; ++jb)
 #pragma unroll

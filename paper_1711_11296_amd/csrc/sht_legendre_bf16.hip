@@ -181,7 +181,7 @@ __global__ __launch_bounds__(X6Analysis<NCB>::NT) __attribute__((amdgpu_waves_pe
   const int Kp = L.Kp;
   const long long Cp = L.Cp;
   const long long plane = L.wplane;
-  const float* wsm = static_cast<const float*>(g.ws) + L.ws_off + (2LL * m) * plane + c0;
+  const float* wsm = static_cast<const float*>(g.ws) + L.ws_off + (2LL * m) * plane;  // region m
 
   const int tid = threadIdx.x;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
@@ -232,7 +232,7 @@ __global__ __launch_bounds__(X6Analysis<NCB>::NT) __attribute__((amdgpu_waves_pe
     const bool valid = TR * 512 == S::TASKS || u < S::TASKS;
     const int uc = valid ? u : S::TASKS - 1;  // loads clamped to a real task
     const int eh = uc & 1, gg = (uc >> 1) & 3, cq = (uc >> 3) % (BN / 4), par = (uc >> 3) / (BN / 4);
-    bsrc[i] = wsm + par * plane + (long long)(16 * eh + gg) * Cp + 4 * cq;
+    bsrc[i] = wsm + (long long)(16 * eh + gg) * 2 * Cp + ws_col(L.wsh, par, c0 + 4 * cq);
     boff[i] = valid ? (par * BN + 4 * cq) * P + 8 * gg + 4 * eh : 32;
   }
 
@@ -258,7 +258,7 @@ __global__ __launch_bounds__(X6Analysis<NCB>::NT) __attribute__((amdgpu_waves_pe
     for (int i = 0; i < TR; ++i)
 #pragma unroll
       for (int e = 0; e < 4; ++e)
-        braw[set][i][e] = *reinterpret_cast<const f4*>(bsrc[i] + (long long)(kb * KB + 4 * e) * Cp);
+        braw[set][i][e] = *reinterpret_cast<const f4*>(bsrc[i] + (long long)(kb * KB + 4 * e) * 2 * Cp);
   };
   auto split_a = [&](int set) __attribute__((always_inline)) {
 #pragma unroll
@@ -679,7 +679,7 @@ __global__ __launch_bounds__(X6Synthesis<NCB>::NT) __attribute__((amdgpu_waves_p
 
   if (!active) return;
   const long long plane = L.wplane;
-  float* ws = static_cast<float*>(g.ws) + L.ws_off + (2LL * m + p) * plane;
+  float* ws = static_cast<float*>(g.ws) + L.ws_off + (2LL * m) * plane + p * L.spoff;
 #pragma unroll
   for (int jb = 0; jb < 2; ++jb)
 #pragma unroll

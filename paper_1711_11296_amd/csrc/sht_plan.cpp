@@ -57,6 +57,7 @@ void layout_levels(int nlev, const int* Nv, const int* Jv, const int* Iv, const 
       L.pmag[q] = ns > 1 ? 0xFFFFFFFFu / (unsigned)ns + 1u : 0u;
     }
     L.nfb = (L.F + FB - 1) / FB;
+    while ((1 << L.wsh) < 2 * FB && L.wsh < 4) ++L.wsh;  // W = min(2 FB, 16), a power of two
     L.fft_item0 = (int)Y.items;
     Y.items += (long long)L.Jh * L.nfb;
     L.m_base = (int)moff;
@@ -67,6 +68,7 @@ void layout_levels(int nlev, const int* Nv, const int* Jv, const int* Iv, const 
     Y.spec += (long long)L.F * (L.N + 1) * (L.N + 2);
     L.ws_off = Y.ws;
     L.wplane = ws_plane(L.Kp, L.Cp);
+    L.spoff = L.Kp == L.Jh ? L.wplane : (long long)L.Jh * L.Cp;
     Y.ws += roundup((long long)(L.N + 1) * 2 * L.wplane, 64);
     for (int m = 0; m <= L.N; ++m) {
       Y.taboff.push_back(Y.tab);
@@ -80,7 +82,7 @@ void layout_levels(int nlev, const int* Nv, const int* Jv, const int* Iv, const 
       Y.recoff.push_back(Y.rec);
       Y.rec += 2LL * (L.N - m + 1);
     }
-    SHT_ASSERT(L.Cp % BN == 0 && L.Cp % (2 * FB) == 0 && L.Cp >= 2 * L.F);
+    SHT_ASSERT(L.Cp % BN == 0 && L.Cp % (2 * FB) == 0 && L.Cp >= 2 * L.F && (1 << L.wsh) == std::min(2 * FB, 16));
     SHT_ASSERT(L.Kp % SHT_K_PAD == 0 && L.Kp >= L.Jh);
   }
   // one sentinel past the last (level, m): block m of a level spans
