@@ -192,6 +192,25 @@ def test_nan_isolation_between_fields():
     p.close()
 
 
+@pytest.mark.parametrize("form", FORMS)
+def test_synthesis_nan_does_not_reach_a_later_analysis(form):
+    # ceil(J/2) = 21 latitude rows, padded to 32.  Synthesis and analysis
+    # share the plan's workspace in different layouts; what a synthesis
+    # leaves there (NaN here) must not reach the padding rows the analysis
+    # reads (their P~ entries are zero, and 0 * NaN is NaN).
+    N, J, I, F = 20, 41, 48, 3
+    p = _plan(N, J, I, F, "fejer2", form)
+    a = inputs.random_spectra(N, F, seed=11)
+    a[1, 5] = np.nan  # m = 0, n = 5: the odd-parity plane of m = 0
+    gn = _host(p.inverse(_to_dev(a, form)))
+    assert np.isnan(gn[1]).any() and np.isfinite(gn[[0, 2]]).all()
+    g_d = _to_dev(inputs.random_grid(F, J, I, seed=12), form)
+    s = _host(p.forward(g_d))
+    assert np.isfinite(s).all()
+    assert rel(s, O.forward(_host(g_d), N, "fejer2")) < TOL[form]
+    p.close()
+
+
 def test_error_paths_on_device():
     from paper_1711_11296_amd import Plan, SHTError
     p = Plan(10, 21, 24, 2, form="fp64")
