@@ -435,9 +435,8 @@ __device__ __forceinline__ void quad_transpose(int (&x)[4][4]) {
 // 64 lanes of a wave hold consecutive wavenumbers: each address is a
 // uniform 64-bit base at the wave's first wavenumber plus a 32-bit per-lane
 // byte offset of fewer than 128 planes (zonal_offsets_fit).  A run of 2 FB
-// values is 64 or 128 bytes; a 128-byte run goes as two 64-byte halves, HS
-// bytes apart.
-template <typename T, int FB, int HS = 64>
+// values is 64 or 128 bytes; a 128-byte run goes as two 64-byte halves.
+template <typename T, int FB>
 __device__ __forceinline__ void store_runs_quad(T* base, long long plane, int m, int N,
                                                 const cx<T> (&v)[FB]) {
   constexpr int HALVES = 2 * FB * (int)sizeof(T) / 64;
@@ -452,7 +451,7 @@ __device__ __forceinline__ void store_runs_quad(T* base, long long plane, int m,
     int x[4][4];
     __builtin_memcpy(x, reinterpret_cast<const char*>(v) + 64 * hf, 64);
     quad_transpose(x);
-    unsigned off = (unsigned)(lane - j) * step + 16u * (unsigned)j + (unsigned)HS * (unsigned)hf;
+    unsigned off = (unsigned)(lane - j) * step + 16u * (unsigned)j + 64u * (unsigned)hf;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int mr = m - j + r;
@@ -1009,14 +1008,29 @@ __device__ __forceinline__ int zonal_analysis_run_p3(const FftArgs& a, int l, in
     const long long Cp = L.Cp;
     const long long plane = L.wplane;
     // the item's column blocks of W = min(2 FB, 16) columns (ws_col): the
-    // even run at the start of each, the odd one W elements later
+    // even run at the start of each, the odd one W elements later; a
+    // 16-field item's two blocks are written in address order (even and odd
+    // piece of the first block, then of the second), one 128-byte line after
+    // the other
     constexpr int WB = 2 * FB < 16 ? 2 * FB : 16;
     T* wrow = ws + (long long)jp * 2 * Cp + 4 * fb * FB;
 #pragma unroll
     for (int s = 0; s < MS; ++s) {
       const int m = threadIdx.x + s * NT;
-      store_runs_quad<T, FB, 2 * WB * (int)sizeof(T)>(wrow, plane, m, N, stS[s]);
-      store_runs_quad<T, FB, 2 * WB * (int)sizeof(T)>(wrow + WB, plane, m, N, stA[s]);
+      if constexpr (2 * FB == WB) {
+        store_runs_quad<T, FB>(wrow, plane, m, N, stS[s]);
+        store_runs_quad<T, FB>(wrow + WB, plane, m, N, stA[s]);
+      } else {
+        static_assert(2 * FB == 2 * WB, "one or two column blocks per item");
+        typedef const cx<T>(&Half)[FB / 2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          store_runs_quad<T, FB / 2>(wrow + 2 * WB * h, plane, m, N,
+                                     reinterpret_cast<Half>(stS[s][h * (FB / 2)]));
+          store_runs_quad<T, FB / 2>(wrow + 2 * WB * h + WB, plane, m, N,
+                                     reinterpret_cast<Half>(stA[s][h * (FB / 2)]));
+        }
+      }
     }
   }
   return item;
