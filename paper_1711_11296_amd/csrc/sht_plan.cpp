@@ -84,6 +84,10 @@ void layout_levels(int nlev, const int* Nv, const int* Jv, const int* Iv, const 
     }
     SHT_ASSERT(L.Cp % BN == 0 && L.Cp % (2 * FB) == 0 && L.Cp >= 2 * L.F && (1 << L.wsh) == std::min(2 * FB, 16));
     SHT_ASSERT(L.Kp % SHT_K_PAD == 0 && L.Kp >= L.Jh);
+    // the synthesis planes stay inside the region and off the rows the
+    // analysis keeps zero (rows Jh .. Kp of its layout, 2 Cp elements each)
+    SHT_ASSERT(L.spoff + (long long)L.Jh * L.Cp <= 2 * L.wplane &&
+               (L.Kp == L.Jh || L.spoff + (long long)L.Jh * L.Cp <= 2LL * L.Jh * L.Cp));
   }
   // one sentinel past the last (level, m): block m of a level spans
   // [off[m], off[m + 1])
